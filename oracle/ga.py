@@ -1,0 +1,197 @@
+"""Genetic operators of GAME -- oracle side, test infrastructure only.
+
+The paper lists the operators (Sec. 3: crossover, mutation, roulette/ranking
+selection, elitism; genes drawn at random in [-1, +1] and kept there) and the
+settings of its experiment (Sec. 5: crossover rate 0.9, 2 elite chromosomes per
+generation).  The operator variants used here are tournament selection,
+one-point crossover producing two complementary children and per-gene
+Gaussian mutation with clamping to [-1, 1].
+
+Every random decision is a pure function of a Philox4x32-10 block
+(``oracle.philox``) addressed by a counter (a, b, generation, tag) under the
+key = seed, so a device implementation that follows the same addressing
+reproduces each decision bit for bit.  Counter addressing:
+
+  init      gene (p, l):           (p, l, 0, INIT) word 0
+  selection pair j, parent s, draw i (i < k <= 16):
+                                    (j, 4*s + i // 4, g, SEL) word i % 4
+  crossover pair j:                 (j, 8, g, SEL) words 0 (decision), 1 (point)
+  mutation  child c, gene l:        (c, l, g, MUT) word 0 (decision); Gaussian
+            from (c,l,g,MUT) words 1..3, (c,l,g,MUT1) words 0..3,
+            (c,l,g,MUT2) words 0..3, (c,l,g,MUT3) word 0
+
+Arithmetic is exact integer arithmetic except the mutation update, which is
+done in IEEE float32 one operation at a time (numpy float32 scalars), exactly
+as a float32 device computes it without fused multiply-add.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .philox import philox4x32_10
+
+TAG_INIT = 1
+TAG_SEL = 2
+TAG_MUT = 3
+TAG_MUT1 = 4
+TAG_MUT2 = 5
+TAG_MUT3 = 6
+
+TWO32 = 1 << 32
+
+
+def prob_threshold(p: float) -> int:
+    """A decision with probability p fires iff a uniform u32 word < floor(p * 2^32)."""
+    if not (0.0 <= p <= 1.0):
+        raise ValueError("probability out of [0, 1]")
+    return int(math.floor(p * 4294967296.0))
+
+
+def index_draw(word: int, n: int) -> int:
+    """Uniform index in [0, n) from a u32 word: floor(word * n / 2^32)."""
+    return (int(word) * int(n)) >> 32
+
+
+def init_population(P: int, L: int, seed: int) -> np.ndarray:
+    """Genes U[-1, 1): (w >> 8) * 2^-23 - 1 from block (p, l, 0, INIT) word 0 (Sec. 3)."""
+    p = np.arange(P, dtype=np.uint64)[:, None]
+    l = np.arange(L, dtype=np.uint64)[None, :]
+    w0, _, _, _ = philox4x32_10(p, l, 0, TAG_INIT, seed)
+    u24 = (w0 >> np.uint32(8)).astype(np.float64)
+    return (u24 * 2.0 ** -23 - 1.0).astype(np.float32)  # exact in float32
+
+
+def _rank_key(f: float) -> float:
+    return -math.inf if math.isnan(f) else float(f)
+
+
+def better(fit, a: int, b: int) -> bool:
+    """a ranks above b: higher fitness, ties to the lower index, NaN worst."""
+    fa, fb = _rank_key(fit[a]), _rank_key(fit[b])
+    return fa > fb or (fa == fb and a < b)
+
+
+def rank_order(fit) -> list:
+    """All indices, best first (fitness descending, index ascending, NaN last)."""
+    return sorted(range(len(fit)), key=lambda i: (-_rank_key(fit[i]), i))
+
+
+def elites(fit, E: int) -> list:
+    return rank_order(fit)[:E]
+
+
+def tournament(fit, j: int, s: int, g: int, k: int, seed: int) -> int:
+    """Best of k indices drawn with replacement (Sec. 3 selection operator)."""
+    P = len(fit)
+    winner = None
+    for i in range(k):
+        blk = philox4x32_10(j, 4 * s + i // 4, g, TAG_SEL, seed)
+        cand = index_draw(int(blk[i % 4]), P)
+        if winner is None or better(fit, cand, winner):
+            winner = cand
+    return winner
+
+
+def gaussian_ih12(words) -> np.float32:
+    """Irwin-Hall sum of 12 bin-midpoint uniforms, centred: mean 0, variance 1 - 2^-48.
+
+    S = sum(2 * (w >> 8) + 1) - 12 * 2^24 as an integer, z = float32(S) * 2^-25.
+    """
+    words = [int(w) for w in words]
+    assert len(words) == 12
+    s = sum(2 * (w >> 8) + 1 for w in words) - 12 * (1 << 24)
+    return np.float32(s) * np.float32(2.0 ** -25)
+
+
+def mutate_gene(gene: np.float32, words12, sigma32: np.float32) -> np.float32:
+    """g' = clamp(fl(g + fl(sigma * z)), -1, 1), float32, no fused multiply-add."""
+    z = gaussian_ih12(words12)
+    delta = np.float32(sigma32 * z)
+    v = np.float32(np.float32(gene) + delta)
+    return np.float32(min(max(v, np.float32(-1.0)), np.float32(1.0)))
+
+
+def _mutation_words(c, l, g: int, seed: int):
+    """Decision word and the 12 Gaussian words for child c, gene l (arrays)."""
+    b0 = philox4x32_10(c, l, g, TAG_MUT, seed)
+    b1 = philox4x32_10(c, l, g, TAG_MUT1, seed)
+    b2 = philox4x32_10(c, l, g, TAG_MUT2, seed)
+    b3 = philox4x32_10(c, l, g, TAG_MUT3, seed)
+    gauss = [b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3],
+             b2[0], b2[1], b2[2], b2[3], b3[0]]
+    return b0[0], gauss
+
+
+def mutate(children: np.ndarray, g: int, seed: int, p_mutation: float,
+           sigma: float) -> np.ndarray:
+    """Per-gene Gaussian mutation of every child (row = child ordinal).
+
+    Same arithmetic as ``mutate_gene``, applied elementwise to float32 arrays
+    (numpy float32 array operations round each operation like the scalars).
+    """
+    children = np.array(children, dtype=np.float32, copy=True)
+    n, L = children.shape
+    if n == 0:
+        return children
+    thr_m = prob_threshold(p_mutation)
+    c = np.arange(n, dtype=np.uint64)[:, None]
+    l = np.arange(L, dtype=np.uint64)[None, :]
+    dec, _ = _mutation_words(c, l, g, seed)
+    hit = dec.astype(np.uint64) < np.uint64(thr_m)
+    ci, li = np.nonzero(hit)
+    if ci.size == 0:
+        return children
+    _, words = _mutation_words(ci.astype(np.uint64), li.astype(np.uint64), g, seed)
+    s = np.zeros(ci.size, dtype=np.int64)
+    for w in words:
+        s += 2 * (w.astype(np.int64) >> 8) + 1
+    s -= 12 * (1 << 24)
+    z = s.astype(np.float32) * np.float32(2.0 ** -25)
+    delta = np.float32(sigma) * z
+    v = children[ci, li] + delta
+    children[ci, li] = np.minimum(np.maximum(v, np.float32(-1.0)), np.float32(1.0))
+    return children
+
+
+def make_offspring(pop, fit, g: int, n_children: int, seed: int, k: int = 3,
+                   p_crossover: float = 0.9, p_mutation: float = 0.05,
+                   sigma: float = 0.1) -> np.ndarray:
+    """n_children children from tournament pairs, crossover, then mutation.
+
+    Pair j yields child ordinals 2j and 2j+1; an odd count drops the last one.
+    """
+    pop = np.asarray(pop, dtype=np.float32)
+    P, L = pop.shape
+    if not 1 <= k <= 16:
+        raise ValueError("tournament size must be in [1, 16]")
+    thr_c = prob_threshold(p_crossover)
+    out = np.empty((n_children, L), dtype=np.float32)
+    for j in range((n_children + 1) // 2):
+        a = tournament(fit, j, 0, g, k, seed)
+        b = tournament(fit, j, 1, g, k, seed)
+        blk = philox4x32_10(j, 8, g, TAG_SEL, seed)
+        ca, cb = pop[a].copy(), pop[b].copy()
+        if int(blk[0]) < thr_c and L >= 2:
+            cut = 1 + index_draw(int(blk[1]), L - 1)
+            ca = np.concatenate([pop[a][:cut], pop[b][cut:]])
+            cb = np.concatenate([pop[b][:cut], pop[a][cut:]])
+        out[2 * j] = ca
+        if 2 * j + 1 < n_children:
+            out[2 * j + 1] = cb
+    return mutate(out, g, seed, p_mutation, sigma)
+
+
+def ga_step(pop, fit, g: int, seed: int, elitism: int = 2, **kw) -> np.ndarray:
+    """Generation g -> g+1: the E elites (best first) then P - E children."""
+    pop = np.asarray(pop, dtype=np.float32)
+    P, L = pop.shape
+    if not 0 <= elitism <= P:
+        raise ValueError("elitism out of range")
+    new = np.empty_like(pop)
+    for e, idx in enumerate(elites(fit, elitism)):
+        new[e] = pop[idx]
+    if P > elitism:
+        new[elitism:] = make_offspring(pop, fit, g, P - elitism, seed, **kw)
+    return new

@@ -1,0 +1,164 @@
+"""Pins of the oracle's genetic operators: closed-form distributions, exact
+enumeration and invariants that any correct implementation must satisfy."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import ga, model
+import synth
+
+
+def test_probability_thresholds_and_index_draws():
+    assert ga.prob_threshold(0.0) == 0
+    assert ga.prob_threshold(1.0) == 2 ** 32
+    assert ga.prob_threshold(0.5) == 2 ** 31
+    assert ga.prob_threshold(0.9) == math.floor(0.9 * 2 ** 32)
+    assert ga.index_draw(0, 17) == 0 and ga.index_draw(2 ** 32 - 1, 17) == 16
+    # every index receives floor or ceil of 2^32 / n words
+    n = 7
+    edges = [-(-(i * 2 ** 32) // n) for i in range(n + 1)]
+    for i in range(n):
+        assert ga.index_draw(edges[i], n) == i and ga.index_draw(edges[i + 1] - 1, n) == i
+
+
+def test_init_population_grid_and_range():
+    pop = ga.init_population(64, 50, seed=123)
+    assert pop.dtype == np.float32 and pop.shape == (64, 50)
+    assert pop.min() >= -1.0 and pop.max() < 1.0
+    scaled = (pop.astype(np.float64) + 1.0) * 2 ** 23
+    np.testing.assert_array_equal(scaled, np.round(scaled))   # exact 2^-23 grid
+    assert abs(pop.mean()) < 0.02
+    assert stats.kstest(pop.ravel(), stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
+    assert not np.array_equal(pop, ga.init_population(64, 50, seed=124))
+
+
+def test_elites_match_library_sort_with_ties_and_nan():
+    fit = synth.random_fitness(200, seed=9, n_ties=40, n_nan=7)
+    key = np.where(np.isnan(fit), -np.inf, fit)
+    order = np.lexsort((np.arange(200), -key))           # fitness desc, index asc
+    assert ga.rank_order(fit) == list(order)
+    assert ga.elites(fit, 5) == list(order[:5])
+
+
+def test_tournament_win_probability_closed_form():
+    # rank r (1 = best) wins a size-k tournament with replacement with
+    # probability ((P - r + 1)^k - (P - r)^k) / P^k.
+    P, k, trials = 20, 3, 20000
+    fit = np.linspace(1.0, 0.0, P)                        # index i has rank i + 1
+    wins = np.zeros(P)
+    for j in range(trials // 2):
+        for s in (0, 1):
+            wins[ga.tournament(fit, j, s, 0, k, seed=31)] += 1
+    r = np.arange(1, P + 1)
+    prob = ((P - r + 1) ** k - (P - r) ** k) / P ** k
+    assert abs(prob[0] - 0.142625) < 1e-12 and abs(prob[-1] - 1.25e-4) < 1e-12
+    expect = prob * trials
+    # pool the sparse tail so every cell has an expected count >= 5
+    cut = np.argmax(np.cumsum(expect[::-1]) >= 5)
+    obs = np.concatenate([wins[:P - cut - 1], [wins[P - cut - 1:].sum()]])
+    exp = np.concatenate([expect[:P - cut - 1], [expect[P - cut - 1:].sum()]])
+    assert stats.chisquare(obs, exp).pvalue > 1e-4
+
+
+def test_irwin_hall_term_exact_enumeration():
+    # z = sum_12 (2u + 1 - 2^24) / 2^25 with u uniform on 0..2^24-1: enumerate every u.
+    u = np.arange(1 << 24, dtype=np.int64)
+    term = 2 * u + 1 - (1 << 24)
+    assert term.sum() == 0                                # mean exactly 0
+    sq = sum(int((c * c).sum()) for c in np.split(term, 1 << 10))   # exact: chunks fit int64
+    assert 3 * sq == (1 << 24) * ((1 << 48) - 1)          # E[term^2] = (2^48 - 1)/3
+    var_z = 12 * sq / (1 << 24) / 2.0 ** 50
+    assert var_z == 1.0 - 2.0 ** -48
+    # the oracle's scalar Gaussian reproduces the extreme values
+    assert ga.gaussian_ih12([0] * 12) == np.float32(-(12 * (2 ** 24 - 1)) / 2 ** 25)
+    assert ga.gaussian_ih12([2 ** 32 - 1] * 12) == np.float32(12 * (2 ** 24 - 1) / 2 ** 25)
+    assert ga.gaussian_ih12([2 ** 31] * 6 + [2 ** 31 - 256] * 6) == 0.0
+
+
+def test_vectorised_mutation_equals_scalar_definition():
+    pop = synth.random_population(40, 33, seed=2)
+    out = ga.mutate(pop, g=5, seed=77, p_mutation=0.3, sigma=0.25)
+    thr = ga.prob_threshold(0.3)
+    n_mut = 0
+    for c in range(40):
+        for l in range(33):
+            dec, words = ga._mutation_words(c, l, 5, 77)
+            if int(dec) < thr:
+                n_mut += 1
+                want = ga.mutate_gene(pop[c, l], [int(w) for w in words], np.float32(0.25))
+            else:
+                want = pop[c, l]
+            assert out[c, l].view(np.uint32) == np.float32(want).view(np.uint32)
+    assert n_mut > 0
+
+
+def test_mutation_statistics():
+    n, L = 400, 64
+    pop = np.zeros((n, L), dtype=np.float32)
+    out = ga.mutate(pop, g=1, seed=5, p_mutation=0.05, sigma=0.1)
+    hit = out != 0
+    rate = hit.mean()
+    assert abs(rate - 0.05) < 4 * math.sqrt(0.05 * 0.95 / (n * L))
+    z = out[hit].astype(np.float64) / 0.1
+    assert abs(z.mean()) < 4 / math.sqrt(z.size) and abs(z.var() - 1) < 0.1
+    assert np.abs(out).max() <= 0.6
+    # clamping: genes at the bound never leave [-1, 1]
+    edge = np.ones((n, L), dtype=np.float32)
+    out = ga.mutate(edge, g=1, seed=5, p_mutation=1.0, sigma=2.0)
+    assert out.max() <= 1.0 and out.min() >= -1.0 and (out == 1.0).mean() > 0.4
+
+
+@pytest.mark.parametrize("P,L,E", [(20, 32, 2), (21, 7, 2), (8, 1, 1), (16, 12, 0), (5, 9, 5)])
+def test_ga_step_invariants(P, L, E):
+    pop = ga.init_population(P, L, seed=P * L)
+    fit = synth.random_fitness(P, seed=L, n_ties=3, n_nan=1)
+    new = ga.ga_step(pop, fit, g=3, seed=99, elitism=E)
+    assert new.shape == pop.shape and new.dtype == np.float32
+    assert new.min() >= -1.0 and new.max() <= 1.0
+    for e, idx in enumerate(ga.elites(fit, E)):
+        np.testing.assert_array_equal(new[e].view(np.uint32), pop[idx].view(np.uint32))
+
+
+def test_without_mutation_children_inherit_loci():
+    P, L = 30, 25
+    pop = ga.init_population(P, L, seed=1)
+    fit = synth.random_fitness(P, seed=2)
+    new = ga.ga_step(pop, fit, g=0, seed=4, elitism=2, p_mutation=0.0)
+    for c in range(2, P):
+        for l in range(L):
+            assert new[c, l] in pop[:, l]
+    copies = ga.ga_step(pop, fit, g=0, seed=4, elitism=2, p_mutation=0.0, p_crossover=0.0)
+    rows = {r.tobytes() for r in pop}
+    assert all(r.tobytes() in rows for r in copies)
+
+
+def test_crossover_children_are_complementary_and_cut_uniform():
+    P, L = 12, 9
+    pop = np.arange(P * L, dtype=np.float32).reshape(P, L) / (P * L)   # every gene unique
+    fit = synth.random_fitness(P, seed=3)
+    cuts = []
+    for g in range(300):
+        kids = ga.make_offspring(pop, fit, g, 2, seed=8, p_crossover=1.0, p_mutation=0.0)
+        a = int(np.argmax((pop[:, 0] == kids[0, 0])))
+        b = int(np.argmax((pop[:, 0] == kids[1, 0])))
+        cut = next((l for l in range(L) if kids[0, l] != pop[a, l]), L)
+        np.testing.assert_array_equal(kids[0], np.concatenate([pop[a, :cut], pop[b, cut:]]))
+        np.testing.assert_array_equal(kids[1], np.concatenate([pop[b, :cut], pop[a, cut:]]))
+        if a != b:
+            cuts.append(cut)
+    counts = np.bincount(cuts, minlength=L)[1:]
+    assert counts.min() > 0 and counts.sum() == len(cuts)
+    assert stats.chisquare(counts).pvalue > 1e-4
+
+
+def test_best_fitness_never_decreases_with_elitism():
+    X, t, _ = synth.regression_dataset(300, 3, 3, 0.05, seed=10)
+    pop = ga.init_population(24, 9, seed=5)
+    best = -np.inf
+    for g in range(15):
+        fit = model.evaluate(X, t, pop, "chebyshev", 3, "regression")["fitness"]
+        assert fit.max() >= best
+        best = fit.max()
+        pop = ga.ga_step(pop, fit, g, seed=5, elitism=2)
