@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the GAME hot path on one MI355X.
+
+One step = one generation of the whole hot path over the benchmark workload:
+pack the population's gene tile, evaluate every chromosome on every pattern
+(MFMA contraction + fused sigmoid / squared error / misclassification
+reduce), the fixed-order final reduce, ranking with elitism, best tracking,
+and the genetic operators (tournament, crossover, mutation) producing the
+next population.  Steps are replayed from captured HIP graphs.  The basis
+Phi is built once when the context is created (the inputs never change) and
+is timed separately.
+
+Workload (default): 100,000 patterns x 10 features from a two-class Gaussian
+mixture (30/70, min-max scaled to [-1, 1]), trigonometric expansion of
+degree 6 (120 genes), population 1000, sigmoid output, FP32.
+
+Prints one JSON line.  Metric: chromosome x pattern fitness evaluations per
+second over the whole step.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fitness evals/s (chromosome x pattern), plain FP32 vs BF16/surrogate at equal MSE"
+PEAK = {  # MI355X published dense peaks
+    "f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0,  # TFLOP/s
+}
+FITNESS_SRC = os.path.join(ROOT, "paper_1211_5481_amd", "csrc", "fitness.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fitness_c2_traffic.txt")
+
+
+def workload(name: str, dtype: str):
+    import synth
+    if name == "c2":
+        N, F, D, P = 100_000, 10, 6, 1000
+        X, t = synth.classification_dataset(N, F, seed=synth.data_seed(2))
+        return dict(workload="classification N=100000 F=10 trig D=6 P=1000",
+                    N=N, F=F, D=D, P=P, basis="trig", task="classification",
+                    ga_seed=synth.ga_seed(2)), X, t
+    if name == "c3":
+        N, F, D, P = 1_000_000, 16, 8, 2048
+        X, t = synth.classification_dataset(N, F, seed=synth.data_seed(3))
+        return dict(workload="classification N=1000000 F=16 legendre D=8 P=2048",
+                    N=N, F=F, D=D, P=P, basis="legendre", task="classification",
+                    ga_seed=synth.ga_seed(3)), X, t
+    raise SystemExit(f"unknown workload {name}")
+
+
+def source_hash() -> str:
+    with open(FITNESS_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(per_launch_bytes_hint=None):
+    """HBM bytes per fitness launch from the committed rocprofv3 counter summary,
+    or None if the summary is missing or was taken on other kernel source."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m_hash = re.search(r"fitness_src_sha256_16:\s*([0-9a-f]+)", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_b or m_hash.group(1) != source_hash():
+        return None
+    return float(m_b.group(1))
+
+
+def cpu_baseline(meta, X, t, dtype, seconds: float):
+    """The float64 oracle timed on the host cores over whole generations
+    (evaluate every chromosome on every pattern, then one GA step)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import ga, model
+    Xo = X.astype(np.float32).astype(np.float64)
+    Phi = model.design_matrix(Xo, meta["basis"], meta["D"])   # once, like the device
+    L = Phi.shape[1]
+    pop = ga.init_population(meta["P"], L, meta["ga_seed"])
+    gens, t0 = 0, time.perf_counter()
+    while True:
+        r = model.evaluate(Xo, t, pop, meta["basis"], meta["D"], meta["task"], Phi=Phi)
+        pop = ga.ga_step(pop, r["fitness"], gens, meta["ga_seed"])
+        gens += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or gens >= 50:
+            break
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": meta["P"] * meta["N"] * gens / el, "unit": "evals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{gens} full generations (all {meta['N']} patterns x {meta['P']} "
+                      f"chromosomes, then the GA step) of the float64 numpy oracle, Phi "
+                      f"precomputed, {el:.1f} s; BLAS threads {threads}, elementwise work "
+                      f"single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16", "f64"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy kernel (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(row sharding is described in the design notes); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1211_5481_amd import Config, Game, build_basis
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        # elementwise copy kernel: reads and writes exactly 256 MiB each
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "elementwise copy", "bytes_read": x.numel() * 4,
+                          "bytes_written": y.numel() * 4, "launches": 3}))
+        return
+    meta, X, t = workload(args.workload, args.dtype)
+    io = torch.float64 if args.dtype == "f64" else torch.float32
+    Xd = torch.tensor(X, dtype=io, device="cuda")
+    td = torch.tensor(t, dtype=io, device="cuda")
+    cfg = Config(n_patterns=meta["N"], n_features=meta["F"], degree=meta["D"], basis=meta["basis"],
+                 task=meta["task"], dtype=args.dtype, pop_size=meta["P"], elitism=2,
+                 tournament_k=3, p_crossover=0.9, p_mutation=0.05, mutation_sigma=0.1,
+                 seed=meta["ga_seed"])
+    g = Game(cfg, Xd, td)
+    M = g.dims.M
+    print(f"[bench] {meta['workload']} dtype={args.dtype} M={M} L={g.L}", file=sys.stderr, flush=True)
+
+    # basis, once per dataset (not part of a step)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    build_basis(cfg, Xd)
+    e0.record()
+    phi = build_basis(cfg, Xd, ld=g.dims.M_pad)
+    e1.record()
+    torch.cuda.synchronize()
+    basis_ms = e0.elapsed_time(e1)
+    del phi
+
+    g.advance(args.warmup)
+    torch.cuda.synchronize()
+    e0.record()
+    g.advance(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    print(f"[bench] {args.steps} steps: {ms_step:.4f} ms/step", file=sys.stderr, flush=True)
+
+    kernel_ms = g.time_fitness(reps=50)
+    st = g.state()
+    N, P = meta["N"], meta["P"]
+    evals = float(N) * P
+    flops = 2.0 * N * M * P                  # algorithmic: unpadded genes and population
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    peak = PEAK[args.dtype]
+    traffic = measured_traffic() if args.dtype == "f32" and args.workload == "c2" else None
+    out = {
+        "metric": METRIC,
+        "value": evals / (ms_step * 1e-3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": meta["workload"], "patterns": N, "features": meta["F"],
+                   "basis": meta["basis"], "degree": meta["D"], "genes": g.L,
+                   "population": P, "task": meta["task"], "elitism": 2, "tournament_k": 3,
+                   "p_crossover": 0.9, "p_mutation": 0.05, "mutation_sigma": 0.1},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "fitness_kernel", "kernel_ms": kernel_ms,
+                     "flops_per_launch": flops},
+        "fitness_kernel_evals_per_s": evals / (kernel_ms * 1e-3),
+        "basis_ms_once": basis_ms,
+        "best_mse_after": st["best_mse"],
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(meta, X, t, args.dtype, args.cpu_seconds)
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,227 @@
+/*
+ * game.h -- C ABI of libgame.so, the MI355X (gfx950) fitness hot path of GAME,
+ * the genetic algorithm of Cavuoti et al., "Genetic Algorithm Modeling with GPU
+ * Parallel Computing Technology" (arXiv:1211.5481).
+ *
+ * What the library computes (Sec. 3 of the paper):
+ *   - every pattern (f_1..f_F, t) has each feature expanded in a polynomial
+ *     sequence of degree D (eq. 1; the trigonometric "polytrigo" sequence of
+ *     eq. 6 has cos and sin groups, B = 2), giving the basis row
+ *     Phi[n, i*K + k] = phi_{k+1}(x[n, i]),  K = B*D,  M = F*K;
+ *   - a chromosome holds one coefficient (gene) per basis column, plus an
+ *     optional constant a_0 stored last (L = M or M + 1 genes), and its output
+ *     on pattern n is z = sum_m Phi[n, m] G[m] (+ a_0)  (eq. 2);
+ *   - the error of a pattern is (t - out)^2 (eq. 3) with out = z (regression)
+ *     or the logistic sigmoid of z (classification); a chromosome's error is
+ *     the mean over all patterns (MSE) and its fitness is 1 - MSE;
+ *   - a generation applies elitism, tournament selection, one-point
+ *     crossover and Gaussian mutation, with genes kept in [-1, 1] (Sec. 3
+ *     operator list; Sec. 5 rates), every random draw coming from a
+ *     Philox4x32-10 counter (Salmon et al., SC'11) keyed by the seed;
+ *   - training repeats evaluation and evolution until a generation count or
+ *     an error threshold is reached (Sec. 4).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns a game_status; nothing throws or aborts across the ABI.
+ *   - The library never allocates device memory.  The caller owns the inputs,
+ *     the workspace, every output buffer and the stream; the workspace must
+ *     stay allocated and untouched while the context lives.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls marked "async" only enqueue work on that stream.
+ *   - Arguments are validated before any launch; an invalid argument returns
+ *     GAME_E_INVALID and changes nothing.  A HIP error returns GAME_E_DEVICE
+ *     and poisons the context: later calls on it return GAME_E_STATE.
+ *   - game_last_error() returns a message describing the last failure of the
+ *     calling thread.
+ */
+#ifndef GAME_H
+#define GAME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct game_ctx game_ctx; /* opaque; created by game_init, freed by game_destroy */
+
+typedef enum {
+  GAME_OK = 0,
+  GAME_E_INVALID = 1,     /* bad argument or configuration                        */
+  GAME_E_OOM = 2,         /* workspace too small for the configuration            */
+  GAME_E_DEVICE = 3,      /* a HIP call failed; the context is poisoned          */
+  GAME_E_STATE = 4,       /* context poisoned, or call out of order               */
+  GAME_E_UNSUPPORTED = 5  /* valid but not implemented combination                */
+} game_status;
+
+/* Basis families.  B = 1 except TRIG (B = 2: cos(1x)..cos(Dx), sin(1x)..sin(Dx)). */
+typedef enum {
+  GAME_BASIS_POWER = 0,     /* x^k, k = 1..D                                      */
+  GAME_BASIS_CHEBYSHEV = 1, /* T_k(x), k = 1..D                                   */
+  GAME_BASIS_LEGENDRE = 2,  /* P_k(x), k = 1..D                                   */
+  GAME_BASIS_TRIG = 3       /* eq. 6 polytrigo                                    */
+} game_basis;
+
+typedef enum { GAME_REGRESSION = 0, GAME_CLASSIFICATION = 1 } game_task;
+
+/* Storage/compute type of Phi and the gene tile.  F64: x and t are double and the
+ * contraction runs in double.  F32: x, t float, FP32 MFMA.  BF16/F16: x, t float,
+ * Phi and genes rounded (nearest even) to 16 bits, FP32 accumulation. */
+typedef enum { GAME_F64 = 0, GAME_F32 = 1, GAME_BF16 = 2, GAME_F16 = 3 } game_dtype;
+
+typedef enum { GAME_SEL_TOURNAMENT = 0 } game_selection;
+
+typedef enum {
+  GAME_STOP_NONE = 0,       /* still running / never run                          */
+  GAME_STOP_THRESHOLD = 1,  /* best MSE <= mse_threshold                          */
+  GAME_STOP_MAX_GEN = 2     /* max_generations generations evaluated              */
+} game_stop_reason;
+
+typedef struct {
+  uint32_t struct_size;     /* must equal sizeof(game_config)                     */
+  int32_t  basis;           /* game_basis                                         */
+  int64_t  n_patterns;      /* N >= 1                                             */
+  int32_t  n_features;      /* F >= 1                                             */
+  int32_t  degree;          /* D >= 1                                             */
+  int32_t  task;            /* game_task                                          */
+  int32_t  dtype;           /* game_dtype                                         */
+  int32_t  bias;            /* 0 | 1: gene a_0 stored at index M                  */
+  int32_t  pop_size;        /* P; 0 -> B*F + 1 (eq. 4)                            */
+  int32_t  n_offspring;     /* 0 -> P - elitism (generational replacement)        */
+  int32_t  elitism;         /* E in [0, min(P, 64)] (the paper's runs use 2)      */
+  int32_t  selection;       /* game_selection                                     */
+  int32_t  tournament_k;    /* k in [1, 16]                                       */
+  int32_t  max_generations; /* >= 1, used by game_run                             */
+  double   p_crossover;     /* [0, 1] per child pair                              */
+  double   p_mutation;      /* [0, 1] per gene                                    */
+  double   mutation_sigma;  /* >= 0, standard deviation of the Gaussian step      */
+  double   mse_threshold;   /* game_run stops once best MSE <= this               */
+  uint64_t seed;            /* Philox key                                         */
+} game_config;
+
+/* Sizes the library derives from a configuration. */
+typedef struct {
+  int32_t  K;               /* basis columns per feature, B*D                     */
+  int32_t  M;               /* basis columns, F*K                                 */
+  int32_t  L;               /* genes per chromosome, M + bias                     */
+  int32_t  M_pad;           /* row stride of Phi and of the gene tile (elements)  */
+  int32_t  P;               /* population size after defaults                     */
+  int32_t  n_offspring;     /* offspring per generation after defaults            */
+  int64_t  N_pad;           /* rows of Phi in the workspace (N rounded up)        */
+  size_t   workspace_bytes; /* bytes game_init needs                              */
+} game_dims;
+
+/* Result of game_run. */
+typedef struct {
+  double   best_mse;        /* MSE of the best chromosome seen                    */
+  double   best_fitness;    /* 1 - best_mse                                       */
+  double   best_miscls;     /* its misclassification rate (0 for regression)      */
+  int32_t  generations;     /* generations evaluated by this call                 */
+  int32_t  stop_reason;     /* game_stop_reason                                   */
+  float*   best_genes;      /* caller-provided HOST buffer of L floats, or NULL   */
+} game_result;
+
+/* Snapshot of the device-side run state (blocking copy). */
+typedef struct {
+  int32_t generation;       /* generations completed since game_init              */
+  int32_t stopped;          /* 1 once a game_run stop condition held              */
+  int32_t best_index;       /* index of the best chromosome of the last ranking   */
+  int32_t stop_reason;
+  double  best_mse, best_fitness, best_miscls;   /* best seen since game_init     */
+} game_state;
+
+/* Fill *cfg with the defaults: Chebyshev D=4, F32, regression, E=2, k=3,
+ * p_crossover 0.9, p_mutation 0.05, sigma 0.1, 100 generations, threshold 0.
+ * n_patterns / n_features must still be set by the caller. */
+void game_config_default(game_config* cfg);
+
+/* Validate cfg and report derived sizes (no device work). */
+game_status game_query(const game_config* cfg, game_dims* dims);
+
+/* Bytes of device workspace game_init needs for cfg. */
+game_status game_workspace_size(const game_config* cfg, size_t* bytes);
+
+/*
+ * Basis expansion alone (eq. 1 and 6), async.
+ *   X_dev:   N x F row-major, double if dtype == F64 else float (device).
+ *   phi_dev: N x ld row-major in the dtype's storage type (device, caller-owned);
+ *            ld >= M; columns M..ld-1 are written as zero.
+ * Returns GAME_E_INVALID for a bad cfg or ld < M.
+ */
+game_status game_build_basis(const game_config* cfg, const void* X_dev, void* phi_dev,
+                             int64_t ld, void* stream);
+
+/*
+ * Create a context: validates cfg, carves the workspace, builds Phi once for
+ * the whole training (the sin/cos precompute of Sec. 4), copies t, and draws
+ * the initial population (genes uniform in [-1, 1), Sec. 3).  Async; X and t
+ * may be freed once the stream has passed this call.
+ *   X_dev: N x F row-major (double if F64 else float); t_dev: N targets of the
+ *   same type (classification targets are 0 or 1).
+ *   workspace_dev: >= game_workspace_size bytes, 256-byte aligned.
+ */
+game_status game_init(const game_config* cfg, const void* X_dev, const void* t_dev,
+                      void* workspace_dev, size_t ws_bytes, void* stream, game_ctx** out);
+
+/*
+ * Fitness of a set of chromosomes over all N patterns, async (eq. 2, 3, MSE,
+ * fitness = 1 - MSE).
+ *   genes_dev: P x L row-major float chromosomes (device), or NULL for the
+ *              current population (then P must equal the population size).
+ *   P:         1 <= P <= max(population size, n_offspring).
+ *   mse_dev, miscls_dev, fitness_dev: P doubles each (device) or NULL.
+ * The results for the current population are also kept for game_step(NULL).
+ */
+game_status game_eval_fitness(game_ctx* ctx, const float* genes_dev, int32_t P,
+                              double* mse_dev, double* miscls_dev, double* fitness_dev);
+
+/*
+ * One generation of the genetic operators on the current population, async:
+ * elitism (the E best, fitness descending, ties to the lower index, NaN worst,
+ * copied unchanged), then P - E children from size-k tournaments, one-point
+ * crossover and per-gene Gaussian mutation clamped to [-1, 1].
+ *   fitness_dev: P doubles of the current population (device), or NULL to use
+ *                the last game_eval_fitness(NULL) result (GAME_E_STATE if none).
+ * Increments the generation counter that keys the random draws.
+ */
+game_status game_step(game_ctx* ctx, const double* fitness_dev);
+
+/*
+ * n generations of (evaluate current population, rank, evolve), async,
+ * replayed from a captured HIP graph; no stop test.
+ */
+game_status game_advance(game_ctx* ctx, int32_t n_generations);
+
+/*
+ * Train until best MSE <= mse_threshold or max_generations generations have
+ * been evaluated (Sec. 4).  Blocking.  Evaluation happens first in every
+ * generation; no evolution follows the generation that stops the run.
+ */
+game_status game_run(game_ctx* ctx, game_result* out);
+
+/* Copy the population out / in: P x L floats, device pointers, async. */
+game_status game_get_population(game_ctx* ctx, float* genes_dev);
+game_status game_set_population(game_ctx* ctx, const float* genes_dev);
+
+/* Blocking snapshot of the run state; best genes optional (host, L floats). */
+game_status game_get_state(game_ctx* ctx, game_state* out, float* best_genes_host);
+
+/*
+ * Measurement: launch only the fitness contraction kernel for the current
+ * population `reps` times on the context's stream, bracketed by two HIP
+ * events, and report the mean duration of one launch in *ms.  Blocking.
+ * The population's gene tile is packed once before the timed launches.
+ */
+game_status game_time_fitness(game_ctx* ctx, int32_t reps, float* ms);
+
+/* Release the context (host memory only; the workspace stays the caller's). */
+void game_destroy(game_ctx* ctx);
+
+const char* game_status_str(game_status s);
+const char* game_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GAME_H */

@@ -1,0 +1,515 @@
+// C ABI of libgame (declared in include/game.h): validation, workspace
+// carve-up, the per-generation launch sequence and its HIP-graph replay.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "game.h"
+#include "game_internal.hpp"
+
+namespace game {
+void fitness_tile(int dtype, int* tile_n, int* tile_p);
+}
+
+using namespace game;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+game_status fail(game_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+constexpr int kChunk = 8;  // generations per replayed graph in game_run / game_advance
+
+}  // namespace
+
+struct game_ctx {
+  game_config cfg;
+  Plan plan;
+  hipStream_t stream = nullptr;      // caller's stream
+  hipStream_t cap = nullptr;         // private stream used only for graph capture
+  hipGraphExec_t exec1 = nullptr, execC = nullptr;
+  hipGraph_t graph1 = nullptr, graphC = nullptr;
+  unsigned char* ws = nullptr;
+  void *phi, *tvec, *tile, *biasv;
+  float *pop, *next, *best;
+  double *psse, *mse, *miscls, *fit;
+  uint32_t* pmiss;
+  int* elite;
+  DevState* state;
+  uint64_t thr_c, thr_m;
+  bool poisoned = false;
+  bool have_eval = false;
+};
+
+namespace game {
+
+game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
+  auto bad = [&](const char* msg) {
+    std::snprintf(err, errlen, "%s", msg);
+    return GAME_E_INVALID;
+  };
+  if (!c) return bad("config is NULL");
+  if (c->struct_size != sizeof(game_config)) return bad("config struct_size mismatch (ABI version)");
+  if (c->basis < GAME_BASIS_POWER || c->basis > GAME_BASIS_TRIG) return bad("unknown basis");
+  if (c->task != GAME_REGRESSION && c->task != GAME_CLASSIFICATION) return bad("unknown task");
+  if (c->dtype < GAME_F64 || c->dtype > GAME_F16) return bad("unknown dtype");
+  if (c->n_patterns < 1) return bad("n_patterns must be >= 1");
+  if (c->n_patterns > (int64_t(1) << 40)) return bad("n_patterns too large");
+  if (c->n_features < 1 || c->degree < 1) return bad("n_features and degree must be >= 1");
+  if (c->bias != 0 && c->bias != 1) return bad("bias must be 0 or 1");
+  if (c->selection != GAME_SEL_TOURNAMENT) return bad("only tournament selection is available");
+  if (c->tournament_k < 1 || c->tournament_k > kMaxTournament) return bad("tournament_k must be in [1, 16]");
+  auto prob_ok = [](double v) { return std::isfinite(v) && v >= 0.0 && v <= 1.0; };
+  if (!prob_ok(c->p_crossover) || !prob_ok(c->p_mutation)) return bad("probabilities must be in [0, 1]");
+  if (!std::isfinite(c->mutation_sigma) || c->mutation_sigma < 0) return bad("mutation_sigma must be finite and >= 0");
+  if (c->max_generations < 1) return bad("max_generations must be >= 1");
+  if (std::isnan(c->mse_threshold)) return bad("mse_threshold is NaN");
+  const int64_t B = c->basis == GAME_BASIS_TRIG ? 2 : 1;
+  const int64_t K = B * c->degree;
+  const int64_t M = (int64_t)c->n_features * K;
+  const int64_t L = M + c->bias;
+  if (L > kMaxGenes) return bad("too many genes (F * B * D + bias must be <= 4096)");
+  int64_t P = c->pop_size;
+  if (P == 0) P = B * c->n_features + 1;  // eq. (4)
+  if (P < 1 || P > (1 << 24)) return bad("pop_size out of range");
+  if (c->elitism < 0 || c->elitism > P || c->elitism > kMaxElite) return bad("elitism must be in [0, min(P, 64)]");
+  int64_t n_off = c->n_offspring == 0 ? P - c->elitism : c->n_offspring;
+  if (n_off != P - c->elitism) {
+    std::snprintf(err, errlen, "n_offspring other than P - elitism is not available");
+    return GAME_E_UNSUPPORTED;
+  }
+  p->K = (int)K;
+  p->M = (int)M;
+  p->L = (int)L;
+  p->M_pad = (int)round_up(M, (c->dtype == GAME_BF16 || c->dtype == GAME_F16) ? 32 : 8);
+  p->P = (int)P;
+  p->n_off = (int)n_off;
+  p->E = c->elitism;
+  p->k = c->tournament_k;
+  p->P_max = (int)(P > n_off ? P : n_off);
+  fitness_tile(c->dtype, &p->tile_n, &p->tile_p);
+  p->N = c->n_patterns;
+  p->N_pad = round_up(p->N, p->tile_n);
+  p->n_rt = p->N_pad / p->tile_n;
+  p->P_max_pad = (int)round_up(p->P_max, p->tile_p);
+  p->n_rg_max = p->n_rt < 8193 ? p->n_rt : 8193;
+  p->rt_per_wg_max = (int)((p->n_rt + p->n_rg_max - 1) / p->n_rg_max);
+  p->elt = c->dtype == GAME_F64 ? 8 : c->dtype == GAME_F32 ? 4 : 2;
+  p->acc = c->dtype == GAME_F64 ? 8 : 4;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  p->off_phi = take((size_t)p->N_pad * p->M_pad * p->elt);
+  p->off_t = take((size_t)p->N_pad * p->acc);
+  p->off_tile = take((size_t)p->P_max_pad * p->M_pad * p->elt);
+  p->off_bias = take((size_t)p->P_max_pad * p->acc);
+  p->off_pop = take((size_t)P * L * 4);
+  p->off_next = take((size_t)P * L * 4);
+  p->off_psse = take((size_t)p->n_rg_max * p->P_max_pad * 8);
+  p->off_pmiss = take((size_t)p->n_rg_max * p->P_max_pad * 4);
+  p->off_mse = take((size_t)p->P_max * 8);
+  p->off_miscls = take((size_t)p->P_max * 8);
+  p->off_fit = take((size_t)p->P_max * 8);
+  p->off_elite = take(kMaxElite * 4);
+  p->off_state = take(sizeof(DevState));
+  p->off_best = take((size_t)L * 4);
+  p->total = off;
+  return GAME_OK;
+}
+
+FitnessGeom fitness_geometry(const Plan& p, int P_eval) {
+  FitnessGeom g;
+  g.n_pt = (P_eval + p.tile_p - 1) / p.tile_p;
+  // Enough workgroups to fill 256 CUs many times over, few enough that the
+  // partial sums stay small next to the Phi traffic.
+  const int64_t target = 8192;
+  int64_t rpw = (p.n_rt * g.n_pt + target - 1) / target;
+  if (rpw < 1) rpw = 1;
+  if ((p.n_rt + rpw - 1) / rpw > p.n_rg_max) rpw = (p.n_rt + p.n_rg_max - 1) / p.n_rg_max;
+  g.rt_per_wg = (int)rpw;
+  g.n_rg = (p.n_rt + rpw - 1) / rpw;
+  g.n_items = g.n_rg * g.n_pt;
+  g.grid = (g.n_items + 7) / 8 * 8;
+  return g;
+}
+
+}  // namespace game
+
+namespace {
+
+game_status check_ctx(game_ctx* ctx) {
+  if (!ctx) return fail(GAME_E_INVALID, "context is NULL");
+  if (ctx->poisoned) return fail(GAME_E_STATE, "context poisoned by an earlier device error");
+  return GAME_OK;
+}
+
+game_status dev(game_ctx* ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return GAME_OK;
+  if (ctx) ctx->poisoned = true;
+  return fail(GAME_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define GAME_TRY(expr)                   \
+  do {                                   \
+    const game_status _s = (expr);       \
+    if (_s != GAME_OK) return _s;        \
+  } while (0)
+
+// pack -> fitness -> reduce for P_eval chromosomes in `genes`.
+game_status enqueue_eval(game_ctx* c, const float* genes, int P_eval, double* mse, double* miscls,
+                         double* fit, double* mse2, double* miscls2, double* fit2,
+                         const DevState* st, hipStream_t s) {
+  const Plan& p = c->plan;
+  const FitnessGeom g = fitness_geometry(p, P_eval);
+  GAME_TRY(dev(c,
+               launch_pack(c->cfg.dtype, genes, P_eval, p.L, p.M, c->cfg.bias, p.M_pad,
+                           g.n_pt * p.tile_p, c->tile, c->biasv, st, s),
+               "pack"));
+  GAME_TRY(dev(c,
+               launch_fitness(p, c->cfg.task, c->cfg.dtype, g, c->phi, c->tile,
+                              c->cfg.bias ? c->biasv : nullptr, c->tvec, c->psse, c->pmiss, st, s),
+               "fitness"));
+  GAME_TRY(dev(c,
+               launch_reduce(p, g, P_eval, c->psse, c->pmiss, mse, miscls, fit, mse2, miscls2,
+                             fit2, st, s),
+               "reduce"));
+  return GAME_OK;
+}
+
+// Evaluate the current population, rank it and track the best chromosome.
+game_status enqueue_eval_population(game_ctx* c, double* mse, double* miscls, double* fit,
+                                    hipStream_t s) {
+  const Plan& p = c->plan;
+  GAME_TRY(enqueue_eval(c, c->pop, p.P, c->mse, c->miscls, c->fit, mse, miscls, fit, c->state, s));
+  const int n_top = p.E > 0 ? p.E : 1;
+  GAME_TRY(dev(c, launch_rank(c->fit, p.P, n_top, c->elite, c->state, s), "rank"));
+  GAME_TRY(dev(c, launch_track(c->state, c->elite, c->mse, c->miscls, c->pop, p.L, c->best, s),
+               "track"));
+  return GAME_OK;
+}
+
+game_status enqueue_evolve(game_ctx* c, const double* fit, hipStream_t s) {
+  const Plan& p = c->plan;
+  GAME_TRY(dev(c,
+               launch_breed(c->pop, fit, c->elite, c->next, p.P, p.L, p.E, p.n_off, p.k, c->thr_c,
+                            c->thr_m, (float)c->cfg.mutation_sigma, c->cfg.seed, c->state, s),
+               "breed"));
+  GAME_TRY(dev(c, launch_commit(c->next, c->pop, (int64_t)p.P * p.L, c->state, s), "commit"));
+  return GAME_OK;
+}
+
+game_status enqueue_generation(game_ctx* c, hipStream_t s) {
+  GAME_TRY(enqueue_eval_population(c, nullptr, nullptr, nullptr, s));
+  GAME_TRY(enqueue_evolve(c, c->fit, s));
+  return GAME_OK;
+}
+
+game_status build_graph(game_ctx* c, int n_gen, hipGraph_t* graph, hipGraphExec_t* exec) {
+  if (*exec) return GAME_OK;
+  if (!c->cap) GAME_TRY(dev(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking), "stream create"));
+  GAME_TRY(dev(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "begin capture"));
+  game_status st = GAME_OK;
+  for (int i = 0; i < n_gen && st == GAME_OK; ++i) st = enqueue_generation(c, c->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->cap, &g);
+  if (st != GAME_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  GAME_TRY(dev(c, e, "end capture"));
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return dev(c, ei, "graph instantiate");
+  }
+  *graph = g;
+  *exec = x;
+  return GAME_OK;
+}
+
+uint64_t threshold(double p) { return (uint64_t)std::floor(p * 4294967296.0); }
+
+}  // namespace
+
+extern "C" {
+
+void game_config_default(game_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->struct_size = sizeof(game_config);
+  c->basis = GAME_BASIS_CHEBYSHEV;
+  c->n_patterns = 0;
+  c->n_features = 0;
+  c->degree = 4;
+  c->task = GAME_REGRESSION;
+  c->dtype = GAME_F32;
+  c->bias = 0;
+  c->pop_size = 0;
+  c->n_offspring = 0;
+  c->elitism = 2;
+  c->selection = GAME_SEL_TOURNAMENT;
+  c->tournament_k = 3;
+  c->max_generations = 100;
+  c->p_crossover = 0.9;
+  c->p_mutation = 0.05;
+  c->mutation_sigma = 0.1;
+  c->mse_threshold = 0.0;
+  c->seed = 0;
+}
+
+game_status game_query(const game_config* cfg, game_dims* d) {
+  if (!d) return fail(GAME_E_INVALID, "dims is NULL");
+  Plan p;
+  char err[256];
+  const game_status s = make_plan(cfg, &p, err, sizeof(err));
+  if (s != GAME_OK) return fail(s, "%s", err);
+  d->K = p.K;
+  d->M = p.M;
+  d->L = p.L;
+  d->M_pad = p.M_pad;
+  d->P = p.P;
+  d->n_offspring = p.n_off;
+  d->N_pad = p.N_pad;
+  d->workspace_bytes = p.total;
+  return GAME_OK;
+}
+
+game_status game_workspace_size(const game_config* cfg, size_t* bytes) {
+  if (!bytes) return fail(GAME_E_INVALID, "bytes is NULL");
+  game_dims d;
+  GAME_TRY(game_query(cfg, &d));
+  *bytes = d.workspace_bytes;
+  return GAME_OK;
+}
+
+game_status game_build_basis(const game_config* cfg, const void* X, void* phi, int64_t ld, void* stream) {
+  Plan p;
+  char err[256];
+  const game_status s = make_plan(cfg, &p, err, sizeof(err));
+  if (s != GAME_OK) return fail(s, "%s", err);
+  if (!X || !phi) return fail(GAME_E_INVALID, "X and phi must be device pointers");
+  if (ld < p.M || ld * (int64_t)p.elt > 65536) return fail(GAME_E_INVALID, "ld must be in [M, 64 KiB / element size]");
+  const hipError_t e = launch_basis(cfg, X, p.N, p.N, phi, ld, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(GAME_E_DEVICE, "basis: %s", hipGetErrorString(e));
+  return GAME_OK;
+}
+
+game_status game_init(const game_config* cfg, const void* X, const void* t, void* ws,
+                      size_t ws_bytes, void* stream, game_ctx** out) {
+  if (!out) return fail(GAME_E_INVALID, "out is NULL");
+  *out = nullptr;
+  Plan p;
+  char err[256];
+  const game_status s = make_plan(cfg, &p, err, sizeof(err));
+  if (s != GAME_OK) return fail(s, "%s", err);
+  if (!X || !t || !ws) return fail(GAME_E_INVALID, "X, t and workspace must be device pointers");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(GAME_E_INVALID, "workspace must be 256-byte aligned");
+  if (ws_bytes < p.total)
+    return fail(GAME_E_OOM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, p.total);
+  game_ctx* c = new (std::nothrow) game_ctx();
+  if (!c) return fail(GAME_E_OOM, "host allocation of the context failed");
+  c->cfg = *cfg;
+  c->plan = p;
+  c->stream = (hipStream_t)stream;
+  c->ws = static_cast<unsigned char*>(ws);
+  c->phi = c->ws + p.off_phi;
+  c->tvec = c->ws + p.off_t;
+  c->tile = c->ws + p.off_tile;
+  c->biasv = c->ws + p.off_bias;
+  c->pop = reinterpret_cast<float*>(c->ws + p.off_pop);
+  c->next = reinterpret_cast<float*>(c->ws + p.off_next);
+  c->psse = reinterpret_cast<double*>(c->ws + p.off_psse);
+  c->pmiss = reinterpret_cast<uint32_t*>(c->ws + p.off_pmiss);
+  c->mse = reinterpret_cast<double*>(c->ws + p.off_mse);
+  c->miscls = reinterpret_cast<double*>(c->ws + p.off_miscls);
+  c->fit = reinterpret_cast<double*>(c->ws + p.off_fit);
+  c->elite = reinterpret_cast<int*>(c->ws + p.off_elite);
+  c->state = reinterpret_cast<DevState*>(c->ws + p.off_state);
+  c->best = reinterpret_cast<float*>(c->ws + p.off_best);
+  c->thr_c = threshold(cfg->p_crossover);
+  c->thr_m = threshold(cfg->p_mutation);
+  hipStream_t st = c->stream;
+  game_status r = GAME_OK;
+  if (r == GAME_OK) r = dev(c, launch_basis(cfg, X, p.N, p.N_pad, c->phi, p.M_pad, st), "basis");
+  if (r == GAME_OK) r = dev(c, launch_copy_targets(cfg->dtype, t, p.N, p.N_pad, c->tvec, st), "targets");
+  if (r == GAME_OK) r = dev(c, launch_init_population(c->pop, p.P, p.L, cfg->seed, st), "init population");
+  if (r == GAME_OK) r = dev(c, launch_state_init(c->state, st), "state init");
+  if (r != GAME_OK) {
+    delete c;
+    return r;
+  }
+  *out = c;
+  return GAME_OK;
+}
+
+game_status game_eval_fitness(game_ctx* c, const float* genes, int32_t P, double* mse,
+                              double* miscls, double* fit) {
+  GAME_TRY(check_ctx(c));
+  if (genes == nullptr) {
+    if (P != c->plan.P) return fail(GAME_E_INVALID, "P must equal the population size when genes is NULL");
+    GAME_TRY(enqueue_eval_population(c, mse, miscls, fit, c->stream));
+    c->have_eval = true;
+    return GAME_OK;
+  }
+  if (P < 1 || P > c->plan.P_max) return fail(GAME_E_INVALID, "P must be in [1, %d]", c->plan.P_max);
+  return enqueue_eval(c, genes, P, mse, miscls, fit, nullptr, nullptr, nullptr, nullptr, c->stream);
+}
+
+game_status game_step(game_ctx* c, const double* fit) {
+  GAME_TRY(check_ctx(c));
+  const Plan& p = c->plan;
+  if (fit == nullptr) {
+    if (!c->have_eval) return fail(GAME_E_STATE, "game_step(NULL) needs game_eval_fitness(NULL) on the current population first");
+    GAME_TRY(enqueue_evolve(c, c->fit, c->stream));
+  } else {
+    const int n_top = p.E > 0 ? p.E : 1;
+    GAME_TRY(dev(c, launch_rank(fit, p.P, n_top, c->elite, nullptr, c->stream), "rank"));
+    GAME_TRY(enqueue_evolve(c, fit, c->stream));
+  }
+  c->have_eval = false;
+  return GAME_OK;
+}
+
+game_status game_advance(game_ctx* c, int32_t n) {
+  GAME_TRY(check_ctx(c));
+  if (n < 0) return fail(GAME_E_INVALID, "n_generations must be >= 0");
+  if (n == 0) return GAME_OK;
+  if (n >= kChunk) GAME_TRY(build_graph(c, kChunk, &c->graphC, &c->execC));
+  if (n % kChunk) GAME_TRY(build_graph(c, 1, &c->graph1, &c->exec1));
+  for (int i = 0; i + kChunk <= n; i += kChunk)
+    GAME_TRY(dev(c, hipGraphLaunch(c->execC, c->stream), "graph launch"));
+  for (int i = 0; i < n % kChunk; ++i) GAME_TRY(dev(c, hipGraphLaunch(c->exec1, c->stream), "graph launch"));
+  c->have_eval = false;
+  return GAME_OK;
+}
+
+game_status game_get_state(game_ctx* c, game_state* out, float* best_genes) {
+  GAME_TRY(check_ctx(c));
+  if (!out) return fail(GAME_E_INVALID, "out is NULL");
+  DevState h;
+  GAME_TRY(dev(c, hipMemcpyAsync(&h, c->state, sizeof(h), hipMemcpyDeviceToHost, c->stream), "state copy"));
+  if (best_genes)
+    GAME_TRY(dev(c, hipMemcpyAsync(best_genes, c->best, (size_t)c->plan.L * 4, hipMemcpyDeviceToHost, c->stream), "best copy"));
+  GAME_TRY(dev(c, hipStreamSynchronize(c->stream), "synchronize"));
+  out->generation = h.generation;
+  out->stopped = h.stopped;
+  out->best_index = h.best_index;
+  out->stop_reason = h.stop_reason;
+  out->best_mse = h.best_mse;
+  out->best_fitness = h.best_fitness;
+  out->best_miscls = h.best_miscls;
+  return GAME_OK;
+}
+
+game_status game_run(game_ctx* c, game_result* res) {
+  GAME_TRY(check_ctx(c));
+  if (!res) return fail(GAME_E_INVALID, "result is NULL");
+  const int G = c->cfg.max_generations;
+  GAME_TRY(build_graph(c, kChunk, &c->graphC, &c->execC));
+  game_state s0;
+  GAME_TRY(game_get_state(c, &s0, nullptr));
+  GAME_TRY(dev(c, launch_run_arm(c->state, G, c->cfg.mse_threshold, c->stream), "arm"));
+  game_state s = s0;
+  // each chunk evaluates up to kChunk generations; kernels after the stop are no-ops
+  for (int launched = 0; launched < G + kChunk; launched += kChunk) {
+    GAME_TRY(dev(c, hipGraphLaunch(c->execC, c->stream), "graph launch"));
+    GAME_TRY(game_get_state(c, &s, nullptr));
+    if (s.stopped) break;
+  }
+  GAME_TRY(dev(c, launch_run_disarm(c->state, c->stream), "disarm"));
+  GAME_TRY(game_get_state(c, &s, res->best_genes));
+  if (!s.stopped) return fail(GAME_E_STATE, "run did not reach a stop condition");
+  res->best_mse = s.best_mse;
+  res->best_fitness = s.best_fitness;
+  res->best_miscls = s.best_miscls;
+  res->generations = s.generation - s0.generation + 1;
+  res->stop_reason = s.stop_reason;
+  c->have_eval = true;  // the population is the last evaluated generation
+  return GAME_OK;
+}
+
+game_status game_get_population(game_ctx* c, float* genes) {
+  GAME_TRY(check_ctx(c));
+  if (!genes) return fail(GAME_E_INVALID, "genes is NULL");
+  return dev(c, hipMemcpyAsync(genes, c->pop, (size_t)c->plan.P * c->plan.L * 4, hipMemcpyDeviceToDevice, c->stream), "population copy");
+}
+
+game_status game_set_population(game_ctx* c, const float* genes) {
+  GAME_TRY(check_ctx(c));
+  if (!genes) return fail(GAME_E_INVALID, "genes is NULL");
+  c->have_eval = false;
+  return dev(c, hipMemcpyAsync(c->pop, genes, (size_t)c->plan.P * c->plan.L * 4, hipMemcpyDeviceToDevice, c->stream), "population copy");
+}
+
+game_status game_time_fitness(game_ctx* c, int32_t reps, float* ms) {
+  GAME_TRY(check_ctx(c));
+  if (reps < 1 || !ms) return fail(GAME_E_INVALID, "reps must be >= 1 and ms non-NULL");
+  const Plan& p = c->plan;
+  const FitnessGeom g = fitness_geometry(p, p.P);
+  GAME_TRY(dev(c,
+               launch_pack(c->cfg.dtype, c->pop, p.P, p.L, p.M, c->cfg.bias, p.M_pad,
+                           g.n_pt * p.tile_p, c->tile, c->biasv, nullptr, c->stream),
+               "pack"));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  GAME_TRY(dev(c, hipEventCreate(&e0), "event create"));
+  game_status s = dev(c, hipEventCreate(&e1), "event create");
+  if (s == GAME_OK) s = dev(c, hipEventRecord(e0, c->stream), "event record");
+  for (int r = 0; r < reps && s == GAME_OK; ++r)
+    s = dev(c,
+            launch_fitness(p, c->cfg.task, c->cfg.dtype, g, c->phi, c->tile,
+                           c->cfg.bias ? c->biasv : nullptr, c->tvec, c->psse, c->pmiss, nullptr,
+                           c->stream),
+            "fitness");
+  if (s == GAME_OK) s = dev(c, hipEventRecord(e1, c->stream), "event record");
+  if (s == GAME_OK) s = dev(c, hipEventSynchronize(e1), "event synchronize");
+  float total = 0.f;
+  if (s == GAME_OK) s = dev(c, hipEventElapsedTime(&total, e0, e1), "elapsed time");
+  if (s == GAME_OK) *ms = total / (float)reps;
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return s;
+}
+
+void game_destroy(game_ctx* c) {
+  if (!c) return;
+  if (c->exec1) (void)hipGraphExecDestroy(c->exec1);
+  if (c->execC) (void)hipGraphExecDestroy(c->execC);
+  if (c->graph1) (void)hipGraphDestroy(c->graph1);
+  if (c->graphC) (void)hipGraphDestroy(c->graphC);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  delete c;
+}
+
+const char* game_status_str(game_status s) {
+  switch (s) {
+    case GAME_OK: return "GAME_OK";
+    case GAME_E_INVALID: return "GAME_E_INVALID";
+    case GAME_E_OOM: return "GAME_E_OOM";
+    case GAME_E_DEVICE: return "GAME_E_DEVICE";
+    case GAME_E_STATE: return "GAME_E_STATE";
+    case GAME_E_UNSUPPORTED: return "GAME_E_UNSUPPORTED";
+  }
+  return "unknown game_status";
+}
+
+const char* game_last_error(void) { return g_err; }
+
+}  // extern "C"

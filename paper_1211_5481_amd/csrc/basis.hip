@@ -1,0 +1,176 @@
+// Basis expansion Phi[n, i*K + k] = phi_{k+1}(x[n, i])  (eq. 1; eq. 6 for trig).
+//
+// The values are computed once per dataset, as the paper does with its sin/cos
+// tables (Sec. 4): inputs never change during training, so only the genes are
+// re-read every generation.  Each value is evaluated in double by the
+// three-term recurrences (Chebyshev, Legendre, the cos/sin multiple-angle
+// recurrence seeded by one sincos) and rounded once to the storage type
+// (bf16/f16 round the float32-rounded value).
+//
+// Layout: Phi is row-major N x ld.  A workgroup builds a block of rows in LDS
+// in any order, then the block, which is contiguous in HBM, is written with
+// 16-byte stores by consecutive lanes (fully coalesced).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "game_internal.hpp"
+
+namespace game {
+namespace {
+
+constexpr int kBasisThreads = 256;
+constexpr int kBasisLdsBytes = 32768;
+
+template <typename O>
+__device__ __forceinline__ O to_storage(double v);
+template <>
+__device__ __forceinline__ double to_storage<double>(double v) {
+  return v;
+}
+template <>
+__device__ __forceinline__ float to_storage<float>(double v) {
+  return (float)v;
+}
+template <>
+__device__ __forceinline__ _Float16 to_storage<_Float16>(double v) {
+  return (_Float16)(float)v;  // v_cvt_f16_f32 rounds to nearest even
+}
+// bf16 kept as its bit pattern; round to nearest even from the float32 value.
+struct bf16_bits {
+  uint16_t b;
+};
+template <>
+__device__ __forceinline__ bf16_bits to_storage<bf16_bits>(double v) {
+  const uint32_t u = __float_as_uint((float)v);
+  const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+  return bf16_bits{(uint16_t)(r >> 16)};
+}
+
+// All K basis values of one feature value x, written through `put(k, value)`.
+template <typename Put>
+__device__ __forceinline__ void expand(int basis, int D, double x, Put put) {
+  if (basis == GAME_BASIS_POWER) {
+    double p = x;
+    for (int k = 0; k < D; ++k) {
+      put(k, p);
+      p *= x;
+    }
+  } else if (basis == GAME_BASIS_CHEBYSHEV) {
+    double prev = 1.0, cur = x;
+    for (int k = 0; k < D; ++k) {
+      put(k, cur);
+      const double nxt = 2.0 * x * cur - prev;
+      prev = cur;
+      cur = nxt;
+    }
+  } else if (basis == GAME_BASIS_LEGENDRE) {
+    double prev = 1.0, cur = x;
+    for (int k = 0; k < D; ++k) {
+      put(k, cur);
+      const double j = (double)(k + 1);
+      const double nxt = ((2.0 * j + 1.0) * x * cur - j * prev) / (j + 1.0);
+      prev = cur;
+      cur = nxt;
+    }
+  } else {  // trig: cos(1x)..cos(Dx), sin(1x)..sin(Dx)
+    double s1, c1;
+    sincos(x, &s1, &c1);
+    double cp = 1.0, cc = c1, sp = 0.0, sc = s1;
+    for (int k = 0; k < D; ++k) {
+      put(k, cc);
+      put(D + k, sc);
+      const double cn = 2.0 * c1 * cc - cp;
+      const double sn = 2.0 * c1 * sc - sp;
+      cp = cc;
+      cc = cn;
+      sp = sc;
+      sc = sn;
+    }
+  }
+}
+
+template <typename XT, typename O>
+__global__ __launch_bounds__(kBasisThreads) void basis_kernel(const XT* __restrict__ X,
+                                                              int64_t rows_in, int64_t rows_out,
+                                                              int F, int D, int K, int basis,
+                                                              int M, int64_t ld, int rows_per_wg,
+                                                              O* __restrict__ phi) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  O* lds = reinterpret_cast<O*>(lds_raw);
+  const int64_t row0 = (int64_t)blockIdx.x * rows_per_wg;
+  if (row0 >= rows_out) return;
+  const int rows = (int)min((int64_t)rows_per_wg, rows_out - row0);
+  const int tid = threadIdx.x;
+
+  // 1) every (row, feature) pair expands into its K columns in LDS
+  for (int idx = tid; idx < rows * F; idx += kBasisThreads) {
+    const int r = idx / F, i = idx - r * F;
+    const int64_t n = row0 + r;
+    O* dst = lds + (int64_t)r * ld + (int64_t)i * K;
+    if (n < rows_in) {
+      const double x = (double)X[n * F + i];
+      expand(basis, D, x, [&](int k, double v) { dst[k] = to_storage<O>(v); });
+    } else {
+      for (int k = 0; k < K; ++k) dst[k] = to_storage<O>(0.0);
+    }
+  }
+  // pad columns M..ld-1
+  const int padw = (int)(ld - M);
+  for (int idx = tid; idx < rows * padw; idx += kBasisThreads) {
+    const int r = idx / padw, c = idx - r * padw;
+    lds[(int64_t)r * ld + M + c] = to_storage<O>(0.0);
+  }
+  __syncthreads();
+
+  // 2) the block is contiguous in global memory: coalesced stores
+  const int64_t bytes = (int64_t)rows * ld * (int64_t)sizeof(O);
+  unsigned char* gdst = reinterpret_cast<unsigned char*>(phi + row0 * ld);
+  if ((bytes & 15) == 0 && (reinterpret_cast<uintptr_t>(gdst) & 15) == 0) {
+    const int64_t n16 = bytes >> 4;
+    const uint4* s = reinterpret_cast<const uint4*>(lds_raw);
+    uint4* d = reinterpret_cast<uint4*>(gdst);
+    for (int64_t v = tid; v < n16; v += kBasisThreads) d[v] = s[v];
+  } else {
+    const int64_t n = (int64_t)rows * ld;
+    for (int64_t v = tid; v < n; v += kBasisThreads) phi[row0 * ld + v] = lds[v];
+  }
+}
+
+template <typename XT, typename O>
+hipError_t launch_typed(const game_config* cfg, const void* X, int64_t rows_in, int64_t rows_out,
+                        void* phi, int64_t ld, hipStream_t s) {
+  const int F = cfg->n_features, D = cfg->degree;
+  const int K = (cfg->basis == GAME_BASIS_TRIG ? 2 : 1) * D;
+  const int M = F * K;
+  const int64_t row_bytes = ld * (int64_t)sizeof(O);
+  int rows_per_wg = (int)(kBasisLdsBytes / row_bytes);
+  if (rows_per_wg < 1) rows_per_wg = 1;
+  if (rows_per_wg > 64) rows_per_wg = 64;
+  const size_t lds = (size_t)rows_per_wg * (size_t)row_bytes;
+  const int64_t grid = (rows_out + rows_per_wg - 1) / rows_per_wg;
+  if (grid == 0) return hipSuccess;
+  if (lds > 65536) return hipErrorInvalidValue;  // a single row larger than LDS allows
+  hipLaunchKernelGGL((basis_kernel<XT, O>), dim3((unsigned)grid), dim3(kBasisThreads), lds, s,
+                     static_cast<const XT*>(X), rows_in, rows_out, F, D, K, cfg->basis, M, ld,
+                     rows_per_wg, static_cast<O*>(phi));
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_basis(const game_config* cfg, const void* X, int64_t rows_in, int64_t rows_out,
+                        void* phi, int64_t ld, hipStream_t s) {
+  switch (cfg->dtype) {
+    case GAME_F64:
+      return launch_typed<double, double>(cfg, X, rows_in, rows_out, phi, ld, s);
+    case GAME_F32:
+      return launch_typed<float, float>(cfg, X, rows_in, rows_out, phi, ld, s);
+    case GAME_BF16:
+      return launch_typed<float, bf16_bits>(cfg, X, rows_in, rows_out, phi, ld, s);
+    case GAME_F16:
+      return launch_typed<float, _Float16>(cfg, X, rows_in, rows_out, phi, ld, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace game

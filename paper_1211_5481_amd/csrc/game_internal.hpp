@@ -1,0 +1,146 @@
+// Internal declarations of libgame: device helpers, workspace plan, launchers.
+// Not part of the public ABI (that is include/game.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "game.h"
+
+namespace game {
+
+// ---------------------------------------------------------------- constants
+constexpr int kMaxElite = 64;      // elitism limit (top-E ranking in one workgroup)
+constexpr int kMaxTournament = 16; // tournament draws addressable by the counter layout
+constexpr int kMaxGenes = 4096;    // L limit (keeps every index well inside int32)
+
+// Philox stream tags: the fourth counter word of every draw.
+enum : uint32_t {
+  kTagInit = 1,
+  kTagSel = 2,
+  kTagMut = 3,
+  kTagMut1 = 4,
+  kTagMut2 = 5,
+  kTagMut3 = 6,
+};
+
+// ------------------------------------------------- Philox4x32-10 (device)
+// Salmon et al., SC'11: ten rounds; each multiplies counter words 0 and 2 by
+// the two round multipliers, exchanges high/low product halves across the
+// counter and xors in the key; the key advances by the two Weyl increments
+// between rounds.
+struct u32x4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+    const uint32_t hi0 = __umulhi(m0, c0), lo0 = m0 * c0;
+    const uint32_t hi1 = __umulhi(m1, c2), lo1 = m1 * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return {c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint32_t word_of(const u32x4& b, int i) {
+  return i == 0 ? b.x : i == 1 ? b.y : i == 2 ? b.z : b.w;
+}
+
+// ---------------------------------------------------------- device state
+// Lives in the workspace; read and written only by kernels (and copied out
+// by game_get_state).
+struct DevState {
+  int32_t generation;      // generations completed (keys the GA draws)
+  int32_t stopped;         // a run's stop condition held
+  int32_t best_index;      // best chromosome of the last ranking
+  int32_t stop_reason;
+  int32_t run_active;      // kernels honour `stopped` only while a run is active
+  int32_t end_generation;  // run stops after evaluating generation end_generation-1
+  int32_t have_best;
+  int32_t pad;
+  double best_mse, best_fitness, best_miscls;
+  double mse_threshold;
+};
+
+// Kernels that may be skipped once a run stopped test this.
+__device__ __forceinline__ bool run_halted(const DevState* s) {
+  return s != nullptr && s->run_active && s->stopped;
+}
+
+// ----------------------------------------------------------- plan
+struct Plan {
+  int K, M, L, M_pad, P, n_off, E, P_max, k;
+  int64_t N, N_pad;
+  int tile_n, tile_p;          // fitness workgroup tile (rows x chromosomes)
+  int64_t n_rt;                // row tiles
+  int P_max_pad;               // P_max rounded up to tile_p
+  int rt_per_wg_max;           // bounds the partial buffer
+  int64_t n_rg_max;            // row groups at rt_per_wg_max... (partials rows)
+  size_t elt;                  // bytes per Phi / tile element
+  size_t acc;                  // bytes per t / bias element (8 for F64 else 4)
+  // workspace offsets
+  size_t off_phi, off_t, off_tile, off_bias, off_pop, off_next, off_psse, off_pmiss;
+  size_t off_mse, off_miscls, off_fit, off_elite, off_state, off_best, total;
+};
+
+game_status make_plan(const game_config* cfg, Plan* p, char* err, size_t errlen);
+
+// ----------------------------------------------------------- launchers
+// Each returns hipSuccess or the launch error.
+hipError_t launch_basis(const game_config* cfg, const void* X, int64_t rows_in, int64_t rows_out,
+                        void* phi, int64_t ld, hipStream_t s);
+
+hipError_t launch_copy_targets(int dtype, const void* t, int64_t N, int64_t N_pad, void* tvec,
+                               hipStream_t s);
+
+hipError_t launch_pack(int dtype, const float* genes, int P, int L, int M, int bias, int M_pad,
+                       int P_pad, void* tile, void* biasv, const DevState* st, hipStream_t s);
+
+struct FitnessGeom {
+  int n_pt;        // chromosome tiles
+  int rt_per_wg;   // row tiles per workgroup
+  int64_t n_rg;    // row groups (= partial rows)
+  int64_t n_items; // workgroups doing work
+  int64_t grid;    // launched workgroups (multiple of 8)
+};
+FitnessGeom fitness_geometry(const Plan& p, int P_eval);
+
+hipError_t launch_fitness(const Plan& p, int task, int dtype, const FitnessGeom& g, const void* phi,
+                          const void* tile, const void* biasv, const void* tvec, double* psse,
+                          uint32_t* pmiss, const DevState* st, hipStream_t s);
+
+hipError_t launch_reduce(const Plan& p, const FitnessGeom& g, int P, const double* psse,
+                         const uint32_t* pmiss, double* mse, double* miscls, double* fit,
+                         double* mse2, double* miscls2, double* fit2, const DevState* st,
+                         hipStream_t s);
+
+hipError_t launch_init_population(float* pop, int P, int L, uint64_t seed, hipStream_t s);
+
+hipError_t launch_rank(const double* fit, int P, int n_top, int* top_idx, const DevState* st,
+                       hipStream_t s);
+
+hipError_t launch_track(DevState* st, const int* top_idx, const double* mse, const double* miscls,
+                        const float* pop, int L, float* best_genes, hipStream_t s);
+
+hipError_t launch_breed(const float* pop, const double* fit, const int* elite_idx, float* next,
+                        int P, int L, int E, int n_children, int k, uint64_t thr_c,
+                        uint64_t thr_m, float sigma, uint64_t seed, const DevState* st,
+                        hipStream_t s);
+
+hipError_t launch_commit(const float* next, float* pop, int64_t count, DevState* st,
+                         hipStream_t s);
+
+hipError_t launch_state_init(DevState* st, hipStream_t s);
+hipError_t launch_run_arm(DevState* st, int max_generations, double threshold, hipStream_t s);
+hipError_t launch_run_disarm(DevState* st, hipStream_t s);
+
+}  // namespace game

@@ -1,0 +1,223 @@
+"""Python binding of libgame with the C ABI's names.
+
+PyTorch provides device memory (the workspace, inputs and outputs) and the
+stream; every step of the fitness path and of the genetic operators runs in
+the library's HIP kernels.  Nothing here computes on the CPU.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as L
+
+
+@dataclass
+class Config:
+    """Mirror of game_config (include/game.h) with readable enum values."""
+    n_patterns: int
+    n_features: int
+    degree: int = 4
+    basis: str = "chebyshev"          # power | chebyshev | legendre | trig
+    task: str = "regression"          # regression | classification
+    dtype: str = "f32"                # f64 | f32 | bf16 | f16
+    bias: int = 0
+    pop_size: int = 0                 # 0 -> B*F + 1 (eq. 4)
+    n_offspring: int = 0
+    elitism: int = 2
+    tournament_k: int = 3
+    max_generations: int = 100
+    p_crossover: float = 0.9
+    p_mutation: float = 0.05
+    mutation_sigma: float = 0.1
+    mse_threshold: float = 0.0
+    seed: int = 0
+
+    def to_c(self) -> L.GameConfig:
+        c = L.GameConfig()
+        L.lib().game_config_default(C.byref(c))
+        c.basis = L.BASIS[self.basis]
+        c.n_patterns = int(self.n_patterns)
+        c.n_features = int(self.n_features)
+        c.degree = int(self.degree)
+        c.task = L.TASK[self.task]
+        c.dtype = L.DTYPE[self.dtype]
+        c.bias = int(self.bias)
+        c.pop_size = int(self.pop_size)
+        c.n_offspring = int(self.n_offspring)
+        c.elitism = int(self.elitism)
+        c.selection = 0
+        c.tournament_k = int(self.tournament_k)
+        c.max_generations = int(self.max_generations)
+        c.p_crossover = float(self.p_crossover)
+        c.p_mutation = float(self.p_mutation)
+        c.mutation_sigma = float(self.mutation_sigma)
+        c.mse_threshold = float(self.mse_threshold)
+        c.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
+        return c
+
+    @property
+    def io_dtype(self):
+        import torch
+        return torch.float64 if self.dtype == "f64" else torch.float32
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+def query(cfg: Config) -> L.GameDims:
+    d = L.GameDims()
+    L.check(L.lib().game_query(C.byref(cfg.to_c()), C.byref(d)), "game_query")
+    return d
+
+
+def workspace_size(cfg: Config) -> int:
+    n = C.c_size_t()
+    L.check(L.lib().game_workspace_size(C.byref(cfg.to_c()), C.byref(n)), "game_workspace_size")
+    return n.value
+
+
+_STORAGE = {"f64": "float64", "f32": "float32", "bf16": "bfloat16", "f16": "float16"}
+
+
+def build_basis(cfg: Config, X, ld: Optional[int] = None, stream=None):
+    """Phi (N x ld, storage dtype) for device patterns X (N x F)."""
+    torch = _torch()
+    d = query(cfg)
+    ld = d.M if ld is None else int(ld)
+    X = X.contiguous()
+    if X.dtype != cfg.io_dtype or not X.is_cuda:
+        raise ValueError(f"X must be a {cfg.io_dtype} CUDA tensor")
+    phi = torch.empty((cfg.n_patterns, ld), dtype=getattr(torch, _STORAGE[cfg.dtype]), device=X.device)
+    L.check(L.lib().game_build_basis(C.byref(cfg.to_c()), _ptr(X), _ptr(phi), ld,
+                                     _stream_handle(stream)), "game_build_basis")
+    return phi
+
+
+class Game:
+    """A GAME training context (game_init ... game_destroy)."""
+
+    def __init__(self, cfg: Config, X, t, stream=None):
+        torch = _torch()
+        self.cfg = cfg
+        self.dims = query(cfg)
+        if X.shape != (cfg.n_patterns, cfg.n_features) or t.shape != (cfg.n_patterns,):
+            raise ValueError("X must be N x F and t must have N entries")
+        for name, a in (("X", X), ("t", t)):
+            if a.dtype != cfg.io_dtype or not a.is_cuda:
+                raise ValueError(f"{name} must be a {cfg.io_dtype} CUDA tensor")
+        self.device = X.device
+        self._stream = stream
+        self._X = X.contiguous()
+        self._t = t.contiguous()
+        self.workspace = torch.empty(self.dims.workspace_bytes + 256, dtype=torch.uint8,
+                                     device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        ctx = C.c_void_p()
+        L.check(L.lib().game_init(C.byref(cfg.to_c()), _ptr(self._X), _ptr(self._t),
+                                  self._ws_ptr, self.dims.workspace_bytes,
+                                  _stream_handle(stream), C.byref(ctx)), "game_init")
+        self._ctx = ctx
+
+    @property
+    def P(self) -> int:
+        return self.dims.P
+
+    @property
+    def L(self) -> int:
+        return self.dims.L
+
+    def eval_fitness(self, genes=None):
+        """(mse, miscls, fitness) float64 device tensors for genes (P x L) or the population."""
+        torch = _torch()
+        if genes is not None:
+            genes = genes.contiguous()
+            if genes.dtype != torch.float32 or genes.dim() != 2 or genes.shape[1] != self.L:
+                raise ValueError("genes must be a float32 P x L CUDA tensor")
+            P = genes.shape[0]
+        else:
+            P = self.P
+        out = torch.empty((3, P), dtype=torch.float64, device=self.device)
+        L.check(L.lib().game_eval_fitness(self._ctx, _ptr(genes), P, _ptr(out[0]),
+                                          _ptr(out[1]), _ptr(out[2])), "game_eval_fitness")
+        return out[0], out[1], out[2]
+
+    def step(self, fitness=None):
+        if fitness is not None:
+            fitness = fitness.contiguous()
+            if fitness.dtype != _torch().float64 or fitness.shape != (self.P,):
+                raise ValueError("fitness must be a float64 CUDA tensor of P entries")
+        L.check(L.lib().game_step(self._ctx, _ptr(fitness)), "game_step")
+
+    def advance(self, n_generations: int):
+        L.check(L.lib().game_advance(self._ctx, int(n_generations)), "game_advance")
+
+    def run(self) -> dict:
+        genes = (C.c_float * self.L)()
+        r = L.GameResult()
+        r.best_genes = C.cast(genes, C.POINTER(C.c_float))
+        L.check(L.lib().game_run(self._ctx, C.byref(r)), "game_run")
+        return dict(best_mse=r.best_mse, best_fitness=r.best_fitness, best_miscls=r.best_miscls,
+                    generations=r.generations, stop_reason=L.STOP.get(r.stop_reason),
+                    best_genes=np.frombuffer(genes, dtype=np.float32).copy())
+
+    @property
+    def population(self):
+        torch = _torch()
+        out = torch.empty((self.P, self.L), dtype=torch.float32, device=self.device)
+        L.check(L.lib().game_get_population(self._ctx, _ptr(out)), "game_get_population")
+        return out
+
+    @population.setter
+    def population(self, genes):
+        torch = _torch()
+        genes = genes.contiguous()
+        if genes.dtype != torch.float32 or tuple(genes.shape) != (self.P, self.L):
+            raise ValueError("population must be a float32 P x L CUDA tensor")
+        L.check(L.lib().game_set_population(self._ctx, _ptr(genes)), "game_set_population")
+        self._pop_keep = genes  # keep alive until the async copy has run
+
+    def state(self, with_genes: bool = False) -> dict:
+        s = L.GameState()
+        genes = (C.c_float * self.L)() if with_genes else None
+        L.check(L.lib().game_get_state(self._ctx, C.byref(s), genes), "game_get_state")
+        d = dict(generation=s.generation, stopped=bool(s.stopped), best_index=s.best_index,
+                 stop_reason=L.STOP.get(s.stop_reason), best_mse=s.best_mse,
+                 best_fitness=s.best_fitness, best_miscls=s.best_miscls)
+        if with_genes:
+            d["best_genes"] = np.frombuffer(genes, dtype=np.float32).copy()
+        return d
+
+    def time_fitness(self, reps: int = 20) -> float:
+        """Mean duration (ms) of one fitness-kernel launch over the population."""
+        ms = C.c_float()
+        L.check(L.lib().game_time_fitness(self._ctx, int(reps), C.byref(ms)), "game_time_fitness")
+        return ms.value
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            L.lib().game_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,161 @@
+"""Fitness path (basis -> MFMA contraction -> fused error reduce) against the
+float64 oracle.
+
+Tolerances (relative, on the MSE of every chromosome):
+  f64        1e-12  (double MFMA, double epilogue)
+  f32        1e-5   (float32 MFMA and epilogue; double across row tiles)
+  bf16/f16   2e-5 against the oracle evaluated on the same rounded Phi and
+             genes (isolates accumulation error); the total error against
+             the unrounded oracle is reported and only bounded loosely.
+Misclassification counts must agree except on patterns whose oracle output
+is within 1e-4 * sum|Phi G| of the decision boundary z = 0.
+"""
+import numpy as np
+import pytest
+
+from oracle import model
+import synth
+from tests.gpu_util import announce, dev, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+RTOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-5, "f16": 2e-5}
+
+
+def make_data(task, N, F, seed):
+    if task == "classification":
+        X, t = synth.classification_dataset(N, F, seed=seed)
+    else:
+        X, t, _ = synth.regression_dataset(N, F, 3, 0.05, seed=seed)
+    return X, t
+
+
+def oracle_inputs(X, t, G, dtype):
+    """The exact values the device sees: inputs cast to the I/O type."""
+    if dtype == "f64":
+        return X, t, G.astype(np.float64)
+    return (X.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64),
+            G.astype(np.float32).astype(np.float64))
+
+
+def check_against_oracle(X, t, G, basis, D, task, bias, dtype, mse, miscls, fit, label=""):
+    Xo, to, Go = oracle_inputs(X, t, G, dtype)
+    Phi = model.design_matrix(Xo, basis, D)
+    M = Phi.shape[1]
+    if dtype in ("bf16", "f16"):
+        Phi_r = model.quantize(Phi, dtype)
+        G_r = Go.copy()
+        G_r[:, :M] = model.quantize(Go[:, :M], dtype)
+        ref = model.evaluate(Xo, to, G_r, basis, D, task, bias, Phi=Phi_r)
+        total = model.evaluate(Xo, to, Go, basis, D, task, bias, Phi=Phi)
+        rel_total = np.max(np.abs(mse - total["mse"]) / np.abs(total["mse"]))
+        print(f"{label} {dtype}: max rel error of mse vs unrounded float64 oracle = {rel_total:.3e}")
+        assert rel_total < (5e-2 if dtype == "bf16" else 1e-2)
+    else:
+        ref = model.evaluate(Xo, to, Go, basis, D, task, bias, Phi=Phi)
+    np.testing.assert_allclose(mse, ref["mse"], rtol=RTOL[dtype], atol=0, err_msg=label)
+    np.testing.assert_allclose(fit, 1.0 - mse, rtol=0, atol=0)
+    N = len(t)
+    if task == "classification":
+        z = ref["z"]
+        scale = np.abs(Phi) @ np.abs(G_r[:, :M] if dtype in ("bf16", "f16") else Go[:, :M]).T
+        near = np.abs(z) <= 1e-4 * np.maximum(scale, 1e-300)
+        cnt_ref = np.round(ref["miscls"] * N)
+        cnt_got = np.round(miscls * N)
+        assert np.all(np.abs(cnt_got - cnt_ref) <= near.sum(axis=0)), label
+    else:
+        assert np.all(miscls == 0.0)
+
+
+CASES = [
+    # basis, dtype, task, bias, N, F, D, P
+    ("chebyshev", "f64", "regression", 0, 1000, 8, 4, 20),
+    ("power", "f64", "classification", 1, 333, 4, 2, 65),
+    ("trig", "f32", "classification", 0, 3001, 10, 6, 300),
+    ("legendre", "f32", "regression", 1, 777, 5, 3, 129),
+    ("chebyshev", "f32", "regression", 0, 1, 2, 2, 3),
+    ("chebyshev", "f32", "classification", 0, 129, 3, 3, 1),
+    ("legendre", "bf16", "classification", 0, 2049, 16, 8, 257),
+    ("legendre", "f16", "classification", 0, 2049, 16, 8, 257),
+    ("trig", "bf16", "regression", 1, 1500, 10, 6, 200),
+    ("chebyshev", "f16", "regression", 0, 500, 3, 5, 31),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(map(str, c)))
+def test_fitness_matches_oracle(case):
+    torch = require_gpu()
+    from paper_1211_5481_amd import Config, Game
+    basis, dtype, task, bias, N, F, D, P = case
+    X, t = make_data(task, N, F, seed=N + F)
+    cfg = Config(n_patterns=N, n_features=F, degree=D, basis=basis, task=task, dtype=dtype,
+                 bias=bias, pop_size=P, elitism=min(2, P), seed=5)
+    io = cfg.io_dtype
+    announce(f"fitness {case}")
+    g = Game(cfg, dev(X, io), dev(t, io))
+    G = synth.random_population(P, g.L, seed=P)
+    mse, miscls, fit = (host(a) for a in g.eval_fitness(dev(G, torch.float32)))
+    check_against_oracle(X, t, G, basis, D, task, bias, dtype, mse, miscls, fit, label=str(case))
+    # the population the library drew itself, through the genes=NULL path
+    pop = host(g.population)
+    mse2, miscls2, fit2 = (host(a) for a in g.eval_fitness())
+    check_against_oracle(X, t, pop, basis, D, task, bias, dtype, mse2, miscls2, fit2, label="pop")
+    # bit-reproducible
+    again = host(g.eval_fitness()[0])
+    assert np.array_equal(again.view(np.uint64), mse2.view(np.uint64))
+    g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_special_chromosomes(dtype):
+    torch = require_gpu()
+    from paper_1211_5481_amd import Config, Game
+    N, F, D = 1000, 4, 3
+    X, t = synth.classification_dataset(N, F, seed=21)
+    cfg = Config(n_patterns=N, n_features=F, degree=D, basis="chebyshev", task="classification",
+                 dtype=dtype, pop_size=16)
+    g = Game(cfg, dev(X, cfg.io_dtype), dev(t, cfg.io_dtype))
+    G = np.zeros((3, g.L), dtype=np.float32)
+    announce(f"special chromosomes {dtype}")
+    mse, miscls, _ = (host(a) for a in g.eval_fitness(dev(G, torch.float32)))
+    assert np.all(mse == 0.25)                       # sigmoid(0) = 1/2 on every pattern
+    assert np.all(miscls == np.mean(t == 0.0))       # z = 0 predicts class 1
+    g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_workload_c2_full_size_sampled(dtype):
+    """100k patterns, 10 features, trig D=6, P=1000, sigmoid: the benchmarked shape."""
+    torch = require_gpu()
+    from paper_1211_5481_amd import Config, Game
+    N, F, D, P = 100_000, 10, 6, 1000
+    X, t = synth.classification_dataset(N, F, seed=synth.data_seed(2))
+    cfg = Config(n_patterns=N, n_features=F, degree=D, basis="trig", task="classification",
+                 dtype=dtype, pop_size=P, seed=synth.ga_seed(2))
+    announce(f"c2 full size {dtype}")
+    g = Game(cfg, dev(X, torch.float32), dev(t, torch.float32))
+    mse, miscls, fit = (host(a) for a in g.eval_fitness())
+    pop = host(g.population)
+    idx = np.concatenate([np.random.default_rng(2).choice(P, 62, replace=False), [0, P - 1]])
+    check_against_oracle(X, t, pop[idx], "trig", D, "classification", 0, dtype, mse[idx],
+                         miscls[idx], fit[idx], label="c2")
+    g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_workload_c3_full_size_sampled(dtype):
+    """1M patterns, 16 features, Legendre D=8 (128 genes), P=2048."""
+    torch = require_gpu()
+    from paper_1211_5481_amd import Config, Game
+    N, F, D, P = 1_000_000, 16, 8, 2048
+    X, t = synth.classification_dataset(N, F, seed=synth.data_seed(3))
+    cfg = Config(n_patterns=N, n_features=F, degree=D, basis="legendre", task="classification",
+                 dtype=dtype, pop_size=P, seed=synth.ga_seed(3))
+    announce(f"c3 full size {dtype}")
+    g = Game(cfg, dev(X, torch.float32), dev(t, torch.float32))
+    mse, miscls, fit = (host(a) for a in g.eval_fitness())
+    pop = host(g.population)
+    idx = np.array([0, 1, 777, P - 1])
+    check_against_oracle(X, t, pop[idx], "legendre", D, "classification", 0, dtype, mse[idx],
+                         miscls[idx], fit[idx], label="c3")
+    g.close()

@@ -1,0 +1,84 @@
+"""Device genetic operators against the oracle, bit for bit, given the same
+fitness vector (the Philox counter layout and the float32 mutation arithmetic
+fix every decision and every gene)."""
+import numpy as np
+import pytest
+
+from oracle import ga
+import synth
+from tests.gpu_util import announce, dev, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def bits(a):
+    return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+
+
+def make_game(P, L_genes, E=2, k=3, pc=0.9, pm=0.05, sigma=0.1, seed=99):
+    torch = require_gpu()
+    from paper_1211_5481_amd import Config, Game
+    # L genes = F * D with the power basis and D = 1 (bias adds one)
+    cfg = Config(n_patterns=64, n_features=L_genes, degree=1, basis="power", dtype="f32",
+                 pop_size=P, elitism=E, tournament_k=k, p_crossover=pc, p_mutation=pm,
+                 mutation_sigma=sigma, seed=seed)
+    X = np.random.default_rng(0).uniform(-1, 1, (64, L_genes))
+    t = np.zeros(64)
+    return Game(cfg, dev(X, torch.float32), dev(t, torch.float32)), cfg
+
+
+@pytest.mark.parametrize("P,L", [(20, 32), (1000, 120), (2048, 128), (7, 1)])
+def test_init_population_bit_exact(P, L):
+    announce(f"init population P={P} L={L}")
+    g, cfg = make_game(P, L, E=min(2, P), seed=12345678901)
+    got = host(g.population)
+    want = ga.init_population(P, L, cfg.seed)
+    assert np.array_equal(bits(got), bits(want))
+    g.close()
+
+
+STEP_CASES = [
+    # P, L, E, k, p_c, p_m, sigma
+    (20, 32, 2, 3, 0.9, 0.05, 0.1),
+    (21, 7, 2, 3, 0.9, 0.05, 0.1),      # odd number of children
+    (8, 1, 1, 3, 0.9, 0.2, 0.3),        # one gene: no crossover point
+    (16, 12, 0, 1, 1.0, 1.0, 0.5),      # no elitism, k = 1, every gene mutates
+    (5, 9, 5, 3, 0.9, 0.05, 0.1),       # all elites, no children
+    (33, 40, 3, 16, 0.5, 0.2, 2.0),     # four Philox blocks per tournament, heavy clamping
+    (1000, 120, 2, 3, 0.9, 0.05, 0.1),  # 100k-pattern classification workload shape
+    (2048, 128, 2, 3, 0.9, 0.05, 0.1),  # 1M-pattern Legendre workload shape
+]
+
+
+@pytest.mark.parametrize("case", STEP_CASES, ids=lambda c: "-".join(map(str, c)))
+def test_step_bit_exact_over_generations(case):
+    torch = require_gpu()
+    P, L, E, k, pc, pm, sigma = case
+    seed = 424242 + P
+    g, cfg = make_game(P, L, E, k, pc, pm, sigma, seed=seed)
+    pop = host(g.population)
+    for gen in range(3):
+        fit = synth.random_fitness(P, seed=gen + P, n_ties=P // 4, n_nan=1 if P > 4 else 0)
+        announce(f"step {case} generation {gen}")
+        g.step(dev(fit, torch.float64))
+        got = host(g.population)
+        want = ga.ga_step(pop, fit, gen, seed, elitism=E, k=k, p_crossover=pc, p_mutation=pm,
+                          sigma=sigma)
+        bad = np.argwhere(bits(got) != bits(want))
+        assert bad.size == 0, f"generation {gen}: first mismatches {bad[:5].tolist()}"
+        assert g.state()["generation"] == gen + 1
+        pop = want
+    g.close()
+
+
+def test_step_after_eval_uses_internal_fitness():
+    torch = require_gpu()
+    g, cfg = make_game(40, 16, seed=3)
+    pop = host(g.population)
+    mse, _, fit = g.eval_fitness()
+    fit_h = host(fit)
+    announce("step(NULL) after eval(NULL)")
+    g.step()
+    want = ga.ga_step(pop, fit_h, 0, cfg.seed)
+    assert np.array_equal(bits(host(g.population)), bits(want))
+    g.close()
