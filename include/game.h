@@ -11,9 +11,11 @@
  *   - a chromosome holds one coefficient (gene) per basis column, plus an
  *     optional constant a_0 stored last (L = M or M + 1 genes), and its output
  *     on pattern n is z = sum_m Phi[n, m] G[m] (+ a_0)  (eq. 2);
- *   - the error of a pattern is (t - out)^2 (eq. 3) with out = z (regression)
- *     or the logistic sigmoid of z (classification); a chromosome's error is
- *     the mean over all patterns (MSE) and its fitness is 1 - MSE;
+ *   - the error of a pattern is (t - z)^2 for regression and
+ *     (l - sigmoid(z))^2 for classification, l = [t >= 0.5] the class label
+ *     (eq. 3 with the logistic output); a chromosome's error is the mean over
+ *     all patterns (MSE) and its fitness is 1 - MSE; a pattern counts as
+ *     misclassified when [z >= 0] differs from l;
  *   - a generation applies elitism, tournament selection, one-point
  *     crossover and Gaussian mutation, with genes kept in [-1, 1] (Sec. 3
  *     operator list; Sec. 5 rates), every random draw coming from a

@@ -21,8 +21,9 @@ Readings taken where the paper is silent (each listed in the design notes):
   * trigonometric columns of a feature are cos(1x)..cos(Dx) then
     sin(1x)..sin(Dx), following the serial loop of Sec. 4 (coefficient j
     multiplies cos, coefficient j + d multiplies sin);
-  * classification maps the output through the logistic sigmoid, targets are
-    {0, 1}, and a pattern is predicted class 1 iff z >= 0; for regression the
+  * classification maps the output through the logistic sigmoid and compares
+    it with the class label l = [t >= 0.5] (t itself for 0/1 targets); a
+    pattern is predicted class 1 iff z >= 0; for regression the
     misclassification rate is reported as 0.
 """
 from __future__ import annotations
@@ -136,17 +137,20 @@ def evaluate(X, t, G, basis: str, degree: int, task: str = "regression",
     """Fitness of every chromosome (row of G) over all patterns.
 
     Returns dict(mse, miscls, fitness, z):
-      out     = z (regression) or sigmoid(z) (classification)
-      mse[p]  = mean_n (t_n - out[n, p])^2        (eq. 3, then MSE)
+      regression:     err = (t_n - z)^2
+      classification: err = (l_n - sigmoid(z))^2,  l_n = [t_n >= 0.5]
+      mse[p]  = mean_n err[n, p]                  (eq. 3, then MSE)
       fitness = 1 - mse                           (complement of the error)
-      miscls  = mean_n [(z >= 0) != (t_n >= 0.5)] (classification only, else 0)
+      miscls  = mean_n [(z >= 0) != l_n]          (classification only, else 0)
     """
     if task not in TASKS:
         raise ValueError(f"unknown task {task!r}")
     t = np.asarray(t, dtype=np.float64)
     z = pattern_output(X, G, basis, degree, bias, Phi)
-    out = sigmoid(z) if task == "classification" else z
-    err = (t[:, None] - out) ** 2
+    if task == "classification":
+        err = ((t >= 0.5).astype(np.float64)[:, None] - sigmoid(z)) ** 2
+    else:
+        err = (t[:, None] - z) ** 2
     mse = err.mean(axis=0)
     if task == "classification":
         miscls = ((z >= 0.0) != (t[:, None] >= 0.5)).mean(axis=0)

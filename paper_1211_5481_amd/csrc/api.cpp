@@ -45,14 +45,15 @@ struct game_ctx {
   hipGraph_t graph1 = nullptr, graphC = nullptr;
   unsigned char* ws = nullptr;
   void *phi, *tvec, *tile, *biasv;
-  float *pop, *next, *best;
+  float *pop0, *pop1, *best;  // generation g lives in pop[g & 1]
   double *psse, *mse, *miscls, *fit;
-  uint32_t* pmiss;
+  uint32_t *pmiss, *counters;
   int* elite;
   DevState* state;
   uint64_t thr_c, thr_m;
   bool poisoned = false;
-  bool have_eval = false;
+  bool have_eval = false;   // elites/fitness of the current population are known
+  bool tile_fresh = false;  // the gene tile holds the current population
 };
 
 namespace game {
@@ -120,8 +121,8 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   p->off_t = take((size_t)p->N_pad * p->acc);
   p->off_tile = take((size_t)p->P_max_pad * p->M_pad * p->elt);
   p->off_bias = take((size_t)p->P_max_pad * p->acc);
-  p->off_pop = take((size_t)P * L * 4);
-  p->off_next = take((size_t)P * L * 4);
+  p->off_pop0 = take((size_t)P * L * 4);
+  p->off_pop1 = take((size_t)P * L * 4);
   p->off_psse = take((size_t)p->n_rg_max * p->P_max_pad * 8);
   p->off_pmiss = take((size_t)p->n_rg_max * p->P_max_pad * 4);
   p->off_mse = take((size_t)p->P_max * 8);
@@ -130,13 +131,28 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   p->off_elite = take(kMaxElite * 4);
   p->off_state = take(sizeof(DevState));
   p->off_best = take((size_t)L * 4);
+  p->n_pt_cap = p->P_max_pad / p->tile_p;
+  p->off_cnt = take((size_t)(p->n_pt_cap + 2) * 4);
   p->total = off;
   return GAME_OK;
 }
 
-FitnessGeom fitness_geometry(const Plan& p, int P_eval) {
+FitnessGeom fitness_geometry(const Plan& p, int task, int dtype, int P_eval) {
   FitnessGeom g;
   g.n_pt = (P_eval + p.tile_p - 1) / p.tile_p;
+  const int slots = fitness_persistent_slots(p, task, dtype);
+  if (slots > 0) {
+    // persistent: one workgroup per (row range, chromosome tile), as many as are resident
+    int64_t R = slots / g.n_pt;
+    if (R < 1) R = 1;
+    if (R > p.n_rt) R = p.n_rt;
+    if (R > p.n_rg_max) R = p.n_rg_max;
+    g.rt_per_wg = 0;
+    g.n_rg = R;
+    g.n_items = R * g.n_pt;
+    g.grid = (g.n_items + 7) / 8 * 8;
+    return g;
+  }
   // Enough workgroups to fill 256 CUs many times over, few enough that the
   // partial sums stay small next to the Phi traffic.
   const int64_t target = 8192;
@@ -172,46 +188,86 @@ game_status dev(game_ctx* ctx, hipError_t e, const char* what) {
     if (_s != GAME_OK) return _s;        \
   } while (0)
 
-// pack -> fitness -> reduce for P_eval chromosomes in `genes`.
-game_status enqueue_eval(game_ctx* c, const float* genes, int P_eval, double* mse, double* miscls,
-                         double* fit, double* mse2, double* miscls2, double* fit2,
-                         const DevState* st, hipStream_t s) {
+FitTail make_tail(game_ctx* c, int P_eval, bool population, double* mse2, double* miscls2,
+                  double* fit2) {
   const Plan& p = c->plan;
-  const FitnessGeom g = fitness_geometry(p, P_eval);
+  FitTail t{};
+  t.counters = c->counters;
+  t.n_pt_cap = p.n_pt_cap;
+  t.P = P_eval;
+  t.invN = 1.0 / (double)p.N;
+  t.mse2 = mse2;
+  t.miscls2 = miscls2;
+  t.fit2 = fit2;
+  if (population) {
+    t.mse = c->mse;
+    t.miscls = c->miscls;
+    t.fit = c->fit;
+    t.n_top = p.E > 0 ? p.E : 1;
+    t.top = c->elite;
+    t.st = c->state;
+    t.pop0 = c->pop0;
+    t.pop1 = c->pop1;
+    t.L = p.L;
+    t.best = c->best;
+  }
+  return t;
+}
+
+game_status enqueue_pack_population(game_ctx* c, hipStream_t s) {
+  const Plan& p = c->plan;
   GAME_TRY(dev(c,
-               launch_pack(c->cfg.dtype, genes, P_eval, p.L, p.M, c->cfg.bias, p.M_pad,
-                           g.n_pt * p.tile_p, c->tile, c->biasv, st, s),
+               launch_pack(c->cfg.dtype, c->pop0, c->pop1, c->state, p.P, p.L, p.M, c->cfg.bias,
+                           p.M_pad, p.P_max_pad, c->tile, c->biasv, s),
                "pack"));
-  GAME_TRY(dev(c,
-               launch_fitness(p, c->cfg.task, c->cfg.dtype, g, c->phi, c->tile,
-                              c->cfg.bias ? c->biasv : nullptr, c->tvec, c->psse, c->pmiss, st, s),
-               "fitness"));
-  GAME_TRY(dev(c,
-               launch_reduce(p, g, P_eval, c->psse, c->pmiss, mse, miscls, fit, mse2, miscls2,
-                             fit2, st, s),
-               "reduce"));
+  c->tile_fresh = true;
   return GAME_OK;
+}
+
+// Fitness of P_eval chromosomes (the gene tile must already hold them); the
+// kernel's tail reduces, and for the population also ranks and tracks.
+game_status enqueue_fitness(game_ctx* c, int P_eval, const FitTail& tail, hipStream_t s) {
+  const Plan& p = c->plan;
+  const FitnessGeom g = fitness_geometry(p, c->cfg.task, c->cfg.dtype, P_eval);
+  return dev(c,
+             launch_fitness(p, c->cfg.task, c->cfg.dtype, g, c->phi, c->tile,
+                            c->cfg.bias ? c->biasv : nullptr, c->tvec, c->psse, c->pmiss,
+                            c->state, tail, s),
+             "fitness");
 }
 
 // Evaluate the current population, rank it and track the best chromosome.
 game_status enqueue_eval_population(game_ctx* c, double* mse, double* miscls, double* fit,
                                     hipStream_t s) {
-  const Plan& p = c->plan;
-  GAME_TRY(enqueue_eval(c, c->pop, p.P, c->mse, c->miscls, c->fit, mse, miscls, fit, c->state, s));
-  const int n_top = p.E > 0 ? p.E : 1;
-  GAME_TRY(dev(c, launch_rank(c->fit, p.P, n_top, c->elite, c->state, s), "rank"));
-  GAME_TRY(dev(c, launch_track(c->state, c->elite, c->mse, c->miscls, c->pop, p.L, c->best, s),
-               "track"));
-  return GAME_OK;
+  if (!c->tile_fresh) GAME_TRY(enqueue_pack_population(c, s));
+  return enqueue_fitness(c, c->plan.P, make_tail(c, c->plan.P, true, mse, miscls, fit), s);
 }
 
 game_status enqueue_evolve(game_ctx* c, const double* fit, hipStream_t s) {
   const Plan& p = c->plan;
-  GAME_TRY(dev(c,
-               launch_breed(c->pop, fit, c->elite, c->next, p.P, p.L, p.E, p.n_off, p.k, c->thr_c,
-                            c->thr_m, (float)c->cfg.mutation_sigma, c->cfg.seed, c->state, s),
-               "breed"));
-  GAME_TRY(dev(c, launch_commit(c->next, c->pop, (int64_t)p.P * p.L, c->state, s), "commit"));
+  BreedArgs a{};
+  a.pop0 = c->pop0;
+  a.pop1 = c->pop1;
+  a.fit = fit;
+  a.elite = c->elite;
+  a.P = p.P;
+  a.L = p.L;
+  a.E = p.E;
+  a.n_children = p.n_off;
+  a.k = p.k;
+  a.thr_c = c->thr_c;
+  a.thr_m = c->thr_m;
+  a.sigma = (float)c->cfg.mutation_sigma;
+  a.k0 = (uint32_t)c->cfg.seed;
+  a.k1 = (uint32_t)(c->cfg.seed >> 32);
+  a.tile = c->tile;
+  a.biasv = c->biasv;
+  a.M = p.M;
+  a.M_pad = p.M_pad;
+  a.bias = c->cfg.bias;
+  a.counter = c->counters + p.n_pt_cap + 1;
+  GAME_TRY(dev(c, launch_breed(c->cfg.dtype, a, c->state, s), "breed"));
+  c->tile_fresh = true;  // breed writes the new population into the tile
   return GAME_OK;
 }
 
@@ -226,6 +282,7 @@ game_status build_graph(game_ctx* c, int n_gen, hipGraph_t* graph, hipGraphExec_
   if (!c->cap) GAME_TRY(dev(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking), "stream create"));
   GAME_TRY(dev(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "begin capture"));
   game_status st = GAME_OK;
+  c->tile_fresh = true;  // callers pack the population before replaying the graph
   for (int i = 0; i < n_gen && st == GAME_OK; ++i) st = enqueue_generation(c, c->cap);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->cap, &g);
@@ -334,8 +391,9 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
   c->tvec = c->ws + p.off_t;
   c->tile = c->ws + p.off_tile;
   c->biasv = c->ws + p.off_bias;
-  c->pop = reinterpret_cast<float*>(c->ws + p.off_pop);
-  c->next = reinterpret_cast<float*>(c->ws + p.off_next);
+  c->pop0 = reinterpret_cast<float*>(c->ws + p.off_pop0);
+  c->pop1 = reinterpret_cast<float*>(c->ws + p.off_pop1);
+  c->counters = reinterpret_cast<uint32_t*>(c->ws + p.off_cnt);
   c->psse = reinterpret_cast<double*>(c->ws + p.off_psse);
   c->pmiss = reinterpret_cast<uint32_t*>(c->ws + p.off_pmiss);
   c->mse = reinterpret_cast<double*>(c->ws + p.off_mse);
@@ -350,8 +408,9 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
   game_status r = GAME_OK;
   if (r == GAME_OK) r = dev(c, launch_basis(cfg, X, p.N, p.N_pad, c->phi, p.M_pad, st), "basis");
   if (r == GAME_OK) r = dev(c, launch_copy_targets(cfg->dtype, t, p.N, p.N_pad, c->tvec, st), "targets");
-  if (r == GAME_OK) r = dev(c, launch_init_population(c->pop, p.P, p.L, cfg->seed, st), "init population");
-  if (r == GAME_OK) r = dev(c, launch_state_init(c->state, st), "state init");
+  if (r == GAME_OK) r = dev(c, launch_init_population(c->pop0, p.P, p.L, cfg->seed, st), "init population");
+  if (r == GAME_OK) r = dev(c, launch_state_init(c->state, c->counters, p.n_pt_cap + 2, st), "state init");
+  if (r == GAME_OK) r = enqueue_pack_population(c, st);
   if (r != GAME_OK) {
     delete c;
     return r;
@@ -370,7 +429,14 @@ game_status game_eval_fitness(game_ctx* c, const float* genes, int32_t P, double
     return GAME_OK;
   }
   if (P < 1 || P > c->plan.P_max) return fail(GAME_E_INVALID, "P must be in [1, %d]", c->plan.P_max);
-  return enqueue_eval(c, genes, P, mse, miscls, fit, nullptr, nullptr, nullptr, nullptr, c->stream);
+  const Plan& p = c->plan;
+  const int P_pad = (P + p.tile_p - 1) / p.tile_p * p.tile_p;
+  c->tile_fresh = false;
+  GAME_TRY(dev(c,
+               launch_pack(c->cfg.dtype, genes, nullptr, nullptr, P, p.L, p.M, c->cfg.bias, p.M_pad,
+                           P_pad, c->tile, c->biasv, c->stream),
+               "pack"));
+  return enqueue_fitness(c, P, make_tail(c, P, false, mse, miscls, fit), c->stream);
 }
 
 game_status game_step(game_ctx* c, const double* fit) {
@@ -394,6 +460,7 @@ game_status game_advance(game_ctx* c, int32_t n) {
   if (n == 0) return GAME_OK;
   if (n >= kChunk) GAME_TRY(build_graph(c, kChunk, &c->graphC, &c->execC));
   if (n % kChunk) GAME_TRY(build_graph(c, 1, &c->graph1, &c->exec1));
+  GAME_TRY(enqueue_pack_population(c, c->stream));
   for (int i = 0; i + kChunk <= n; i += kChunk)
     GAME_TRY(dev(c, hipGraphLaunch(c->execC, c->stream), "graph launch"));
   for (int i = 0; i < n % kChunk; ++i) GAME_TRY(dev(c, hipGraphLaunch(c->exec1, c->stream), "graph launch"));
@@ -424,6 +491,7 @@ game_status game_run(game_ctx* c, game_result* res) {
   if (!res) return fail(GAME_E_INVALID, "result is NULL");
   const int G = c->cfg.max_generations;
   GAME_TRY(build_graph(c, kChunk, &c->graphC, &c->execC));
+  if (!c->tile_fresh) GAME_TRY(enqueue_pack_population(c, c->stream));
   game_state s0;
   GAME_TRY(game_get_state(c, &s0, nullptr));
   GAME_TRY(dev(c, launch_run_arm(c->state, G, c->cfg.mse_threshold, c->stream), "arm"));
@@ -449,35 +517,28 @@ game_status game_run(game_ctx* c, game_result* res) {
 game_status game_get_population(game_ctx* c, float* genes) {
   GAME_TRY(check_ctx(c));
   if (!genes) return fail(GAME_E_INVALID, "genes is NULL");
-  return dev(c, hipMemcpyAsync(genes, c->pop, (size_t)c->plan.P * c->plan.L * 4, hipMemcpyDeviceToDevice, c->stream), "population copy");
+  return dev(c, launch_pop_copy(c->pop0, c->pop1, c->state, genes, (int64_t)c->plan.P * c->plan.L, 0, c->stream), "population copy");
 }
 
 game_status game_set_population(game_ctx* c, const float* genes) {
   GAME_TRY(check_ctx(c));
   if (!genes) return fail(GAME_E_INVALID, "genes is NULL");
   c->have_eval = false;
-  return dev(c, hipMemcpyAsync(c->pop, genes, (size_t)c->plan.P * c->plan.L * 4, hipMemcpyDeviceToDevice, c->stream), "population copy");
+  c->tile_fresh = false;
+  return dev(c, launch_pop_copy(c->pop0, c->pop1, c->state, const_cast<float*>(genes), (int64_t)c->plan.P * c->plan.L, 1, c->stream), "population copy");
 }
 
 game_status game_time_fitness(game_ctx* c, int32_t reps, float* ms) {
   GAME_TRY(check_ctx(c));
   if (reps < 1 || !ms) return fail(GAME_E_INVALID, "reps must be >= 1 and ms non-NULL");
   const Plan& p = c->plan;
-  const FitnessGeom g = fitness_geometry(p, p.P);
-  GAME_TRY(dev(c,
-               launch_pack(c->cfg.dtype, c->pop, p.P, p.L, p.M, c->cfg.bias, p.M_pad,
-                           g.n_pt * p.tile_p, c->tile, c->biasv, nullptr, c->stream),
-               "pack"));
+  if (!c->tile_fresh) GAME_TRY(enqueue_pack_population(c, c->stream));
+  const FitTail tail = make_tail(c, p.P, false, nullptr, nullptr, nullptr);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   GAME_TRY(dev(c, hipEventCreate(&e0), "event create"));
   game_status s = dev(c, hipEventCreate(&e1), "event create");
   if (s == GAME_OK) s = dev(c, hipEventRecord(e0, c->stream), "event record");
-  for (int r = 0; r < reps && s == GAME_OK; ++r)
-    s = dev(c,
-            launch_fitness(p, c->cfg.task, c->cfg.dtype, g, c->phi, c->tile,
-                           c->cfg.bias ? c->biasv : nullptr, c->tvec, c->psse, c->pmiss, nullptr,
-                           c->stream),
-            "fitness");
+  for (int r = 0; r < reps && s == GAME_OK; ++r) s = enqueue_fitness(c, p.P, tail, c->stream);
   if (s == GAME_OK) s = dev(c, hipEventRecord(e1, c->stream), "event record");
   if (s == GAME_OK) s = dev(c, hipEventSynchronize(e1), "event synchronize");
   float total = 0.f;

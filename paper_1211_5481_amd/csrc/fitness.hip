@@ -2,8 +2,9 @@
 //
 // For every chromosome p and pattern n (eq. 2 and 3):
 //   z[n,p]  = sum_m Phi[n,m] G[p,m] (+ a_0 of p)
-//   e[n,p]  = (t_n - out)^2,  out = z (regression) or 1/(1+exp(-z)) (classification)
-//   miss    = [(z >= 0) != (t_n >= 0.5)]            (classification)
+//   e[n,p]  = (t_n - z)^2                    (regression)
+//           = (l_n - 1/(1+exp(-z)))^2        (classification, label l_n = [t_n >= 0.5])
+//   miss    = [(z >= 0) != l_n]              (classification)
 // and per chromosome sse = sum_n e, misses = sum_n miss, reduced to
 // mse = sse / N and fitness = 1 - mse by reduce_kernel.
 //
@@ -28,7 +29,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "game_internal.hpp"
+#include "select.hpp"
 
 namespace game {
 namespace {
@@ -49,10 +53,10 @@ struct F32Tr {
   using Ld = float2;                  // 2 k-steps of 16x16x4
   static constexpr int kBlk = 8;      // Phi columns per K-block
   static constexpr int kPerLane = 2;  // contiguous elements a lane loads per K-block
+  static constexpr int kSteps = 2;    // MFMAs per K-block
+  template <int S>
   __device__ static AccV mma(const Ld& a, const Ld& b, AccV c) {
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, c, 0, 0, 0);
-    return c;
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(S == 0 ? a.x : a.y, S == 0 ? b.x : b.y, c, 0, 0, 0);
   }
 };
 
@@ -64,10 +68,10 @@ struct F64Tr {
   using Ld = double2;
   static constexpr int kBlk = 8;
   static constexpr int kPerLane = 2;
+  static constexpr int kSteps = 2;
+  template <int S>
   __device__ static AccV mma(const Ld& a, const Ld& b, AccV c) {
-    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, c, 0, 0, 0);
-    return c;
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(S == 0 ? a.x : a.y, S == 0 ? b.x : b.y, c, 0, 0, 0);
   }
 };
 
@@ -79,6 +83,8 @@ struct BF16Tr {
   using Ld = uint4;    // 8 x bf16
   static constexpr int kBlk = 32;
   static constexpr int kPerLane = 8;
+  static constexpr int kSteps = 1;
+  template <int S>
   __device__ static AccV mma(const Ld& a, const Ld& b, AccV c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
                                                    __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
@@ -93,24 +99,118 @@ struct F16Tr {
   using Ld = uint4;    // 8 x f16
   static constexpr int kBlk = 32;
   static constexpr int kPerLane = 8;
+  static constexpr int kSteps = 1;
+  template <int S>
   __device__ static AccV mma(const Ld& a, const Ld& b, AccV c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a),
                                                   __builtin_bit_cast(v8h, b), c, 0, 0, 0);
   }
 };
 
-__device__ __forceinline__ float sigmoid_acc(float z) {
-  // 1 / (1 + 2^(-z log2 e)); v_exp_f32 and v_rcp_f32 (about 1 ulp each)
-  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-z * 1.4426950408889634f));
+// Classification error of one pattern, (l - sigmoid(z))^2 with the class label
+// l in {0, 1}, written as sigmoid(s z)^2 with s = +1 for l = 0 and -1 for
+// l = 1:  r = 1 / (1 + 2^(c z)),  c = -s log2(e),  error = r^2.  One exp and
+// one reciprocal (v_exp_f32 / v_rcp_f32, about 1 ulp each).
+constexpr double kLog2e = 1.4426950408889634;
+__device__ __forceinline__ float sig_pos(float cz) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(cz));
 }
-__device__ __forceinline__ double sigmoid_acc(double z) { return 1.0 / (1.0 + exp(-z)); }
+__device__ __forceinline__ double sig_pos(double cz) { return 1.0 / (1.0 + exp2(cz)); }
+
+// Misclassification test by floating-point class: for label 0 a pattern is
+// missed when z >= 0 (+-0, positive denormal/normal/inf), for label 1 when
+// z < 0 or z is NaN; padding rows use an empty class mask.
+constexpr int kMissIfLabel0 = 0x3E0;  // -0, +0, +denorm, +normal, +inf
+constexpr int kMissIfLabel1 = 0x01F;  // sNaN, qNaN, -inf, -normal, -denorm
+__device__ __forceinline__ bool in_class(float z, int mask) { return __builtin_amdgcn_classf(z, mask); }
+__device__ __forceinline__ bool in_class(double z, int mask) { return __builtin_amdgcn_class(z, mask); }
+
+// Tail shared by both fitness kernels (all 256 threads call it after their
+// partial row is written).  The last workgroup of chromosome tile pt (atomic
+// arrival count) adds that tile's partial rows in a fixed order: 256 / TP
+// contiguous segments of row groups, each summed in row order, then the
+// segments in order.  For a population evaluation the last tile to finish
+// ranks the population and tracks the best chromosome.  Counters return to
+// zero, so the kernel can be replayed from a graph.
+template <int TP>
+__device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, int part_ld,
+                             const double* psse, const uint32_t* pmiss) {
+  constexpr int S = 256 / TP;
+  __shared__ int s_flag;
+  __shared__ double s_red[256];
+  __shared__ uint64_t s_redm[256];
+  // the partial row was stored at agent scope; order it before the arrival
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) s_flag = atomicAdd(&t.counters[pt], 1u) == (uint32_t)(n_rg - 1);
+  __syncthreads();
+  if (!s_flag) return;
+  const int c = threadIdx.x % TP, seg = threadIdx.x / TP;
+  const int p = pt * TP + c;
+  const int64_t chunk = (n_rg + S - 1) / S;
+  const int64_t b = seg * chunk, e = min(n_rg, b + chunk);
+  double sum = 0.0;
+  uint64_t cnt = 0;
+  int64_t r = b;
+  for (; r + 8 <= e; r += 8) {
+    double v[8];
+    uint32_t m[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      v[q] = ld_agent(psse + (r + q) * part_ld + p);
+      m[q] = ld_agent(pmiss + (r + q) * part_ld + p);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      sum += v[q];
+      cnt += m[q];
+    }
+  }
+  for (; r < e; ++r) {
+    sum += ld_agent(psse + r * part_ld + p);
+    cnt += ld_agent(pmiss + r * part_ld + p);
+  }
+  s_red[threadIdx.x] = sum;
+  s_redm[threadIdx.x] = cnt;
+  __syncthreads();
+  if (seg == 0 && p < t.P) {
+    double tot = 0.0;
+    uint64_t mt = 0;
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      tot += s_red[q * TP + c];
+      mt += s_redm[q * TP + c];
+    }
+    const double ms = tot * t.invN, mc = (double)mt * t.invN, f = 1.0 - ms;
+    if (t.mse) st_agent(t.mse + p, ms);
+    if (t.miscls) st_agent(t.miscls + p, mc);
+    if (t.fit) st_agent(t.fit + p, f);
+    if (t.mse2) t.mse2[p] = ms;
+    if (t.miscls2) t.miscls2[p] = mc;
+    if (t.fit2) t.fit2[p] = f;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    t.counters[pt] = 0u;
+    s_flag = t.n_top > 0 && atomicAdd(&t.counters[t.n_pt_cap], 1u) == (uint32_t)(n_pt - 1);
+  }
+  __syncthreads();
+  if (!s_flag) return;
+  block_topk<256, true>(t.fit, t.P, t.n_top, t.top);
+  __syncthreads();
+  const float* pop = (t.st->generation & 1) ? t.pop1 : t.pop0;
+  track_best(t.st, t.top, t.mse, t.miscls, pop, t.L, t.best);
+  if (threadIdx.x == 0) t.counters[t.n_pt_cap] = 0u;
+}
 
 template <class Tr, int WM, int WN, bool kCls>
-__global__ __launch_bounds__(256) void fitness_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fitness_kernel(
     const typename Tr::T* __restrict__ phi, const typename Tr::T* __restrict__ tile,
     const typename Tr::Acc* __restrict__ biasv, const typename Tr::Acc* __restrict__ tvec,
     int64_t N, int M_pad, int64_t n_rt, int n_pt, int rt_per_wg, int64_t n_items, int part_ld,
-    double* __restrict__ part_sse, uint32_t* __restrict__ part_miss, const DevState* st) {
+    double* __restrict__ part_sse, uint32_t* __restrict__ part_miss, const DevState* st,
+    const FitTail tail) {
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
   using AccV = typename Tr::AccV;
@@ -171,10 +271,17 @@ __global__ __launch_bounds__(256) void fitness_kernel(
       for (int j = 0; j < WN; ++j) b[j] = *reinterpret_cast<const Ld*>(bptr[j] + kb * Tr::kBlk);
     };
     auto mma_all = [&](const Ld* a, const Ld* b) {
+      // one k-step across all accumulators before the next, so consecutive
+      // MFMAs never depend on each other
+      auto step = [&](auto s_tag) {
+        constexpr int S = decltype(s_tag)::value;
 #pragma unroll
-      for (int i = 0; i < WM; ++i)
+        for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < WN; ++j) acc[i][j] = Tr::mma(a[i], b[j], acc[i][j]);
+          for (int j = 0; j < WN; ++j) acc[i][j] = Tr::template mma<S>(a[i], b[j], acc[i][j]);
+      };
+      step(std::integral_constant<int, 0>{});
+      if constexpr (Tr::kSteps > 1) step(std::integral_constant<int, 1>{});
     };
     load(a0, b0, 0);
     int kb = 0;
@@ -189,12 +296,19 @@ __global__ __launch_bounds__(256) void fitness_kernel(
     // epilogue: accumulator element r of block (i, j) is pattern
     // nw0 + 16 i + row_in_block(r) and chromosome pw0 + 16 j + lrow
     auto row_in_block = [&](int r) { return Tr::kRowInterleave ? lgrp + 4 * r : 4 * lgrp + r; };
-    const bool full = (rt + 1) * TN <= N;
-    Acc tv[WM][4];
+    Acc tv[WM][4], cz[WM][4], wgt[WM][4];
+    int cmask[WM][4];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) tv[i][r] = tvec[nw0 + i * 16 + row_in_block(r)];
+      for (int r = 0; r < 4; ++r) {
+        const bool valid = nw0 + i * 16 + row_in_block(r) < N;
+        tv[i][r] = tvec[nw0 + i * 16 + row_in_block(r)];
+        const bool lab = tv[i][r] >= Acc(0.5);
+        cz[i][r] = lab ? Acc(kLog2e) : Acc(-kLog2e);
+        cmask[i][r] = valid ? (lab ? kMissIfLabel1 : kMissIfLabel0) : 0;
+        wgt[i][r] = valid ? Acc(1) : Acc(0);
+      }
 #pragma unroll
     for (int j = 0; j < WN; ++j) {
       Acc loc = Acc(0);
@@ -204,24 +318,14 @@ __global__ __launch_bounds__(256) void fitness_kernel(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const Acc z = acc[i][j][r] + bias_j[j];
-          const Acc t = tv[i][r];
-          Acc e;
-          bool m = false;
           if constexpr (kCls) {
-            const Acc d = t - sigmoid_acc(z);
-            e = d * d;
-            m = (z >= Acc(0)) != (t >= Acc(0.5));
+            const Acc q = sig_pos(cz[i][r] * z) * wgt[i][r];
+            loc += q * q;
+            ms += in_class(z, cmask[i][r]) ? 1u : 0u;
           } else {
-            const Acc d = t - z;
-            e = d * d;
+            const Acc d = (tv[i][r] - z) * wgt[i][r];
+            loc += d * d;
           }
-          if (!full) {
-            const bool valid = nw0 + i * 16 + row_in_block(r) < N;
-            e = valid ? e : Acc(0);
-            m = m && valid;
-          }
-          loc += e;
-          ms += m ? 1u : 0u;
         }
       }
       sse[j] += (double)loc;
@@ -249,73 +353,321 @@ __global__ __launch_bounds__(256) void fitness_kernel(
   __syncthreads();
   for (int c = threadIdx.x; c < TP; c += 256) {
     const int64_t o = rg * part_ld + pt * TP + c;
-    part_sse[o] = s_sse[0][c] + s_sse[1][c];
-    part_miss[o] = s_miss[0][c] + s_miss[1][c];
+    st_agent(part_sse + o, s_sse[0][c] + s_sse[1][c]);
+    st_agent(part_miss + o, s_miss[0][c] + s_miss[1][c]);
   }
+  const int64_t n_rg = (n_rt + rt_per_wg - 1) / rt_per_wg;
+  fitness_tail<TP>(tail, pt, n_pt, n_rg, part_ld, part_sse, part_miss);
 }
 
-// Fixed-order sum of the row-group partials: 16 chromosomes x 16 segments per
-// workgroup; segments are contiguous row-group ranges added in index order.
-__global__ __launch_bounds__(256) void reduce_kernel(int64_t n_rg, int part_ld, int P, double invN,
-                                                     const double* __restrict__ psse,
-                                                     const uint32_t* __restrict__ pmiss,
-                                                     double* mse, double* miscls, double* fit,
-                                                     double* mse2, double* miscls2, double* fit2,
-                                                     const DevState* st) {
+// Persistent decomposition, used when the gene tile of 128 chromosomes fits
+// in LDS.  The grid holds as many workgroups as can be resident; workgroup
+// (row range wr, chromosome tile pt) stages its gene tile in LDS once (row
+// stride padded so the 16 rows a quarter-wave reads sit in distinct banks)
+// and walks its contiguous range of 128-pattern row tiles.  The four waves are
+// stacked over rows, each computing 32 patterns x 128 chromosomes (2 x 8
+// blocks of 16 x 16), so every Phi row is read by exactly one wave.  The next
+// row tile's targets and first Phi K-block are fetched before the current
+// epilogue.  One partial row per workgroup: part[wr][p].
+template <class Tr, bool kCls>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fitness_lds_kernel(
+    const typename Tr::T* __restrict__ phi, const typename Tr::T* __restrict__ tile,
+    const typename Tr::Acc* __restrict__ biasv, const typename Tr::Acc* __restrict__ tvec,
+    int64_t N, int M_pad, int ldsw, int64_t n_rt, int n_pt, int n_ranges, int64_t n_items,
+    int part_ld, double* __restrict__ part_sse, uint32_t* __restrict__ part_miss,
+    const DevState* st, const FitTail tail) {
+  using T = typename Tr::T;
+  using Acc = typename Tr::Acc;
+  using AccV = typename Tr::AccV;
+  using Ld = typename Tr::Ld;
+  constexpr int WM = 2, WN = 8, TN = 128, TP = 128;
+  constexpr int kLdWords = (int)(sizeof(Ld) / 4);
+  constexpr int kBlkWords = Tr::kBlk * (int)sizeof(T) / 4;
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ double s_sse[4][TP];
+  __shared__ uint32_t s_miss[4][TP];
+
   if (run_halted(st)) return;
-  const int c = threadIdx.x & 15, seg = threadIdx.x >> 4;
-  const int p = blockIdx.x * 16 + c;
-  const int64_t chunk = (n_rg + 15) / 16;
-  const int64_t b = seg * chunk, e = min(n_rg, b + chunk);
-  double s = 0.0;
-  uint64_t m = 0;
-  if (p < P) {
-    for (int64_t r = b; r < e; ++r) {
-      s += psse[r * part_ld + p];
-      m += pmiss[r * part_ld + p];
+  const int64_t nwg = gridDim.x;
+  const int64_t w = blockIdx.x;
+  const int64_t lt = (w & 7) * (nwg >> 3) + (w >> 3);
+  if (lt >= n_items) return;
+  const int pt = (int)(lt % n_pt);
+  const int wr = (int)(lt / n_pt);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lrow = lane & 15, lgrp = lane >> 4;
+  const int KB = M_pad / Tr::kBlk;
+  const int64_t rt_begin = (int64_t)wr * n_rt / n_ranges;
+  const int64_t rt_end = (int64_t)(wr + 1) * n_rt / n_ranges;
+
+  // stage the gene tile (rows pt*TP .. +TP) into LDS
+  {
+    const int units = M_pad / Tr::kPerLane;  // Ld units per gene row
+    const Ld* src = reinterpret_cast<const Ld*>(tile + (int64_t)pt * TP * M_pad);
+    for (int v = tid; v < TP * units; v += 256) {
+      const int r = v / units, c = v - r * units;
+      *reinterpret_cast<Ld*>(&lds[r * ldsw + c * kLdWords]) = src[v];
     }
   }
-  __shared__ double ss[16][16];
-  __shared__ uint64_t sm[16][16];
-  ss[seg][c] = s;
-  sm[seg][c] = m;
+  const int p0 = pt * TP;
+  Acc bias_j[WN];
+#pragma unroll
+  for (int j = 0; j < WN; ++j) bias_j[j] = biasv ? biasv[p0 + j * 16 + lrow] : Acc(0);
+  const int bofs0 = lrow * ldsw + lgrp * kLdWords;  // + 16 j ldsw for block j
+
+  auto row_in_block = [&](int r) { return Tr::kRowInterleave ? lgrp + 4 * r : 4 * lgrp + r; };
+  auto tile_rows = [&](int64_t rt) { return rt * TN + wave * 32; };
+
+  double sse[WN];
+  uint32_t miss[WN];
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    sse[j] = 0.0;
+    miss[j] = 0u;
+  }
+
+  Ld a0[WM], a1[WM], b0[WN], b1[WN];
+  Acc tv[WM][4];
+  auto load_t = [&](int64_t rt) {
+    const int64_t nw0 = tile_rows(rt);
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tv[i][r] = tvec[nw0 + i * 16 + row_in_block(r)];
+  };
+  auto loadA = [&](Ld* a, int64_t rt, int kb) {
+    const int64_t nw0 = tile_rows(rt);
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+      a[i] = *reinterpret_cast<const Ld*>(phi + (nw0 + i * 16 + lrow) * (int64_t)M_pad +
+                                          lgrp * Tr::kPerLane + kb * Tr::kBlk);
+  };
+  auto loadB = [&](Ld* b, int kb) {
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+      b[j] = *reinterpret_cast<const Ld*>(&lds[bofs0 + j * 16 * ldsw + kb * kBlkWords]);
+  };
+
+  if (rt_begin < rt_end) {
+    load_t(rt_begin);
+    loadA(a0, rt_begin, 0);
+  }
   __syncthreads();
-  if (seg == 0 && p < P) {
-    double tot = 0.0;
-    uint64_t mt = 0;
-    for (int q = 0; q < 16; ++q) {
-      tot += ss[q][c];
-      mt += sm[q][c];
+
+  for (int64_t rt = rt_begin; rt < rt_end; ++rt) {
+    AccV acc[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j) acc[i][j] = AccV{};
+    auto mma_all = [&](const Ld* a, const Ld* b) {
+      // one k-step across all accumulators before the next, so consecutive
+      // MFMAs never depend on each other
+      auto step = [&](auto s_tag) {
+        constexpr int S = decltype(s_tag)::value;
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) acc[i][j] = Tr::template mma<S>(a[i], b[j], acc[i][j]);
+      };
+      step(std::integral_constant<int, 0>{});
+      if constexpr (Tr::kSteps > 1) step(std::integral_constant<int, 1>{});
+    };
+    // 16-bit operands: the gene fragments are 16 bytes per lane, so only Phi is
+    // double-buffered (LDS reads are issued right before their MFMAs)
+    constexpr bool kDoubleB = sizeof(Ld) == 8;
+    int kb = 0;
+    if constexpr (kDoubleB) {
+      loadB(b0, 0);
+      for (; kb + 1 < KB; kb += 2) {
+        loadA(a1, rt, kb + 1);
+        loadB(b1, kb + 1);
+        mma_all(a0, b0);
+        if (kb + 2 < KB) {
+          loadA(a0, rt, kb + 2);
+          loadB(b0, kb + 2);
+        }
+        mma_all(a1, b1);
+      }
+      if (kb < KB) mma_all(a0, b0);
+    } else {
+      for (; kb + 1 < KB; kb += 2) {
+        loadA(a1, rt, kb + 1);
+        loadB(b0, kb);
+        mma_all(a0, b0);
+        if (kb + 2 < KB) loadA(a0, rt, kb + 2);
+        loadB(b0, kb + 1);
+        mma_all(a1, b0);
+      }
+      if (kb < KB) {
+        loadB(b0, kb);
+        mma_all(a0, b0);
+      }
     }
-    const double ms = tot * invN;
-    const double mc = (double)mt * invN;
-    const double f = 1.0 - ms;
-    if (mse) mse[p] = ms;
-    if (miscls) miscls[p] = mc;
-    if (fit) fit[p] = f;
-    if (mse2) mse2[p] = ms;
-    if (miscls2) miscls2[p] = mc;
-    if (fit2) fit2[p] = f;
+    (void)b1;
+
+    // this tile's targets -> per-pattern coefficients, then prefetch the next tile
+    const int64_t nw0 = tile_rows(rt);
+    const bool full = (rt + 1) * TN <= N;
+    Acc tcur[WM][4];   // regression: target; classification: -s log2(e)
+    int cmask[WM][4];  // classification: class mask of missed outputs
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool valid = full || nw0 + i * 16 + row_in_block(r) < N;
+        const bool lab = tv[i][r] >= Acc(0.5);
+        tcur[i][r] = kCls ? (lab ? Acc(kLog2e) : Acc(-kLog2e)) : tv[i][r];
+        cmask[i][r] = valid ? (lab ? kMissIfLabel1 : kMissIfLabel0) : 0;
+      }
+    if (rt + 1 < rt_end) {
+      load_t(rt + 1);
+      loadA(a0, rt + 1, 0);
+    }
+
+    // epilogue: element r of block (i, j) is pattern nw0 + 16 i + row_in_block(r),
+    // chromosome p0 + 16 j + lrow
+    auto epilogue = [&](auto full_tag) {
+      constexpr bool kFull = decltype(full_tag)::value;
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        Acc loc = Acc(0);
+        uint32_t ms = 0u;
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const Acc z = acc[i][j][r] + bias_j[j];
+            Acc q;
+            if constexpr (kCls) {
+              q = sig_pos(tcur[i][r] * z);
+              ms += in_class(z, cmask[i][r]) ? 1u : 0u;
+            } else {
+              q = tcur[i][r] - z;
+            }
+            if constexpr (!kFull) q = (nw0 + i * 16 + row_in_block(r) < N) ? q : Acc(0);
+            loc += q * q;
+          }
+        sse[j] += (double)loc;
+        miss[j] += ms;
+      }
+    };
+    if (full)
+      epilogue(std::integral_constant<bool, true>{});
+    else
+      epilogue(std::integral_constant<bool, false>{});
   }
+
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    sse[j] += __shfl_xor(sse[j], 16);
+    sse[j] += __shfl_xor(sse[j], 32);
+    miss[j] += __shfl_xor(miss[j], 16);
+    miss[j] += __shfl_xor(miss[j], 32);
+  }
+  if (lgrp == 0) {
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      s_sse[wave][j * 16 + lrow] = sse[j];
+      s_miss[wave][j * 16 + lrow] = miss[j];
+    }
+  }
+  __syncthreads();
+  if (tid < TP) {
+    const int64_t o = (int64_t)wr * part_ld + p0 + tid;
+    st_agent(part_sse + o, ((s_sse[0][tid] + s_sse[1][tid]) + s_sse[2][tid]) + s_sse[3][tid]);
+    st_agent(part_miss + o, s_miss[0][tid] + s_miss[1][tid] + s_miss[2][tid] + s_miss[3][tid]);
+  }
+  fitness_tail<TP>(tail, pt, n_pt, n_ranges, part_ld, part_sse, part_miss);
 }
 
 template <class Tr, int WM, int WN>
 hipError_t launch_tr(int task, const FitnessGeom& g, const Plan& p, const void* phi,
                      const void* tile, const void* biasv, const void* tvec, double* psse,
-                     uint32_t* pmiss, const DevState* st, hipStream_t s) {
+                     uint32_t* pmiss, const DevState* st, const FitTail& tail, hipStream_t s) {
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
   if (task == GAME_CLASSIFICATION)
     hipLaunchKernelGGL((fitness_kernel<Tr, WM, WN, true>), dim3((unsigned)g.grid), dim3(256), 0, s,
                        (const T*)phi, (const T*)tile, (const Acc*)biasv, (const Acc*)tvec, p.N,
                        p.M_pad, p.n_rt, g.n_pt, g.rt_per_wg, g.n_items, p.P_max_pad, psse, pmiss,
-                       st);
+                       st, tail);
   else
     hipLaunchKernelGGL((fitness_kernel<Tr, WM, WN, false>), dim3((unsigned)g.grid), dim3(256), 0,
                        s, (const T*)phi, (const T*)tile, (const Acc*)biasv, (const Acc*)tvec, p.N,
                        p.M_pad, p.n_rt, g.n_pt, g.rt_per_wg, g.n_items, p.P_max_pad, psse, pmiss,
-                       st);
+                       st, tail);
   return hipGetLastError();
+}
+
+// LDS row stride (4-byte words) for the staged gene tile: a multiple of the
+// per-lane load unit, congruent to it modulo 64 words, so the 16 rows read by
+// a quarter-wave fall in distinct banks.
+template <class Tr>
+int lds_stride_words(int M_pad) {
+  const int unit = (int)(sizeof(typename Tr::Ld) / 4);
+  const int row = M_pad * (int)sizeof(typename Tr::T) / 4;
+  int s = row + ((unit - row) % 64 + 64) % 64;
+  return s;
+}
+
+template <class Tr>
+auto lds_kernel_for(int task) {
+  return task == GAME_CLASSIFICATION ? fitness_lds_kernel<Tr, true> : fitness_lds_kernel<Tr, false>;
+}
+
+// Dynamic LDS above 64 KiB has to be enabled per kernel once.
+template <class Tr>
+hipError_t lds_prepare(int task) {
+  static bool done[2] = {false, false};
+  const int ai = task == GAME_CLASSIFICATION ? 1 : 0;
+  if (done[ai]) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(lds_kernel_for<Tr>(task)),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 98304);
+  if (e == hipSuccess) done[ai] = true;
+  return e;
+}
+
+template <class Tr>
+hipError_t launch_lds(int task, const FitnessGeom& g, const Plan& p, const void* phi,
+                      const void* tile, const void* biasv, const void* tvec, double* psse,
+                      uint32_t* pmiss, const DevState* st, const FitTail& tail, hipStream_t s) {
+  using T = typename Tr::T;
+  using Acc = typename Tr::Acc;
+  const int ldsw = lds_stride_words<Tr>(p.M_pad);
+  const size_t lds = (size_t)128 * ldsw * 4;
+  const hipError_t e = lds_prepare<Tr>(task);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(lds_kernel_for<Tr>(task), dim3((unsigned)g.grid), dim3(256), lds, s,
+                     (const T*)phi, (const T*)tile, (const Acc*)biasv, (const Acc*)tvec, p.N,
+                     p.M_pad, ldsw, p.n_rt, g.n_pt, (int)g.n_rg, g.n_items, p.P_max_pad, psse,
+                     pmiss, st, tail);
+  return hipGetLastError();
+}
+
+// Workgroups of the LDS kernel that are resident at once on the device.
+template <class Tr>
+int lds_resident(int task, int M_pad) {
+  static int cache[2][8192 / 8 + 1] = {};
+  const int ai = task == GAME_CLASSIFICATION ? 1 : 0;
+  const int ci = M_pad / 8 < 1024 ? M_pad / 8 : 1024;
+  if (cache[ai][ci]) return cache[ai][ci];
+  if (lds_prepare<Tr>(task) != hipSuccess) return 0;
+  const size_t lds = (size_t)128 * lds_stride_words<Tr>(M_pad) * 4;
+  int blocks = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &blocks, reinterpret_cast<const void*>(lds_kernel_for<Tr>(task)), 256, lds) != hipSuccess)
+    return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  cache[ai][ci] = blocks * cus;
+  return cache[ai][ci];
+}
+
+// The LDS variant needs 128 rows of the padded gene tile in at most 96 KiB.
+template <class Tr>
+bool lds_fits(const Plan& p) {
+  return (size_t)128 * lds_stride_words<Tr>(p.M_pad) * 4 <= 98304;
 }
 
 }  // namespace
@@ -331,30 +683,39 @@ void fitness_tile(int dtype, int* tile_n, int* tile_p) {
   }
 }
 
-hipError_t launch_fitness(const Plan& p, int task, int dtype, const FitnessGeom& g, const void* phi,
-                          const void* tile, const void* biasv, const void* tvec, double* psse,
-                          uint32_t* pmiss, const DevState* st, hipStream_t s) {
+int fitness_persistent_slots(const Plan& p, int task, int dtype) {
   switch (dtype) {
-    case GAME_F64:
-      return launch_tr<F64Tr, 2, 2>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, s);
     case GAME_F32:
-      return launch_tr<F32Tr, 4, 4>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, s);
+      return lds_fits<F32Tr>(p) ? lds_resident<F32Tr>(task, p.M_pad) : 0;
     case GAME_BF16:
-      return launch_tr<BF16Tr, 4, 4>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, s);
+      return lds_fits<BF16Tr>(p) ? lds_resident<BF16Tr>(task, p.M_pad) : 0;
     case GAME_F16:
-      return launch_tr<F16Tr, 4, 4>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, s);
+      return lds_fits<F16Tr>(p) ? lds_resident<F16Tr>(task, p.M_pad) : 0;
   }
-  return hipErrorInvalidValue;
+  return 0;
 }
 
-hipError_t launch_reduce(const Plan& p, const FitnessGeom& g, int P, const double* psse,
-                         const uint32_t* pmiss, double* mse, double* miscls, double* fit,
-                         double* mse2, double* miscls2, double* fit2, const DevState* st,
-                         hipStream_t s) {
-  const int grid = (P + 15) / 16;
-  hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(256), 0, s, g.n_rg, p.P_max_pad, P,
-                     1.0 / (double)p.N, psse, pmiss, mse, miscls, fit, mse2, miscls2, fit2, st);
-  return hipGetLastError();
+hipError_t launch_fitness(const Plan& p, int task, int dtype, const FitnessGeom& g, const void* phi,
+                          const void* tile, const void* biasv, const void* tvec, double* psse,
+                          uint32_t* pmiss, const DevState* st, const FitTail& tail,
+                          hipStream_t s) {
+  switch (dtype) {
+    case GAME_F64:
+      return launch_tr<F64Tr, 2, 2>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
+    case GAME_F32:
+      if (lds_fits<F32Tr>(p))
+        return launch_lds<F32Tr>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
+      return launch_tr<F32Tr, 4, 4>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
+    case GAME_BF16:
+      if (lds_fits<BF16Tr>(p))
+        return launch_lds<BF16Tr>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
+      return launch_tr<BF16Tr, 4, 4>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
+    case GAME_F16:
+      if (lds_fits<F16Tr>(p))
+        return launch_lds<F16Tr>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
+      return launch_tr<F16Tr, 4, 4>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace game

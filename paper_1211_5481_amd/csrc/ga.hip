@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #include "game_internal.hpp"
+#include "select.hpp"
 
 // Every float operation in this file is rounded on its own: a fused
 // multiply-add would change the mutated genes.
@@ -41,105 +42,39 @@ __global__ void init_population_kernel(float* __restrict__ pop, int P, int L, ui
 }
 
 // ------------------------------------------------------------ ranking
-// Order: higher fitness first, ties to the lower index, NaN ranks last.
-struct Ranked {
-  double key;
-  int idx;
-};
-__device__ __forceinline__ bool better(const Ranked& a, const Ranked& b) {
-  return a.key > b.key || (a.key == b.key && a.idx < b.idx);
-}
-__device__ __forceinline__ double rank_key(double f) { return isnan(f) ? -INFINITY : f; }
-
 constexpr int kRankThreads = 1024;
 
-// Top n_top indices by repeated arg-max (n_top <= kMaxElite); one workgroup.
 __global__ __launch_bounds__(kRankThreads) void rank_kernel(const double* __restrict__ fit, int P,
-                                                            int n_top, int* __restrict__ top,
-                                                            const DevState* st) {
-  if (run_halted(st)) return;
-  __shared__ int chosen[kMaxElite];
-  __shared__ double wkey[kRankThreads / 64];
-  __shared__ int widx[kRankThreads / 64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = 0; e < n_top; ++e) {
-    Ranked best{-INFINITY, 0x7fffffff};
-    for (int i = tid; i < P; i += kRankThreads) {
-      bool taken = false;
-      for (int q = 0; q < e; ++q) taken |= (chosen[q] == i);
-      if (taken) continue;
-      const Ranked c{rank_key(fit[i]), i};
-      if (better(c, best)) best = c;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      Ranked o{__shfl_xor(best.key, off), __shfl_xor(best.idx, off)};
-      if (better(o, best)) best = o;
-    }
-    if (lane == 0) {
-      wkey[wave] = best.key;
-      widx[wave] = best.idx;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      Ranked b{wkey[0], widx[0]};
-      for (int q = 1; q < kRankThreads / 64; ++q) {
-        const Ranked o{wkey[q], widx[q]};
-        if (better(o, b)) b = o;
-      }
-      chosen[e] = b.idx;
-      top[e] = b.idx;
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------- best tracking
-// Keeps the best chromosome seen (strictly lower MSE replaces it) and, while
-// a run is active, decides whether the run stops after this generation.
-__global__ void track_kernel(DevState* st, const int* __restrict__ top,
-                             const double* __restrict__ mse, const double* __restrict__ miscls,
-                             const float* __restrict__ pop, int L, float* __restrict__ best) {
-  if (run_halted(st)) return;
-  const int b = top[0];
-  const double m = mse[b];
-  const bool improve = !st->have_best || m < st->best_mse;
-  __syncthreads();
-  if (improve)
-    for (int l = threadIdx.x; l < L; l += blockDim.x) best[l] = pop[(int64_t)b * L + l];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    st->best_index = b;
-    if (improve) {
-      st->have_best = 1;
-      st->best_mse = m;
-      st->best_fitness = 1.0 - m;
-      st->best_miscls = miscls[b];
-    }
-    if (st->run_active) {
-      if (st->best_mse <= st->mse_threshold) {
-        st->stopped = 1;
-        st->stop_reason = GAME_STOP_THRESHOLD;
-      } else if (st->generation + 1 >= st->end_generation) {
-        st->stopped = 1;
-        st->stop_reason = GAME_STOP_MAX_GEN;
-      }
-    }
-  }
+                                                            int n_top, int* __restrict__ top) {
+  block_topk<kRankThreads>(fit, P, n_top, top);
 }
 
 // --------------------------------------------------------------- breed
-// One wave per output slot group: waves 0..E-1 copy the elites, wave E + j
-// builds the children of pair j (tournaments, crossover, mutation).
-struct BreedArgs {
-  const float* pop;
-  const double* fit;
-  const int* elite;
-  float* next;
-  int P, L, E, n_children, k;
-  uint64_t thr_c, thr_m;
-  float sigma;
-  uint32_t k0, k1;
-};
+// One wave per output row group: waves 0..E-1 copy the elites, wave E + j
+// builds the children of pair j (tournaments, crossover, mutation).  Each
+// new gene goes to the next population buffer (float32 master) and, rounded
+// to the contraction type, to the gene tile the fitness kernel reads next.
+// The last workgroup to finish advances the generation counter.
+
+template <typename O>
+__device__ __forceinline__ O cvt_gene(float g);
+template <>
+__device__ __forceinline__ double cvt_gene<double>(float g) {
+  return (double)g;
+}
+template <>
+__device__ __forceinline__ float cvt_gene<float>(float g) {
+  return g;
+}
+template <>
+__device__ __forceinline__ _Float16 cvt_gene<_Float16>(float g) {
+  return (_Float16)g;
+}
+template <>
+__device__ __forceinline__ uint16_t cvt_gene<uint16_t>(float g) {  // bf16, nearest even
+  const uint32_t u = __float_as_uint(g);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
 
 __device__ __forceinline__ int tournament(const BreedArgs& a, uint32_t j, uint32_t s, uint32_t g) {
   Ranked win{0.0, -1};
@@ -171,77 +106,76 @@ __device__ __forceinline__ float mutate_gene(float gene, uint32_t c, uint32_t l,
   return fminf(fmaxf(v, -1.0f), 1.0f);
 }
 
-__global__ __launch_bounds__(256) void breed_kernel(BreedArgs a, const DevState* st) {
+template <typename O, typename B>
+__device__ __forceinline__ void put_gene(const BreedArgs& a, float* dst, int row, int l, float v) {
+  dst[(int64_t)row * a.L + l] = v;
+  if (l < a.M)
+    static_cast<O*>(a.tile)[(int64_t)row * a.M_pad + l] = cvt_gene<O>(v);
+  else
+    static_cast<B*>(a.biasv)[row] = (B)v;
+}
+
+template <typename O, typename B>
+__global__ __launch_bounds__(256) void breed_kernel(BreedArgs a, DevState* st) {
   if (run_halted(st)) return;
   const int wave = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   const uint32_t g = (uint32_t)st->generation;
+  const float* src = (g & 1u) ? a.pop1 : a.pop0;
+  float* dst = (g & 1u) ? a.pop0 : a.pop1;
   if (wave < a.E) {
-    const float* src = a.pop + (int64_t)a.elite[wave] * a.L;
-    float* dst = a.next + (int64_t)wave * a.L;
-    for (int l = lane; l < a.L; l += 64) dst[l] = src[l];
-    return;
+    const float* row = src + (int64_t)a.elite[wave] * a.L;
+    for (int l = lane; l < a.L; l += 64) put_gene<O, B>(a, dst, wave, l, row[l]);
+  } else if (2 * (wave - a.E) < a.n_children) {
+    const int j = wave - a.E;
+    const int pa = tournament(a, (uint32_t)j, 0u, g);
+    const int pb = tournament(a, (uint32_t)j, 1u, g);
+    const u32x4 xb = philox((uint32_t)j, 8u, g, kTagSel, a.k0, a.k1);
+    int cut = a.L;  // no crossover: child0 = a, child1 = b
+    if ((uint64_t)xb.x < a.thr_c && a.L >= 2) cut = 1 + (int)__umulhi(xb.y, (uint32_t)(a.L - 1));
+    const float* ra = src + (int64_t)pa * a.L;
+    const float* rb = src + (int64_t)pb * a.L;
+    const uint32_t c0 = 2u * (uint32_t)j, c1 = c0 + 1u;
+    const bool has1 = (int)c1 < a.n_children;
+    for (int l = lane; l < a.L; l += 64) {
+      const float ga = ra[l], gb = rb[l];
+      const float x0 = l < cut ? ga : gb;
+      const float x1 = l < cut ? gb : ga;
+      put_gene<O, B>(a, dst, a.E + (int)c0, l, mutate_gene(x0, c0, (uint32_t)l, g, a));
+      if (has1) put_gene<O, B>(a, dst, a.E + (int)c1, l, mutate_gene(x1, c1, (uint32_t)l, g, a));
+    }
   }
-  const int j = wave - a.E;
-  if (2 * j >= a.n_children) return;
-  const int pa = tournament(a, (uint32_t)j, 0u, g);
-  const int pb = tournament(a, (uint32_t)j, 1u, g);
-  const u32x4 xb = philox((uint32_t)j, 8u, g, kTagSel, a.k0, a.k1);
-  int cut = a.L;  // no crossover: child0 = a, child1 = b
-  if ((uint64_t)xb.x < a.thr_c && a.L >= 2) cut = 1 + (int)__umulhi(xb.y, (uint32_t)(a.L - 1));
-  const float* ra = a.pop + (int64_t)pa * a.L;
-  const float* rb = a.pop + (int64_t)pb * a.L;
-  const uint32_t c0 = 2u * (uint32_t)j, c1 = c0 + 1u;
-  const bool has1 = (int)c1 < a.n_children;
-  float* d0 = a.next + (int64_t)(a.E + (int)c0) * a.L;
-  float* d1 = a.next + (int64_t)(a.E + (int)c1) * a.L;
-  for (int l = lane; l < a.L; l += 64) {
-    const float ga = ra[l], gb = rb[l];
-    const float x0 = l < cut ? ga : gb;
-    const float x1 = l < cut ? gb : ga;
-    d0[l] = mutate_gene(x0, c0, (uint32_t)l, g, a);
-    if (has1) d1[l] = mutate_gene(x1, c1, (uint32_t)l, g, a);
+  // The last workgroup to arrive advances the generation.  The barrier waits
+  // for this workgroup's loads (its read of the generation included) before
+  // the arrival; the new genes are read only by later launches.
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = atomicAdd(a.counter, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (s_last && threadIdx.x == 0) {
+    st->generation += 1;
+    *a.counter = 0u;
   }
 }
 
-// ------------------------------------------------------------- commit
-__global__ void commit_kernel(const float4* __restrict__ next, float4* __restrict__ pop,
-                              int64_t n4, const float* __restrict__ next_s,
-                              float* __restrict__ pop_s, int64_t count, DevState* st) {
-  if (run_halted(st)) return;
+__global__ void pop_copy_kernel(float* __restrict__ pop0, float* __restrict__ pop1,
+                                const DevState* __restrict__ st, float* __restrict__ ext,
+                                int64_t n, int dir) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n4) pop[i] = next[i];
-  const int64_t tail = n4 * 4 + i;
-  if (i < 4 && tail < count) pop_s[tail] = next_s[tail];
-  if (i == 0) st->generation += 1;
+  if (i >= n) return;
+  float* cur = (st->generation & 1) ? pop1 : pop0;
+  if (dir == 0)
+    ext[i] = cur[i];
+  else
+    cur[i] = ext[i];
 }
 
 // --------------------------------------------------------------- pack
-template <typename O>
-__device__ __forceinline__ O cvt_gene(float g);
-template <>
-__device__ __forceinline__ double cvt_gene<double>(float g) {
-  return (double)g;
-}
-template <>
-__device__ __forceinline__ float cvt_gene<float>(float g) {
-  return g;
-}
-template <>
-__device__ __forceinline__ _Float16 cvt_gene<_Float16>(float g) {
-  return (_Float16)g;
-}
-template <>
-__device__ __forceinline__ uint16_t cvt_gene<uint16_t>(float g) {  // bf16, nearest even
-  const uint32_t u = __float_as_uint(g);
-  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
-
 template <typename O, typename B>
-__global__ void pack_kernel(const float* __restrict__ genes, int P, int L, int M, int bias,
-                            int M_pad, int P_pad, O* __restrict__ tile, B* __restrict__ biasv,
-                            const DevState* st) {
-  if (run_halted(st)) return;
+__global__ void pack_kernel(const float* __restrict__ genes0, const float* __restrict__ genes1,
+                            const DevState* sel, int P, int L, int M, int bias, int M_pad,
+                            int P_pad, O* __restrict__ tile, B* __restrict__ biasv) {
+  const float* genes = (sel && (sel->generation & 1)) ? genes1 : genes0;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)P_pad * M_pad;
   if (idx < total) {
@@ -256,6 +190,11 @@ __global__ void copy_targets_kernel(const T* __restrict__ t, int64_t N, int64_t 
                                     T* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < N_pad) out[i] = i < N ? t[i] : (T)0;
+}
+
+__global__ void zero_counters_kernel(uint32_t* c, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) c[i] = 0u;
 }
 
 __global__ void state_init_kernel(DevState* st) {
@@ -294,59 +233,62 @@ hipError_t launch_init_population(float* pop, int P, int L, uint64_t seed, hipSt
 
 hipError_t launch_rank(const double* fit, int P, int n_top, int* top_idx, const DevState* st,
                        hipStream_t s) {
-  hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(kRankThreads), 0, s, fit, P, n_top, top_idx, st);
+  (void)st;
+  hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(kRankThreads), 0, s, fit, P, n_top, top_idx);
   return hipGetLastError();
 }
 
-hipError_t launch_track(DevState* st, const int* top_idx, const double* mse, const double* miscls,
-                        const float* pop, int L, float* best_genes, hipStream_t s) {
-  hipLaunchKernelGGL(track_kernel, dim3(1), dim3(256), 0, s, st, top_idx, mse, miscls, pop, L,
-                     best_genes);
+hipError_t launch_breed(int dtype, const BreedArgs& a, DevState* st, hipStream_t s) {
+  const int waves = a.E + (a.n_children + 1) / 2;
+  const dim3 grid((unsigned)((waves + 3) / 4 > 0 ? (waves + 3) / 4 : 1)), block(256);
+  switch (dtype) {
+    case GAME_F64:
+      hipLaunchKernelGGL((breed_kernel<double, double>), grid, block, 0, s, a, st);
+      break;
+    case GAME_F32:
+      hipLaunchKernelGGL((breed_kernel<float, float>), grid, block, 0, s, a, st);
+      break;
+    case GAME_BF16:
+      hipLaunchKernelGGL((breed_kernel<uint16_t, float>), grid, block, 0, s, a, st);
+      break;
+    case GAME_F16:
+      hipLaunchKernelGGL((breed_kernel<_Float16, float>), grid, block, 0, s, a, st);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_breed(const float* pop, const double* fit, const int* elite_idx, float* next,
-                        int P, int L, int E, int n_children, int k, uint64_t thr_c,
-                        uint64_t thr_m, float sigma, uint64_t seed, const DevState* st,
-                        hipStream_t s) {
-  BreedArgs a{pop, fit, elite_idx, next, P, L, E, n_children, k, thr_c, thr_m, sigma,
-              (uint32_t)seed, (uint32_t)(seed >> 32)};
-  const int waves = E + (n_children + 1) / 2;
-  if (waves == 0) return hipSuccess;
-  hipLaunchKernelGGL(breed_kernel, dim3((waves + 3) / 4), dim3(256), 0, s, a, st);
+hipError_t launch_pop_copy(float* pop0, float* pop1, const DevState* st, float* ext, int64_t n,
+                           int dir, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(pop_copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pop0,
+                     pop1, st, ext, n, dir);
   return hipGetLastError();
 }
 
-hipError_t launch_commit(const float* next, float* pop, int64_t count, DevState* st,
-                         hipStream_t s) {
-  const int64_t n4 = count / 4;
-  const int64_t threads = n4 > 4 ? n4 : 4;
-  hipLaunchKernelGGL(commit_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
-                     reinterpret_cast<const float4*>(next), reinterpret_cast<float4*>(pop), n4,
-                     next, pop, count, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_pack(int dtype, const float* genes, int P, int L, int M, int bias, int M_pad,
-                       int P_pad, void* tile, void* biasv, const DevState* st, hipStream_t s) {
+hipError_t launch_pack(int dtype, const float* genes0, const float* genes1, const DevState* sel,
+                       int P, int L, int M, int bias, int M_pad, int P_pad, void* tile, void* biasv,
+                       hipStream_t s) {
   const int64_t total = (int64_t)P_pad * M_pad;
   const dim3 grid((unsigned)((total + 255) / 256)), block(256);
   switch (dtype) {
     case GAME_F64:
-      hipLaunchKernelGGL((pack_kernel<double, double>), grid, block, 0, s, genes, P, L, M, bias,
-                         M_pad, P_pad, (double*)tile, (double*)biasv, st);
+      hipLaunchKernelGGL((pack_kernel<double, double>), grid, block, 0, s, genes0, genes1, sel, P,
+                         L, M, bias, M_pad, P_pad, (double*)tile, (double*)biasv);
       break;
     case GAME_F32:
-      hipLaunchKernelGGL((pack_kernel<float, float>), grid, block, 0, s, genes, P, L, M, bias,
-                         M_pad, P_pad, (float*)tile, (float*)biasv, st);
+      hipLaunchKernelGGL((pack_kernel<float, float>), grid, block, 0, s, genes0, genes1, sel, P, L,
+                         M, bias, M_pad, P_pad, (float*)tile, (float*)biasv);
       break;
     case GAME_BF16:
-      hipLaunchKernelGGL((pack_kernel<uint16_t, float>), grid, block, 0, s, genes, P, L, M, bias,
-                         M_pad, P_pad, (uint16_t*)tile, (float*)biasv, st);
+      hipLaunchKernelGGL((pack_kernel<uint16_t, float>), grid, block, 0, s, genes0, genes1, sel, P,
+                         L, M, bias, M_pad, P_pad, (uint16_t*)tile, (float*)biasv);
       break;
     case GAME_F16:
-      hipLaunchKernelGGL((pack_kernel<_Float16, float>), grid, block, 0, s, genes, P, L, M, bias,
-                         M_pad, P_pad, (_Float16*)tile, (float*)biasv, st);
+      hipLaunchKernelGGL((pack_kernel<_Float16, float>), grid, block, 0, s, genes0, genes1, sel, P,
+                         L, M, bias, M_pad, P_pad, (_Float16*)tile, (float*)biasv);
       break;
     default:
       return hipErrorInvalidValue;
@@ -366,8 +308,10 @@ hipError_t launch_copy_targets(int dtype, const void* t, int64_t N, int64_t N_pa
   return hipGetLastError();
 }
 
-hipError_t launch_state_init(DevState* st, hipStream_t s) {
+hipError_t launch_state_init(DevState* st, uint32_t* counters, int n_counters, hipStream_t s) {
   hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(1), 0, s, st);
+  hipLaunchKernelGGL(zero_counters_kernel, dim3((unsigned)((n_counters + 255) / 256)), dim3(256), 0,
+                     s, counters, n_counters);
   return hipGetLastError();
 }
 

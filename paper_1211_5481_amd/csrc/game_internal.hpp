@@ -76,6 +76,26 @@ __device__ __forceinline__ bool run_halted(const DevState* s) {
   return s != nullptr && s->run_active && s->stopped;
 }
 
+// Tail of the fitness kernels: the last workgroup of each chromosome tile
+// reduces that tile's partial sums (fixed order) into mse / miscls / fitness;
+// for a population evaluation the last tile to finish also ranks the
+// population and tracks the best chromosome.
+struct FitTail {
+  uint32_t* counters;   // [n_pt_cap + 1], zero between launches
+  int n_pt_cap;         // index of the "tiles done" counter
+  int P;                // chromosomes evaluated
+  double invN;
+  double *mse, *miscls, *fit;     // internal results or null
+  double *mse2, *miscls2, *fit2;  // caller results or null
+  int n_top;            // > 0: rank the population (top n_top) and track the best
+  int* top;
+  DevState* st;
+  const float* pop0;    // population buffers; generation g lives in pop[g & 1]
+  const float* pop1;
+  int L;
+  float* best;
+};
+
 // ----------------------------------------------------------- plan
 struct Plan {
   int K, M, L, M_pad, P, n_off, E, P_max, k;
@@ -88,8 +108,9 @@ struct Plan {
   size_t elt;                  // bytes per Phi / tile element
   size_t acc;                  // bytes per t / bias element (8 for F64 else 4)
   // workspace offsets
-  size_t off_phi, off_t, off_tile, off_bias, off_pop, off_next, off_psse, off_pmiss;
-  size_t off_mse, off_miscls, off_fit, off_elite, off_state, off_best, total;
+  int n_pt_cap;                // chromosome tiles at P_max
+  size_t off_phi, off_t, off_tile, off_bias, off_pop0, off_pop1, off_psse, off_pmiss;
+  size_t off_mse, off_miscls, off_fit, off_elite, off_state, off_best, off_cnt, total;
 };
 
 game_status make_plan(const game_config* cfg, Plan* p, char* err, size_t errlen);
@@ -102,8 +123,10 @@ hipError_t launch_basis(const game_config* cfg, const void* X, int64_t rows_in, 
 hipError_t launch_copy_targets(int dtype, const void* t, int64_t N, int64_t N_pad, void* tvec,
                                hipStream_t s);
 
-hipError_t launch_pack(int dtype, const float* genes, int P, int L, int M, int bias, int M_pad,
-                       int P_pad, void* tile, void* biasv, const DevState* st, hipStream_t s);
+// genes = (sel && sel->generation is odd) ? genes1 : genes0
+hipError_t launch_pack(int dtype, const float* genes0, const float* genes1, const DevState* sel,
+                       int P, int L, int M, int bias, int M_pad, int P_pad, void* tile, void* biasv,
+                       hipStream_t s);
 
 struct FitnessGeom {
   int n_pt;        // chromosome tiles
@@ -112,34 +135,44 @@ struct FitnessGeom {
   int64_t n_items; // workgroups doing work
   int64_t grid;    // launched workgroups (multiple of 8)
 };
-FitnessGeom fitness_geometry(const Plan& p, int P_eval);
+// Workgroups of the persistent (LDS) fitness kernel resident at once, or 0
+// when the configuration uses the non-persistent kernel.
+int fitness_persistent_slots(const Plan& p, int task, int dtype);
+FitnessGeom fitness_geometry(const Plan& p, int task, int dtype, int P_eval);
 
 hipError_t launch_fitness(const Plan& p, int task, int dtype, const FitnessGeom& g, const void* phi,
                           const void* tile, const void* biasv, const void* tvec, double* psse,
-                          uint32_t* pmiss, const DevState* st, hipStream_t s);
-
-hipError_t launch_reduce(const Plan& p, const FitnessGeom& g, int P, const double* psse,
-                         const uint32_t* pmiss, double* mse, double* miscls, double* fit,
-                         double* mse2, double* miscls2, double* fit2, const DevState* st,
-                         hipStream_t s);
+                          uint32_t* pmiss, const DevState* st, const FitTail& tail,
+                          hipStream_t s);
 
 hipError_t launch_init_population(float* pop, int P, int L, uint64_t seed, hipStream_t s);
 
 hipError_t launch_rank(const double* fit, int P, int n_top, int* top_idx, const DevState* st,
                        hipStream_t s);
 
-hipError_t launch_track(DevState* st, const int* top_idx, const double* mse, const double* miscls,
-                        const float* pop, int L, float* best_genes, hipStream_t s);
+// One generation of the genetic operators: reads pop[g & 1], writes
+// pop[(g + 1) & 1] and the gene tile (+ bias), then advances the generation.
+struct BreedArgs {
+  float* pop0;
+  float* pop1;
+  const double* fit;
+  const int* elite;
+  int P, L, E, n_children, k;
+  uint64_t thr_c, thr_m;
+  float sigma;
+  uint32_t k0, k1;
+  void* tile;
+  void* biasv;
+  int M, M_pad, bias;
+  uint32_t* counter;  // zero between launches
+};
+hipError_t launch_breed(int dtype, const BreedArgs& a, DevState* st, hipStream_t s);
 
-hipError_t launch_breed(const float* pop, const double* fit, const int* elite_idx, float* next,
-                        int P, int L, int E, int n_children, int k, uint64_t thr_c,
-                        uint64_t thr_m, float sigma, uint64_t seed, const DevState* st,
-                        hipStream_t s);
+// Population copies in and out of pop[g & 1] (dir 0: out to dst, 1: in from src).
+hipError_t launch_pop_copy(float* pop0, float* pop1, const DevState* st, float* ext, int64_t n,
+                           int dir, hipStream_t s);
 
-hipError_t launch_commit(const float* next, float* pop, int64_t count, DevState* st,
-                         hipStream_t s);
-
-hipError_t launch_state_init(DevState* st, hipStream_t s);
+hipError_t launch_state_init(DevState* st, uint32_t* counters, int n_counters, hipStream_t s);
 hipError_t launch_run_arm(DevState* st, int max_generations, double threshold, hipStream_t s);
 hipError_t launch_run_disarm(DevState* st, hipStream_t s);
 

@@ -1,0 +1,120 @@
+// Block-level ranking and best tracking, shared by the standalone rank kernel
+// and the tail of the fitness kernels.
+//
+// Order (Sec. 3 elitism with a total order): higher fitness first, ties to
+// the lower index, NaN ranks last.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "game_internal.hpp"
+
+namespace game {
+
+struct Ranked {
+  double key;
+  int idx;
+};
+__device__ __forceinline__ bool better(const Ranked& a, const Ranked& b) {
+  return a.key > b.key || (a.key == b.key && a.idx < b.idx);
+}
+__device__ __forceinline__ double rank_key(double f) { return isnan(f) ? -INFINITY : f; }
+
+// Loads and stores of values another workgroup of the same launch produces or
+// consumes: agent-scope atomics, which go through to the device-coherent
+// level instead of an XCD's L2 (no cache invalidation needed).
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Top n_top indices of fit[0..P) by repeated arg-max, computed by one
+// workgroup of kThreads threads (all of which must call this).  kAgent: fit
+// was written earlier in the same launch by other workgroups.
+template <int kThreads, bool kAgent = false>
+__device__ void block_topk(const double* __restrict__ fit, int P, int n_top, int* __restrict__ top) {
+  __shared__ int chosen[kMaxElite];
+  __shared__ double wkey[kThreads / 64];
+  __shared__ int widx[kThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = 0; e < n_top; ++e) {
+    Ranked best{-INFINITY, 0x7fffffff};
+    for (int i = tid; i < P; i += kThreads) {
+      bool taken = false;
+      for (int q = 0; q < e; ++q) taken |= (chosen[q] == i);
+      if (taken) continue;
+      const Ranked c{rank_key(kAgent ? ld_agent(fit + i) : fit[i]), i};
+      if (better(c, best)) best = c;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const Ranked o{__shfl_xor(best.key, off), __shfl_xor(best.idx, off)};
+      if (better(o, best)) best = o;
+    }
+    if (lane == 0) {
+      wkey[wave] = best.key;
+      widx[wave] = best.idx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      Ranked b{wkey[0], widx[0]};
+      for (int q = 1; q < kThreads / 64; ++q) {
+        const Ranked o{wkey[q], widx[q]};
+        if (better(o, b)) b = o;
+      }
+      chosen[e] = b.idx;
+      top[e] = b.idx;
+    }
+    __syncthreads();
+  }
+}
+
+// Keep the best chromosome seen (strictly lower MSE replaces it) and, while a
+// run is active, decide whether the run stops after this generation.  `top`
+// holds the generation's ranking (written by this workgroup); mse and miscls
+// were written by other workgroups of the same launch.  Every thread of the
+// workgroup calls this.
+__device__ inline void track_best(DevState* st, const int* __restrict__ top,
+                                  const double* __restrict__ mse, const double* __restrict__ miscls,
+                                  const float* __restrict__ pop, int L, float* __restrict__ best) {
+  __shared__ int s_improve;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int b = top[0];
+    s_improve = (!st->have_best || ld_agent(mse + b) < st->best_mse) ? 1 : 0;
+  }
+  __syncthreads();
+  const int b = top[0];
+  if (s_improve)
+    for (int l = threadIdx.x; l < L; l += blockDim.x) best[l] = pop[(int64_t)b * L + l];
+  if (threadIdx.x == 0) {
+    const double m = ld_agent(mse + b);
+    st->best_index = b;
+    if (s_improve) {
+      st->have_best = 1;
+      st->best_mse = m;
+      st->best_fitness = 1.0 - m;
+      st->best_miscls = ld_agent(miscls + b);
+    }
+    if (st->run_active) {
+      if (st->best_mse <= st->mse_threshold) {
+        st->stopped = 1;
+        st->stop_reason = GAME_STOP_THRESHOLD;
+      } else if (st->generation + 1 >= st->end_generation) {
+        st->stopped = 1;
+        st->stop_reason = GAME_STOP_MAX_GEN;
+      }
+    }
+  }
+}
+
+}  // namespace game

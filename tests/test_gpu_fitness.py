@@ -23,6 +23,9 @@ RTOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-5, "f16": 2e-5}
 
 
 def make_data(task, N, F, seed):
+    if task == "classification-soft":
+        X, _ = synth.classification_dataset(N, F, seed=seed)
+        return X, np.random.default_rng(seed).uniform(0.0, 1.0, N)
     if task == "classification":
         X, t = synth.classification_dataset(N, F, seed=seed)
     else:
@@ -79,6 +82,7 @@ CASES = [
     ("legendre", "f16", "classification", 0, 2049, 16, 8, 257),
     ("trig", "bf16", "regression", 1, 1500, 10, 6, 200),
     ("chebyshev", "f16", "regression", 0, 500, 3, 5, 31),
+    ("trig", "f32", "classification-soft", 1, 1000, 6, 4, 150),   # targets in [0, 1]
 ]
 
 
@@ -88,6 +92,7 @@ def test_fitness_matches_oracle(case):
     from paper_1211_5481_amd import Config, Game
     basis, dtype, task, bias, N, F, D, P = case
     X, t = make_data(task, N, F, seed=N + F)
+    task = task.replace("-soft", "")
     cfg = Config(n_patterns=N, n_features=F, degree=D, basis=basis, task=task, dtype=dtype,
                  bias=bias, pop_size=P, elitism=min(2, P), seed=5)
     io = cfg.io_dtype

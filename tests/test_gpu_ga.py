@@ -82,3 +82,25 @@ def test_step_after_eval_uses_internal_fitness():
     want = ga.ga_step(pop, fit_h, 0, cfg.seed)
     assert np.array_equal(bits(host(g.population)), bits(want))
     g.close()
+
+
+def test_set_population_then_evolve_from_odd_generation():
+    """Populations written in after an odd number of generations (the second
+    population buffer is current) evolve exactly like the oracle."""
+    torch = require_gpu()
+    g, cfg = make_game(24, 10, seed=77)
+    fit0 = synth.random_fitness(24, seed=1)
+    g.step(dev(fit0, torch.float64))                       # generation 1: buffers swapped
+    mine = synth.random_population(24, 10, seed=5)
+    g.population = dev(mine, torch.float32)
+    assert np.array_equal(bits(host(g.population)), bits(mine))
+    fit1 = synth.random_fitness(24, seed=2, n_ties=5)
+    announce("set population at generation 1, then step")
+    g.step(dev(fit1, torch.float64))
+    want = ga.ga_step(mine, fit1, 1, cfg.seed)
+    assert np.array_equal(bits(host(g.population)), bits(want))
+    # the fitness path sees the written population too
+    mse, _, _ = g.eval_fitness()
+    ref, _, _ = g.eval_fitness(dev(want, torch.float32))
+    assert np.array_equal(host(mse), host(ref))
+    g.close()

@@ -203,3 +203,16 @@ def test_quantize_round_to_nearest_even():
     h = model.quantize(v, "f16")
     assert h[2] == 1.0 and h[3] == 1.0 + 2.0 ** -9
     assert model.quantize(v, "f32")[4] == float(np.float32(0.1))
+
+
+def test_classification_compares_with_class_labels():
+    # classification scores the sigmoid output against the label [t >= 0.5]
+    rng = np.random.default_rng(4)
+    X = rng.uniform(-1, 1, (50, 3))
+    t_soft = rng.uniform(0, 1, 50)
+    t_lab = (t_soft >= 0.5).astype(np.float64)
+    G = rng.uniform(-1, 1, (4, 6))
+    a = model.evaluate(X, t_soft, G, "legendre", 2, "classification")
+    b = model.evaluate(X, t_lab, G, "legendre", 2, "classification")
+    np.testing.assert_array_equal(a["mse"], b["mse"])
+    np.testing.assert_array_equal(a["miscls"], b["miscls"])
