@@ -101,6 +101,44 @@ def cpu_baseline(meta, X, t, dtype, seconds: float):
                       f"single-threaded"}
 
 
+def time_to_mse(args):
+    """Plain FP32 run for G generations -> its final best MSE; then BF16 and
+    FP16 runs (top-2 re-scored in FP32 every generation) until their FP32
+    best MSE reaches that value."""
+    import torch
+    from paper_1211_5481_amd import Config, Game
+    meta, X, t = workload(args.workload, "f32")
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    td = torch.tensor(t, dtype=torch.float32, device="cuda")
+    base = dict(n_patterns=meta["N"], n_features=meta["F"], degree=meta["D"], basis=meta["basis"],
+                task=meta["task"], pop_size=meta["P"], seed=meta["ga_seed"])
+    out = {"metric": "time to the plain FP32 run's final best MSE", "workload": meta["workload"]}
+
+    def timed_run(cfg):
+        g = Game(cfg, Xd, td)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = g.run()
+        el = time.perf_counter() - t0
+        g.close()
+        return r, el
+
+    r, el = timed_run(Config(**base, dtype="f32", max_generations=args.generations,
+                             mse_threshold=0.0))
+    target = r["best_mse"]
+    out["f32"] = {"generations": r["generations"], "seconds": el, "best_mse": target,
+                  "evals_per_s": meta["P"] * meta["N"] * r["generations"] / el}
+    for d in ("bf16", "f16"):
+        r, el = timed_run(Config(**base, dtype=d, rescore_top=2, mse_threshold=target,
+                                 max_generations=4 * args.generations))
+        out[d] = {"generations": r["generations"], "seconds": el, "best_mse_fp32": r["best_mse"],
+                  "reached": r["stop_reason"] == "threshold",
+                  "evals_per_s": meta["P"] * meta["N"] * r["generations"] / el,
+                  "speedup_vs_f32": out["f32"]["seconds"] / el}
+        print(f"[bench] {d}: {out[d]}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +148,10 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--time-to-mse", action="store_true",
+                    help="precision forms: generations and wall time of BF16/FP16 runs (elites "
+                         "re-scored in FP32) to reach the final best MSE of a plain FP32 run")
+    ap.add_argument("--generations", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -133,6 +175,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "elementwise copy", "bytes_read": x.numel() * 4,
                           "bytes_written": y.numel() * 4, "launches": 3}))
+        return
+    if args.time_to_mse:
+        print(json.dumps(time_to_mse(args)), flush=True)
         return
     meta, X, t = workload(args.workload, args.dtype)
     io = torch.float64 if args.dtype == "f64" else torch.float32

@@ -95,6 +95,10 @@ typedef struct {
   int32_t  selection;       /* game_selection                                     */
   int32_t  tournament_k;    /* k in [1, 16]                                       */
   int32_t  max_generations; /* >= 1, used by game_run                             */
+  int32_t  rescore_top;     /* 0..8: every generation re-scores the top-k ranked   */
+                            /* chromosomes in float32 and tracks the best and     */
+                            /* tests the stop rule on those float32 MSEs (meant   */
+                            /* for BF16/F16; not available with F64)              */
   double   p_crossover;     /* [0, 1] per child pair                              */
   double   p_mutation;      /* [0, 1] per gene                                    */
   double   mutation_sigma;  /* >= 0, standard deviation of the Gaussian step      */
@@ -201,6 +205,18 @@ game_status game_advance(game_ctx* ctx, int32_t n_generations);
  * generation; no evolution follows the generation that stops the run.
  */
 game_status game_run(game_ctx* ctx, game_result* out);
+
+/*
+ * Float32 re-score (the precision forms' check of their elites): MSE and
+ * misclassification rate of n <= 8 chromosomes with float32 basis values
+ * (recomputed from the patterns) and float32 arithmetic, async.
+ *   genes_dev: n x L floats (device), or NULL for the current population's n
+ *              best by the last ranking (GAME_E_STATE if none).
+ *   mse_dev, miscls_dev: n doubles (device) or NULL.
+ * GAME_E_UNSUPPORTED for F64 contexts; n * L must be <= 16384.
+ */
+game_status game_rescore(game_ctx* ctx, const float* genes_dev, int32_t n, double* mse_dev,
+                         double* miscls_dev);
 
 /* Copy the population out / in: P x L floats, device pointers, async. */
 game_status game_get_population(game_ctx* ctx, float* genes_dev);

@@ -33,6 +33,7 @@ class GameConfig(C.Structure):
         ("selection", C.c_int32),
         ("tournament_k", C.c_int32),
         ("max_generations", C.c_int32),
+        ("rescore_top", C.c_int32),
         ("p_crossover", C.c_double),
         ("p_mutation", C.c_double),
         ("mutation_sigma", C.c_double),
@@ -89,6 +90,7 @@ SIGNATURES = {
     "game_step": (C.c_int, [_VP, _VP]),
     "game_advance": (C.c_int, [_VP, C.c_int32]),
     "game_run": (C.c_int, [_VP, C.POINTER(GameResult)]),
+    "game_rescore": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP]),
     "game_get_population": (C.c_int, [_VP, _VP]),
     "game_set_population": (C.c_int, [_VP, _VP]),
     "game_get_state": (C.c_int, [_VP, C.POINTER(GameState), _VP]),

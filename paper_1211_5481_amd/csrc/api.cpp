@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <algorithm>
 
 #include "game.h"
 #include "game_internal.hpp"
@@ -48,6 +49,8 @@ struct game_ctx {
   float *pop0, *pop1, *best;  // generation g lives in pop[g & 1]
   double *psse, *mse, *miscls, *fit;
   uint32_t *pmiss, *counters;
+  float* xf;      // float32 patterns (16-bit and float32 forms)
+  double* rpart;  // re-score partials
   int* elite;
   DevState* state;
   uint64_t thr_c, thr_m;
@@ -79,6 +82,7 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   if (!std::isfinite(c->mutation_sigma) || c->mutation_sigma < 0) return bad("mutation_sigma must be finite and >= 0");
   if (c->max_generations < 1) return bad("max_generations must be >= 1");
   if (std::isnan(c->mse_threshold)) return bad("mse_threshold is NaN");
+  if (c->rescore_top < 0 || c->rescore_top > kMaxRescore) return bad("rescore_top must be in [0, 8]");
   const int64_t B = c->basis == GAME_BASIS_TRIG ? 2 : 1;
   const int64_t K = B * c->degree;
   const int64_t M = (int64_t)c->n_features * K;
@@ -89,6 +93,11 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   if (P < 1 || P > (1 << 24)) return bad("pop_size out of range");
   if (c->elitism < 0 || c->elitism > P || c->elitism > kMaxElite) return bad("elitism must be in [0, min(P, 64)]");
   int64_t n_off = c->n_offspring == 0 ? P - c->elitism : c->n_offspring;
+  if (c->rescore_top > 0 && c->dtype == GAME_F64) {
+    std::snprintf(err, errlen, "rescore_top is not available with F64");
+    return GAME_E_UNSUPPORTED;
+  }
+  if (c->rescore_top > P) return bad("rescore_top must not exceed the population size");
   if (n_off != P - c->elitism) {
     std::snprintf(err, errlen, "n_offspring other than P - elitism is not available");
     return GAME_E_UNSUPPORTED;
@@ -132,7 +141,12 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   p->off_state = take(sizeof(DevState));
   p->off_best = take((size_t)L * 4);
   p->n_pt_cap = p->P_max_pad / p->tile_p;
-  p->off_cnt = take((size_t)(p->n_pt_cap + 2) * 4);
+  p->n_counters = p->n_pt_cap + 3;
+  p->off_cnt = take((size_t)p->n_counters * 4);
+  // float32 copy of the patterns and re-score partials (not kept for F64)
+  const bool f32x = c->dtype != GAME_F64;
+  p->off_x = take(f32x ? (size_t)p->N * c->n_features * 4 : 0);
+  p->off_rpart = take(f32x ? (size_t)rescore_grid() * 2 * kMaxRescore * 8 : 0);
   p->total = off;
   return GAME_OK;
 }
@@ -203,7 +217,8 @@ FitTail make_tail(game_ctx* c, int P_eval, bool population, double* mse2, double
     t.mse = c->mse;
     t.miscls = c->miscls;
     t.fit = c->fit;
-    t.n_top = p.E > 0 ? p.E : 1;
+    t.n_top = std::max(p.E > 0 ? p.E : 1, c->cfg.rescore_top);
+    t.track = c->cfg.rescore_top > 0 ? 0 : 1;
     t.top = c->elite;
     t.st = c->state;
     t.pop0 = c->pop0;
@@ -236,11 +251,27 @@ game_status enqueue_fitness(game_ctx* c, int P_eval, const FitTail& tail, hipStr
              "fitness");
 }
 
-// Evaluate the current population, rank it and track the best chromosome.
+game_status enqueue_rescore(game_ctx* c, const float* genes, int n, double* mse, double* miscls,
+                            bool population, hipStream_t s) {
+  const Plan& p = c->plan;
+  return dev(c,
+             launch_rescore(c->xf, reinterpret_cast<const float*>(c->tvec), p.N,
+                            c->cfg.n_features, c->cfg.degree, p.K, c->cfg.basis, p.M, p.L,
+                            c->cfg.bias, c->cfg.task, genes, n, c->pop0, c->pop1, c->elite,
+                            c->rpart, c->counters + p.n_pt_cap + 2, mse, miscls, c->state,
+                            population ? c->state : nullptr, c->best, s),
+             "rescore");
+}
+
+// Evaluate the current population, rank it and track the best chromosome
+// (by the float32 re-score of the top-k when rescore_top > 0).
 game_status enqueue_eval_population(game_ctx* c, double* mse, double* miscls, double* fit,
                                     hipStream_t s) {
   if (!c->tile_fresh) GAME_TRY(enqueue_pack_population(c, s));
-  return enqueue_fitness(c, c->plan.P, make_tail(c, c->plan.P, true, mse, miscls, fit), s);
+  GAME_TRY(enqueue_fitness(c, c->plan.P, make_tail(c, c->plan.P, true, mse, miscls, fit), s));
+  if (c->cfg.rescore_top > 0)
+    GAME_TRY(enqueue_rescore(c, nullptr, c->cfg.rescore_top, nullptr, nullptr, true, s));
+  return GAME_OK;
 }
 
 game_status enqueue_evolve(game_ctx* c, const double* fit, hipStream_t s) {
@@ -394,6 +425,8 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
   c->pop0 = reinterpret_cast<float*>(c->ws + p.off_pop0);
   c->pop1 = reinterpret_cast<float*>(c->ws + p.off_pop1);
   c->counters = reinterpret_cast<uint32_t*>(c->ws + p.off_cnt);
+  c->xf = reinterpret_cast<float*>(c->ws + p.off_x);
+  c->rpart = reinterpret_cast<double*>(c->ws + p.off_rpart);
   c->psse = reinterpret_cast<double*>(c->ws + p.off_psse);
   c->pmiss = reinterpret_cast<uint32_t*>(c->ws + p.off_pmiss);
   c->mse = reinterpret_cast<double*>(c->ws + p.off_mse);
@@ -409,7 +442,10 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
   if (r == GAME_OK) r = dev(c, launch_basis(cfg, X, p.N, p.N_pad, c->phi, p.M_pad, st), "basis");
   if (r == GAME_OK) r = dev(c, launch_copy_targets(cfg->dtype, t, p.N, p.N_pad, c->tvec, st), "targets");
   if (r == GAME_OK) r = dev(c, launch_init_population(c->pop0, p.P, p.L, cfg->seed, st), "init population");
-  if (r == GAME_OK) r = dev(c, launch_state_init(c->state, c->counters, p.n_pt_cap + 2, st), "state init");
+  if (r == GAME_OK) r = dev(c, launch_state_init(c->state, c->counters, p.n_counters, st), "state init");
+  if (r == GAME_OK && cfg->dtype != GAME_F64)
+    r = dev(c, hipMemcpyAsync(c->xf, X, (size_t)p.N * cfg->n_features * 4, hipMemcpyDeviceToDevice, st),
+            "pattern copy");
   if (r == GAME_OK) r = enqueue_pack_population(c, st);
   if (r != GAME_OK) {
     delete c;
@@ -512,6 +548,18 @@ game_status game_run(game_ctx* c, game_result* res) {
   res->stop_reason = s.stop_reason;
   c->have_eval = true;  // the population is the last evaluated generation
   return GAME_OK;
+}
+
+game_status game_rescore(game_ctx* c, const float* genes, int32_t n, double* mse, double* miscls) {
+  GAME_TRY(check_ctx(c));
+  if (c->cfg.dtype == GAME_F64) return fail(GAME_E_UNSUPPORTED, "game_rescore is not available with F64");
+  if (n < 1 || n > kMaxRescore || n > c->plan.P) return fail(GAME_E_INVALID, "n must be in [1, min(8, P)]");
+  if ((int64_t)n * c->plan.L > 16384) return fail(GAME_E_INVALID, "n * L must be <= 16384");
+  if (!genes && !c->have_eval)
+    return fail(GAME_E_STATE, "game_rescore(NULL) needs a ranking of the current population");
+  const int ranked = std::max(c->plan.E > 0 ? c->plan.E : 1, c->cfg.rescore_top);
+  if (!genes && n > ranked) return fail(GAME_E_INVALID, "n exceeds the ranked elites (%d)", ranked);
+  return enqueue_rescore(c, genes, n, mse, miscls, false, c->stream);
 }
 
 game_status game_get_population(game_ctx* c, float* genes) {

@@ -199,8 +199,10 @@ __device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, i
   if (!s_flag) return;
   block_topk<256, true>(t.fit, t.P, t.n_top, t.top);
   __syncthreads();
-  const float* pop = (t.st->generation & 1) ? t.pop1 : t.pop0;
-  track_best(t.st, t.top, t.mse, t.miscls, pop, t.L, t.best);
+  if (t.track) {
+    const float* pop = (t.st->generation & 1) ? t.pop1 : t.pop0;
+    track_best(t.st, t.top, t.mse, t.miscls, pop, t.L, t.best);
+  }
   if (threadIdx.x == 0) t.counters[t.n_pt_cap] = 0u;
 }
 

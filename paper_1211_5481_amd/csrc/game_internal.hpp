@@ -13,6 +13,7 @@ namespace game {
 constexpr int kMaxElite = 64;      // elitism limit (top-E ranking in one workgroup)
 constexpr int kMaxTournament = 16; // tournament draws addressable by the counter layout
 constexpr int kMaxGenes = 4096;    // L limit (keeps every index well inside int32)
+constexpr int kMaxRescore = 8;     // chromosomes one float32 re-score launch handles
 
 // Philox stream tags: the fourth counter word of every draw.
 enum : uint32_t {
@@ -87,7 +88,8 @@ struct FitTail {
   double invN;
   double *mse, *miscls, *fit;     // internal results or null
   double *mse2, *miscls2, *fit2;  // caller results or null
-  int n_top;            // > 0: rank the population (top n_top) and track the best
+  int n_top;            // > 0: rank the population (top n_top)
+  int track;            // with n_top: track the best chromosome and test the stop rule
   int* top;
   DevState* st;
   const float* pop0;    // population buffers; generation g lives in pop[g & 1]
@@ -109,8 +111,10 @@ struct Plan {
   size_t acc;                  // bytes per t / bias element (8 for F64 else 4)
   // workspace offsets
   int n_pt_cap;                // chromosome tiles at P_max
+  int n_counters;              // arrival counters: tiles, tiles done, breed, re-score
   size_t off_phi, off_t, off_tile, off_bias, off_pop0, off_pop1, off_psse, off_pmiss;
-  size_t off_mse, off_miscls, off_fit, off_elite, off_state, off_best, off_cnt, total;
+  size_t off_mse, off_miscls, off_fit, off_elite, off_state, off_best, off_cnt;
+  size_t off_x, off_rpart, total;   // float32 patterns and re-score partials (16-bit forms)
 };
 
 game_status make_plan(const game_config* cfg, Plan* p, char* err, size_t errlen);
@@ -171,6 +175,13 @@ hipError_t launch_breed(int dtype, const BreedArgs& a, DevState* st, hipStream_t
 // Population copies in and out of pop[g & 1] (dir 0: out to dst, 1: in from src).
 hipError_t launch_pop_copy(float* pop0, float* pop1, const DevState* st, float* ext, int64_t n,
                            int dir, hipStream_t s);
+
+int rescore_grid();
+hipError_t launch_rescore(const float* X, const float* t, int64_t N, int F, int D, int K, int basis,
+                          int M, int L, int bias, int task, const float* genes, int n,
+                          const float* pop0, const float* pop1, const int* top, double* part,
+                          uint32_t* counter, double* mse, double* miscls, const DevState* sel,
+                          DevState* st, float* best, hipStream_t s);
 
 hipError_t launch_state_init(DevState* st, uint32_t* counters, int n_counters, hipStream_t s);
 hipError_t launch_run_arm(DevState* st, int max_generations, double threshold, hipStream_t s);

@@ -1,0 +1,251 @@
+// Float32 re-score of a few chromosomes (the elites of a 16-bit run).
+//
+// The BF16/FP16 forms rank the population with 16-bit Phi and genes; the
+// chromosomes that matter (the elites, and in the end the best one) are
+// scored again here with float32 basis values and float32 arithmetic: each
+// thread walks patterns, recomputes the pattern's basis row from x (double
+// recurrence rounded to float32, as the FP32 path stores Phi), forms
+// z = sum_m phi_m g_m in float32 for every chromosome, and adds the error
+// (eq. 3; classification against the class label) in double.  Block sums
+// are combined in a fixed order by the last workgroup to arrive, so results
+// are bit-reproducible.  For a population evaluation the same workgroup then
+// tracks the best chromosome by the float32 MSE and applies the stop test.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "game_internal.hpp"
+#include "select.hpp"
+
+namespace game {
+namespace {
+
+constexpr int kThreads = 256;
+
+struct RescoreArgs {
+  const float* X;        // N x F, float32 copy of the patterns
+  const float* t;        // N_pad targets (float32)
+  int64_t N;
+  int F, D, K, basis, M, L, bias, task;
+  const float* genes;    // n x L chromosomes (explicit set), or null: population elites
+  int n;                 // chromosomes to score (<= kMaxRescore)
+  const float* pop0;     // population buffers (generation parity) when genes is null
+  const float* pop1;
+  const int* top;        // ranking of the population when genes is null
+  double* part;          // [grid][2 * kMaxRescore] block partials (sse, misses)
+  uint32_t* counter;     // zero between launches
+  double* mse;           // n results (device) or null
+  double* miscls;
+  const DevState* sel;   // generation parity for the population buffers (never null)
+  DevState* st;          // tracking mode: best tracking + stop test; else null
+  float* best;           // best genes (tracking mode)
+};
+
+// One feature value -> its K basis values (double recurrence), each handed to
+// put(k, value) as soon as it is formed.
+template <typename Put>
+__device__ __forceinline__ void basis_row(int basis, int D, double x, Put put) {
+  if (basis == GAME_BASIS_POWER) {
+    double p = x;
+    for (int k = 0; k < D; ++k) {
+      put(k, p);
+      p *= x;
+    }
+  } else if (basis == GAME_BASIS_CHEBYSHEV) {
+    double prev = 1.0, cur = x;
+    for (int k = 0; k < D; ++k) {
+      put(k, cur);
+      const double nxt = 2.0 * x * cur - prev;
+      prev = cur;
+      cur = nxt;
+    }
+  } else if (basis == GAME_BASIS_LEGENDRE) {
+    double prev = 1.0, cur = x;
+    for (int k = 0; k < D; ++k) {
+      put(k, cur);
+      const double j = (double)(k + 1);
+      const double nxt = ((2.0 * j + 1.0) * x * cur - j * prev) / (j + 1.0);
+      prev = cur;
+      cur = nxt;
+    }
+  } else {
+    double s1, c1;
+    sincos(x, &s1, &c1);
+    double cp = 1.0, cc = c1, sp = 0.0, sc = s1;
+    for (int k = 0; k < D; ++k) {
+      put(k, cc);
+      put(D + k, sc);
+      const double cn = 2.0 * c1 * cc - cp;
+      const double sn = 2.0 * c1 * sc - sp;
+      cp = cc;
+      cc = cn;
+      sp = sc;
+      sc = sn;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
+  if (run_halted(a.st)) return;
+  extern __shared__ float g_lds[];  // n x L genes
+  __shared__ double s_red[kThreads / 64][2 * kMaxRescore];
+  __shared__ int s_flag;
+  __shared__ int s_rows[kMaxRescore];
+  const int tid = threadIdx.x;
+  const float* src = a.genes;
+  if (!src) src = (a.sel->generation & 1) ? a.pop1 : a.pop0;
+  if (tid < a.n) s_rows[tid] = a.genes ? tid : a.top[tid];
+  __syncthreads();
+  for (int i = tid; i < a.n * a.L; i += kThreads) {
+    const int e = i / a.L, l = i - e * a.L;
+    g_lds[i] = src[(int64_t)s_rows[e] * a.L + l];
+  }
+  __syncthreads();
+
+  double sse[kMaxRescore];
+  double mis[kMaxRescore];
+#pragma unroll
+  for (int e = 0; e < kMaxRescore; ++e) {
+    sse[e] = 0.0;
+    mis[e] = 0.0;
+  }
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t nrow = (int64_t)blockIdx.x * kThreads + tid; nrow < a.N; nrow += stride) {
+    float z[kMaxRescore];
+#pragma unroll
+    for (int e = 0; e < kMaxRescore; ++e) z[e] = 0.0f;
+    for (int i = 0; i < a.F; ++i) {
+      const float* gi = g_lds + i * a.K;
+      basis_row(a.basis, a.D, (double)a.X[nrow * a.F + i], [&](int k, double val) {
+        const float vf = (float)val;
+#pragma unroll
+        for (int e = 0; e < kMaxRescore; ++e)
+          if (e < a.n) z[e] = fmaf(vf, gi[e * a.L + k], z[e]);
+      });
+    }
+    const float tn = a.t[nrow];
+    const float lab = tn >= 0.5f ? 1.0f : 0.0f;
+#pragma unroll
+    for (int e = 0; e < kMaxRescore; ++e) {
+      if (e >= a.n) continue;
+      const float ze = a.bias ? z[e] + g_lds[e * a.L + a.M] : z[e];
+      float d;
+      if (a.task == GAME_CLASSIFICATION) {
+        d = lab - 1.0f / (1.0f + expf(-ze));
+        mis[e] += ((ze >= 0.0f) != (lab > 0.5f)) ? 1.0 : 0.0;
+      } else {
+        d = tn - ze;
+      }
+      sse[e] += (double)(d * d);
+    }
+  }
+  // fixed-order block reduction: wave shuffle tree, then waves in order
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int e = 0; e < kMaxRescore; ++e) {
+    for (int off = 32; off > 0; off >>= 1) {
+      sse[e] += __shfl_xor(sse[e], off);
+      mis[e] += __shfl_xor(mis[e], off);
+    }
+    if (lane == 0) {
+      s_red[wave][e] = sse[e];
+      s_red[wave][kMaxRescore + e] = mis[e];
+    }
+  }
+  __syncthreads();
+  if (tid < 2 * kMaxRescore) {
+    double s = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) s += s_red[w][tid];
+    st_agent(a.part + (int64_t)blockIdx.x * 2 * kMaxRescore + tid, s);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (tid == 0) s_flag = atomicAdd(a.counter, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!s_flag) return;
+  // last workgroup: thread t adds blocks t, t + 256, ... (in that order), then
+  // thread v adds the 256 thread sums of value v in thread order
+  __shared__ double s_all[kThreads][2 * kMaxRescore];
+  __shared__ double s_mse[kMaxRescore], s_mis[kMaxRescore];
+  {
+    double acc[2 * kMaxRescore];
+#pragma unroll
+    for (int v = 0; v < 2 * kMaxRescore; ++v) acc[v] = 0.0;
+    for (unsigned b = tid; b < gridDim.x; b += kThreads) {
+#pragma unroll
+      for (int v = 0; v < 2 * kMaxRescore; ++v)
+        acc[v] += ld_agent(a.part + (int64_t)b * 2 * kMaxRescore + v);
+    }
+#pragma unroll
+    for (int v = 0; v < 2 * kMaxRescore; ++v) s_all[tid][v] = acc[v];
+  }
+  __syncthreads();
+  if (tid < 2 * kMaxRescore) {
+    double s = 0.0;
+    for (int q = 0; q < kThreads; ++q) s += s_all[q][tid];
+    if (tid < kMaxRescore)
+      s_mse[tid] = s / (double)a.N;
+    else
+      s_mis[tid - kMaxRescore] = s / (double)a.N;
+  }
+  __syncthreads();
+  if (tid < a.n) {
+    if (a.mse) a.mse[tid] = s_mse[tid];
+    if (a.miscls) a.miscls[tid] = s_mis[tid];
+  }
+  if (tid == 0) *a.counter = 0u;
+  if (!a.st || a.genes) return;
+  // population mode: best of the re-scored elites (lowest float32 MSE, ties
+  // to the better-ranked one) becomes the tracked best; then the stop test
+  __shared__ int s_b, s_improve;
+  if (tid == 0) {
+    int b = 0;
+    for (int e = 1; e < a.n; ++e)
+      if (s_mse[e] < s_mse[b]) b = e;
+    s_b = b;
+    s_improve = (!a.st->have_best || s_mse[b] < a.st->best_mse) ? 1 : 0;
+  }
+  __syncthreads();
+  if (s_improve)
+    for (int l = tid; l < a.L; l += kThreads) a.best[l] = g_lds[s_b * a.L + l];
+  if (tid == 0) {
+    DevState* st = a.st;
+    st->best_index = s_rows[s_b];
+    if (s_improve) {
+      st->have_best = 1;
+      st->best_mse = s_mse[s_b];
+      st->best_fitness = 1.0 - s_mse[s_b];
+      st->best_miscls = s_mis[s_b];
+    }
+    if (st->run_active) {
+      if (st->best_mse <= st->mse_threshold) {
+        st->stopped = 1;
+        st->stop_reason = GAME_STOP_THRESHOLD;
+      } else if (st->generation + 1 >= st->end_generation) {
+        st->stopped = 1;
+        st->stop_reason = GAME_STOP_MAX_GEN;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int rescore_grid() { return 1024; }
+
+hipError_t launch_rescore(const float* X, const float* t, int64_t N, int F, int D, int K, int basis,
+                          int M, int L, int bias, int task, const float* genes, int n,
+                          const float* pop0, const float* pop1, const int* top, double* part,
+                          uint32_t* counter, double* mse, double* miscls, const DevState* sel,
+                          DevState* st, float* best, hipStream_t s) {
+  RescoreArgs a{X, t, N, F, D, K, basis, M, L, bias, task, genes, n, pop0, pop1, top,
+                part, counter, mse, miscls, sel, st, best};
+  if (!genes && !sel) return hipErrorInvalidValue;
+  if (n < 1 || n > kMaxRescore) return hipErrorInvalidValue;
+  const size_t lds = (size_t)n * L * sizeof(float);
+  if (lds > 65536) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rescore_kernel, dim3(rescore_grid()), dim3(kThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace game

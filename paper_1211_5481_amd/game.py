@@ -30,6 +30,7 @@ class Config:
     elitism: int = 2
     tournament_k: int = 3
     max_generations: int = 100
+    rescore_top: int = 0              # per-generation float32 re-score of the top-k
     p_crossover: float = 0.9
     p_mutation: float = 0.05
     mutation_sigma: float = 0.1
@@ -52,6 +53,7 @@ class Config:
         c.selection = 0
         c.tournament_k = int(self.tournament_k)
         c.max_generations = int(self.max_generations)
+        c.rescore_top = int(self.rescore_top)
         c.p_crossover = float(self.p_crossover)
         c.p_mutation = float(self.p_mutation)
         c.mutation_sigma = float(self.mutation_sigma)
@@ -177,6 +179,21 @@ class Game:
         return dict(best_mse=r.best_mse, best_fitness=r.best_fitness, best_miscls=r.best_miscls,
                     generations=r.generations, stop_reason=L.STOP.get(r.stop_reason),
                     best_genes=np.frombuffer(genes, dtype=np.float32).copy())
+
+    def rescore(self, genes=None, n: int = None):
+        """Float32 (mse, miscls) of n chromosomes: genes (n x L) or the population's n best."""
+        torch = _torch()
+        if genes is not None:
+            genes = genes.contiguous()
+            if genes.dtype != torch.float32 or genes.dim() != 2 or genes.shape[1] != self.L:
+                raise ValueError("genes must be a float32 n x L CUDA tensor")
+            n = genes.shape[0]
+        elif n is None:
+            n = 1
+        out = torch.empty((2, n), dtype=torch.float64, device=self.device)
+        L.check(L.lib().game_rescore(self._ctx, _ptr(genes), int(n), _ptr(out[0]), _ptr(out[1])),
+                "game_rescore")
+        return out[0], out[1]
 
     @property
     def population(self):
