@@ -195,3 +195,21 @@ def ga_step(pop, fit, g: int, seed: int, elitism: int = 2, **kw) -> np.ndarray:
     if P > elitism:
         new[elitism:] = make_offspring(pop, fit, g, P - elitism, seed, **kw)
     return new
+
+
+def merge_survivors(pop, fit_pop, cand, fit_cand, elitism: int):
+    """Next population of the offspring form: the E best of the current
+    population (unchanged, best first), then the P - E best candidates by
+    exact fitness (descending, ties to the lower candidate index, NaN last).
+    Returns (genes, fitness)."""
+    pop = np.asarray(pop, dtype=np.float32)
+    cand = np.asarray(cand, dtype=np.float32)
+    P = pop.shape[0]
+    if cand.shape[0] < P - elitism:
+        raise ValueError("not enough candidates")
+    keep = elites(fit_pop, elitism)
+    best = rank_order(fit_cand)[:P - elitism]
+    genes = np.concatenate([pop[keep], cand[best]], axis=0)
+    fit = np.concatenate([np.asarray(fit_pop, np.float64)[keep],
+                          np.asarray(fit_cand, np.float64)[best]])
+    return genes, fit
