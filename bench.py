@@ -139,6 +139,65 @@ def time_to_mse(args):
     return out
 
 
+def surrogate_compare(args):
+    """Surrogate form on the 1M-pattern Legendre workload: each generation
+    breeds 8192 offspring.  Plain: all of them evaluated exactly, for G
+    generations -> its final best MSE.  Then the MLP prescreen (top 25 %
+    evaluated exactly, plus a 256-offspring audit) and the random 25 %
+    control run until their best MSE reaches that value."""
+    import numpy as np
+    import torch
+    from paper_1211_5481_amd import Config, Game
+    meta, X, t = workload("c3", "f32")
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    td = torch.tensor(t, dtype=torch.float32, device="cuda")
+    n_off = 8192
+    base = dict(n_patterns=meta["N"], n_features=meta["F"], degree=meta["D"], basis=meta["basis"],
+                task=meta["task"], pop_size=meta["P"], seed=meta["ga_seed"], dtype="f32",
+                n_offspring=n_off)
+    out = {"metric": "generations and wall time to the plain run's final best MSE",
+           "workload": meta["workload"] + f", {n_off} offspring per generation"}
+
+    def timed_run(cfg):
+        g = Game(cfg, Xd, td)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = g.run()
+        el = time.perf_counter() - t0
+        log = g.surrogate_log() if cfg.surrogate == "mlp" else None
+        g.close()
+        return r, el, log
+
+    r, el, _ = timed_run(Config(**base, max_generations=args.generations))
+    target = r["best_mse"]
+    G = r["generations"]
+    exact = n_off * G
+    out["plain"] = {"generations": G, "seconds": el, "best_mse": target,
+                    "generations_per_s": G / el, "exact_evals": exact,
+                    "evals_per_s": float(exact) * meta["N"] / el}
+    print(f"[bench] plain: {out['plain']}", file=sys.stderr, flush=True)
+    for mode in ("mlp", "random"):
+        cfg = Config(**base, surrogate=mode, prescreen_frac=0.25, audit=256, surrogate_hidden=256,
+                     surrogate_buffer=50000, surrogate_batch=1024, mse_threshold=target,
+                     max_generations=4 * args.generations)
+        r, el, log = timed_run(cfg)
+        G = r["generations"]
+        per_gen = 2048 + (256 if mode == "mlp" else 0)
+        rec = {"generations": G, "seconds": el, "reached": r["stop_reason"] == "threshold",
+               "best_mse": r["best_mse"], "generations_per_s": G / el,
+               "exact_evals": per_gen * G, "screened_per_s": n_off * G / el,
+               "evals_per_s": float(per_gen * G) * meta["N"] / el,
+               "speedup_vs_plain": out["plain"]["seconds"] / el}
+        if log is not None and len(log):
+            rec["spearman_audit_mean"] = float(np.mean(log[:, 0]))
+            rec["spearman_audit_last10"] = float(np.mean(log[-10:, 0]))
+            rec["spearman_selected_mean"] = float(np.mean(log[:, 1]))
+            rec["train_loss_last"] = float(log[-1, 2])
+        out[mode] = rec
+        print(f"[bench] {mode}: {rec}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +210,9 @@ def main():
     ap.add_argument("--time-to-mse", action="store_true",
                     help="precision forms: generations and wall time of BF16/FP16 runs (elites "
                          "re-scored in FP32) to reach the final best MSE of a plain FP32 run")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="surrogate form: MLP and random 25 %% prescreens vs exact evaluation of "
+                         "all 8192 offspring, generations and time to the plain run's final MSE")
     ap.add_argument("--generations", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy kernel (HBM counter calibration)")
@@ -178,6 +240,9 @@ def main():
         return
     if args.time_to_mse:
         print(json.dumps(time_to_mse(args)), flush=True)
+        return
+    if args.surrogate:
+        print(json.dumps(surrogate_compare(args)), flush=True)
         return
     meta, X, t = workload(args.workload, args.dtype)
     io = torch.float64 if args.dtype == "f64" else torch.float32

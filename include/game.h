@@ -74,6 +74,13 @@ typedef enum { GAME_F64 = 0, GAME_F32 = 1, GAME_BF16 = 2, GAME_F16 = 3 } game_dt
 
 typedef enum { GAME_SEL_TOURNAMENT = 0 } game_selection;
 
+/* Prescreen of the offspring form.  NONE: every child is evaluated exactly.
+ * MLP: a 2-hidden-layer GELU perceptron trained online (Adam) on the
+ * (chromosome, standardised log MSE) pairs evaluated so far ranks the
+ * children and only the best prescreen_frac are evaluated exactly.
+ * RANDOM: the same number chosen at random (control). */
+typedef enum { GAME_SURROGATE_NONE = 0, GAME_SURROGATE_MLP = 1, GAME_SURROGATE_RANDOM = 2 } game_surrogate;
+
 typedef enum {
   GAME_STOP_NONE = 0,       /* still running / never run                          */
   GAME_STOP_THRESHOLD = 1,  /* best MSE <= mse_threshold                          */
@@ -90,7 +97,11 @@ typedef struct {
   int32_t  dtype;           /* game_dtype                                         */
   int32_t  bias;            /* 0 | 1: gene a_0 stored at index M                  */
   int32_t  pop_size;        /* P; 0 -> B*F + 1 (eq. 4)                            */
-  int32_t  n_offspring;     /* 0 -> P - elitism (generational replacement)        */
+  int32_t  n_offspring;     /* 0 -> P - elitism (generational replacement);       */
+                            /* other values select the offspring form: each       */
+                            /* generation breeds n_offspring children (<= 8192),  */
+                            /* evaluates some exactly and keeps the E elites plus */
+                            /* the best P - E evaluated children                  */
   int32_t  elitism;         /* E in [0, min(P, 64)] (the paper's runs use 2)      */
   int32_t  selection;       /* game_selection                                     */
   int32_t  tournament_k;    /* k in [1, 16]                                       */
@@ -99,6 +110,20 @@ typedef struct {
                             /* chromosomes in float32 and tracks the best and     */
                             /* tests the stop rule on those float32 MSEs (meant   */
                             /* for BF16/F16; not available with F64)              */
+  int32_t  surrogate;       /* offspring form prescreen: game_surrogate           */
+  int32_t  surrogate_hidden;/* hidden width of both MLP layers, 16..1024          */
+  int32_t  surrogate_buffer;/* replay ring capacity (pairs), >= surrogate_batch    */
+  int32_t  surrogate_steps; /* Adam steps per generation                          */
+  int32_t  surrogate_batch; /* minibatch rows                                     */
+  int32_t  audit;           /* MLP prescreen: offspring also evaluated exactly,   */
+                            /* drawn at random each generation, to measure the    */
+                            /* surrogate's rank error (0..4096, capped at         */
+                            /* n_offspring; unused by the other modes)            */
+  double   prescreen_frac;  /* fraction of the offspring evaluated exactly        */
+  double   surrogate_lr;    /* Adam learning rate                                 */
+  double   surrogate_recent;/* fraction of each minibatch drawn from the latest   */
+                            /* generation's exact evaluations, [0, 1]; the rest   */
+                            /* is drawn uniformly from the whole replay buffer    */
   double   p_crossover;     /* [0, 1] per child pair                              */
   double   p_mutation;      /* [0, 1] per gene                                    */
   double   mutation_sigma;  /* >= 0, standard deviation of the Gaussian step      */
@@ -175,7 +200,9 @@ game_status game_init(const game_config* cfg, const void* X_dev, const void* t_d
  * fitness = 1 - MSE).
  *   genes_dev: P x L row-major float chromosomes (device), or NULL for the
  *              current population (then P must equal the population size).
- *   P:         1 <= P <= max(population size, n_offspring).
+ *   P:         1 <= P <= max(population size, n_offspring) in the generational
+ *              form; <= max(population size, children evaluated exactly per
+ *              generation) in the offspring form.
  *   mse_dev, miscls_dev, fitness_dev: P doubles each (device) or NULL.
  * The results for the current population are also kept for game_step(NULL).
  */
@@ -190,6 +217,12 @@ game_status game_eval_fitness(game_ctx* ctx, const float* genes_dev, int32_t P,
  *   fitness_dev: P doubles of the current population (device), or NULL to use
  *                the last game_eval_fitness(NULL) result (GAME_E_STATE if none).
  * Increments the generation counter that keys the random draws.
+ * Offspring form (n_offspring != P - elitism or a surrogate): fitness_dev must
+ * be NULL (GAME_E_UNSUPPORTED otherwise); one call breeds n_offspring children
+ * from the current population, prescreens them (surrogate MLP scores, or a
+ * uniformly random subset), evaluates the chosen ones exactly and keeps the E
+ * elites plus the best P - E of them; with the MLP it also stores the exact
+ * results in the replay buffer and trains on it.
  */
 game_status game_step(game_ctx* ctx, const double* fitness_dev);
 
@@ -217,6 +250,49 @@ game_status game_run(game_ctx* ctx, game_result* out);
  */
 game_status game_rescore(game_ctx* ctx, const float* genes_dev, int32_t n, double* mse_dev,
                          double* miscls_dev);
+
+/*
+ * Offspring form, per generation, blocking: the Spearman rank correlation of
+ * the surrogate's scores with the exact log MSE on the audit sample
+ * (rho_audit) and on the children evaluated exactly (rho_selected), and the
+ * last training loss.  Fills up to n_max records of the most recent
+ * generations (oldest first, at most 4096 kept) into the host array
+ * log_host (4 floats each: rho_audit, rho_selected, loss, 1) and returns the
+ * number written in *n_out.
+ */
+game_status game_surrogate_log(game_ctx* ctx, float* log_host, int32_t n_max, int32_t* n_out);
+
+/*
+ * The surrogate's replay buffer (MLP prescreen contexts), for inspection:
+ * genes_dev (surrogate_buffer x L floats) and y_dev (surrogate_buffer floats,
+ * the stored natural-log MSEs) are device copies, async, either may be NULL;
+ * count_head_host (2 ints: pairs stored, next slot) and mu_sigma_host (2
+ * floats: mean and standard deviation the training targets are standardised
+ * with) are host copies, and when either is non-NULL the call blocks.
+ * Generations append their exact evaluations at the next slots of the ring
+ * in evaluation order (prescreen choices, then the audit sample).
+ */
+game_status game_surrogate_buffer(game_ctx* ctx, float* genes_dev, float* y_dev,
+                                  int32_t* count_head_host, float* mu_sigma_host);
+
+/*
+ * The surrogate MLP itself (MLP prescreen contexts), async; for checks
+ * against a reference implementation.  Parameters are one float32 array in
+ * the order W1 (H x L, row-major), b1 (H), W2 (H x H), b2 (H), w3 (H), b3 (1).
+ *   game_mlp_params: dir 0 copies the parameters out to params_dev, dir 1 in.
+ *   game_mlp_forward: y_dev[i] = score of row i of X_dev (n x L),
+ *     1 <= n <= max(n_offspring, surrogate_batch, P).
+ *   game_mlp_grads: gradients (same layout) of the mean squared error of the
+ *     scores against target_dev over the n rows (n <= surrogate_batch), and
+ *     the loss in *loss_dev (device float) when non-NULL.
+ *   game_mlp_adam: one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the
+ *     given gradients and the configured learning rate.
+ */
+game_status game_mlp_params(game_ctx* ctx, float* params_dev, int32_t dir);
+game_status game_mlp_forward(game_ctx* ctx, const float* X_dev, int32_t n, float* y_dev);
+game_status game_mlp_grads(game_ctx* ctx, const float* X_dev, const float* target_dev, int32_t n,
+                           float* grads_dev, float* loss_dev);
+game_status game_mlp_adam(game_ctx* ctx, const float* grads_dev);
 
 /* Copy the population out / in: P x L floats, device pointers, async. */
 game_status game_get_population(game_ctx* ctx, float* genes_dev);

@@ -10,8 +10,10 @@ definition directly.
 
 Initialisation: He-uniform (bound sqrt(6 / fan_in)) from Philox4x32-10 block
 (layer, row, col, MLP_INIT) word 0 as u = ((w >> 8) + 1/2) 2^-24, weight =
-bound (2u - 1); biases zero.  Minibatch draw i of training step s takes slot
-floor(w * count / 2^32) with w = word 0 of block (s, i, 0, MINIBATCH).
+bound (2u - 1); biases zero.  Minibatch draw i of training step s uses
+w = word 0 of block (s, i, 0, MINIBATCH): most rows are uniform over the
+replay buffer, a set fraction over the latest generation's evaluations
+(``minibatch_slots``).
 """
 from __future__ import annotations
 
@@ -109,8 +111,27 @@ def standardise(values) -> tuple:
     return mu, (sd if sd > 0.0 else 1.0)
 
 
-def minibatch_slots(step: int, batch: int, count: int, seed: int) -> np.ndarray:
-    """Buffer slots of the minibatch of training step `step` (drawn with replacement)."""
+def recent_rows(batch: int, recent: float) -> int:
+    """Rows of a minibatch drawn from the latest append: floor(recent * batch + 1/2)."""
+    return int(math.floor(recent * batch + 0.5))
+
+
+def minibatch_slots(step: int, batch: int, count: int, seed: int, n_recent: int = 0,
+                    head: int = 0, last: int = 0, cap: int = 0) -> np.ndarray:
+    """Buffer slots of the minibatch of training step `step` (drawn with replacement).
+
+    Row i uses w = word 0 of block (step, i, 0, MINIBATCH).  The first
+    batch - n_recent rows are uniform over the count stored pairs, slot
+    floor(w count / 2^32); the last n_recent rows are uniform over the `last`
+    pairs of the latest append, which end just before slot `head` of the ring
+    of capacity `cap`: slot (head - 1 - floor(w last / 2^32)) mod cap.
+    """
     i = np.arange(batch, dtype=np.uint64)
     w0, _, _, _ = philox4x32_10(step, i, 0, TAG_MINIBATCH, seed)
-    return ((w0.astype(np.uint64) * np.uint64(count)) >> np.uint64(32)).astype(np.int64)
+    w = w0.astype(np.uint64)
+    slots = ((w * np.uint64(count)) >> np.uint64(32)).astype(np.int64)
+    if n_recent > 0:
+        back = ((w * np.uint64(last)) >> np.uint64(32)).astype(np.int64)
+        rec = (head - 1 - back) % cap
+        slots[batch - n_recent:] = rec[batch - n_recent:]
+    return slots

@@ -15,6 +15,7 @@ BASIS = {"power": 0, "chebyshev": 1, "legendre": 2, "trig": 3}
 TASK = {"regression": 0, "classification": 1}
 DTYPE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 STOP = {0: "none", 1: "threshold", 2: "max_generations"}
+SURROGATE = {"none": 0, "mlp": 1, "random": 2}
 
 
 class GameConfig(C.Structure):
@@ -34,6 +35,15 @@ class GameConfig(C.Structure):
         ("tournament_k", C.c_int32),
         ("max_generations", C.c_int32),
         ("rescore_top", C.c_int32),
+        ("surrogate", C.c_int32),
+        ("surrogate_hidden", C.c_int32),
+        ("surrogate_buffer", C.c_int32),
+        ("surrogate_steps", C.c_int32),
+        ("surrogate_batch", C.c_int32),
+        ("audit", C.c_int32),
+        ("prescreen_frac", C.c_double),
+        ("surrogate_lr", C.c_double),
+        ("surrogate_recent", C.c_double),
         ("p_crossover", C.c_double),
         ("p_mutation", C.c_double),
         ("mutation_sigma", C.c_double),
@@ -91,6 +101,12 @@ SIGNATURES = {
     "game_advance": (C.c_int, [_VP, C.c_int32]),
     "game_run": (C.c_int, [_VP, C.POINTER(GameResult)]),
     "game_rescore": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP]),
+    "game_surrogate_log": (C.c_int, [_VP, _VP, C.c_int32, C.POINTER(C.c_int32)]),
+    "game_surrogate_buffer": (C.c_int, [_VP, _VP, _VP, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+    "game_mlp_params": (C.c_int, [_VP, _VP, C.c_int32]),
+    "game_mlp_forward": (C.c_int, [_VP, _VP, C.c_int32, _VP]),
+    "game_mlp_grads": (C.c_int, [_VP, _VP, _VP, C.c_int32, _VP, _VP]),
+    "game_mlp_adam": (C.c_int, [_VP, _VP]),
     "game_get_population": (C.c_int, [_VP, _VP]),
     "game_set_population": (C.c_int, [_VP, _VP]),
     "game_get_state": (C.c_int, [_VP, C.POINTER(GameState), _VP]),

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <vector>
 
 #include "game.h"
 #include "game_internal.hpp"
@@ -57,6 +58,17 @@ struct game_ctx {
   bool poisoned = false;
   bool have_eval = false;   // elites/fitness of the current population are known
   bool tile_fresh = false;  // the gene tile holds the current population
+  bool sur_warm = false;    // offspring form: initial population stored (and learned)
+  // offspring form buffers
+  float *O = nullptr, *evg = nullptr, *yhat = nullptr, *rho = nullptr, *loss = nullptr;
+  uint64_t* keys = nullptr;
+  int *sel = nullptr, *aud = nullptr, *surv = nullptr;
+  double *emse = nullptr, *emis = nullptr, *efit = nullptr, *snap = nullptr;
+  float *prm = nullptr, *grd = nullptr, *am = nullptr, *av = nullptr;
+  int32_t* step = nullptr;
+  MlpScratch scr{};
+  float *Xb = nullptr, *tb = nullptr, *buf = nullptr, *bufy = nullptr, *log = nullptr;
+  SurState* sst = nullptr;
 };
 
 namespace game {
@@ -98,9 +110,47 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
     return GAME_E_UNSUPPORTED;
   }
   if (c->rescore_top > P) return bad("rescore_top must not exceed the population size");
-  if (n_off != P - c->elitism) {
-    std::snprintf(err, errlen, "n_offspring other than P - elitism is not available");
-    return GAME_E_UNSUPPORTED;
+  if (c->surrogate < GAME_SURROGATE_NONE || c->surrogate > GAME_SURROGATE_RANDOM) return bad("unknown surrogate mode");
+  const bool offspring = c->surrogate != GAME_SURROGATE_NONE || n_off != P - c->elitism;
+  p->offspring = offspring;
+  p->n_off = (int)n_off;
+  p->sur = c->surrogate;
+  if (offspring) {
+    if (n_off < 2 || n_off > 8192) return bad("n_offspring must be in [2, 8192] in the offspring form");
+    if (c->rescore_top > 0) {
+      std::snprintf(err, errlen, "rescore_top is not available in the offspring form");
+      return GAME_E_UNSUPPORTED;
+    }
+    if (c->surrogate != GAME_SURROGATE_NONE) {
+      if (!(c->prescreen_frac > 0.0 && c->prescreen_frac <= 1.0)) return bad("prescreen_frac must be in (0, 1]");
+      p->k_sel = (int)std::llround(c->prescreen_frac * (double)n_off);
+      if (p->k_sel < 1) p->k_sel = 1;
+      if (p->k_sel > 4096) return bad("prescreen_frac * n_offspring must be <= 4096");
+      if (c->audit < 0 || c->audit > 4096) return bad("audit must be in [0, 4096]");
+      // the audit sample measures the MLP's ranking; it is capped at n_offspring
+      p->audit = c->surrogate == GAME_SURROGATE_MLP ? (int)std::min<int64_t>(c->audit, n_off) : 0;
+    } else {
+      p->k_sel = (int)n_off;
+      p->audit = 0;
+    }
+    if (p->k_sel < P - c->elitism) return bad("the offspring evaluated exactly must cover P - elitism");
+    p->P_eval = p->k_sel + p->audit;
+    if (c->surrogate == GAME_SURROGATE_MLP) {
+      if (c->surrogate_hidden < 16 || c->surrogate_hidden > 1024) return bad("surrogate_hidden must be in [16, 1024]");
+      if (c->surrogate_batch < 1 || c->surrogate_batch > 8192) return bad("surrogate_batch must be in [1, 8192]");
+      if (c->surrogate_buffer < c->surrogate_batch) return bad("surrogate_buffer must be >= surrogate_batch");
+      if (c->surrogate_buffer > (1 << 24)) return bad("surrogate_buffer too large");
+      if (c->surrogate_buffer < std::max<int64_t>(P, p->k_sel + p->audit))
+        return bad("surrogate_buffer must hold one generation's exact evaluations (and the population)");
+      if (c->surrogate_steps < 0 || c->surrogate_steps > 1024) return bad("surrogate_steps must be in [0, 1024]");
+      if (!(std::isfinite(c->surrogate_lr) && c->surrogate_lr > 0.0)) return bad("surrogate_lr must be > 0");
+      if (!(c->surrogate_recent >= 0.0 && c->surrogate_recent <= 1.0)) return bad("surrogate_recent must be in [0, 1]");
+      p->n_recent = (int)std::floor(c->surrogate_recent * c->surrogate_batch + 0.5);
+      p->H = c->surrogate_hidden;
+      p->cap = c->surrogate_buffer;
+      p->steps = c->surrogate_steps;
+      p->batch = c->surrogate_batch;
+    }
   }
   p->K = (int)K;
   p->M = (int)M;
@@ -110,7 +160,7 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   p->n_off = (int)n_off;
   p->E = c->elitism;
   p->k = c->tournament_k;
-  p->P_max = (int)(P > n_off ? P : n_off);
+  p->P_max = (int)(offspring ? std::max<int64_t>(P, p->P_eval) : std::max<int64_t>(P, n_off));
   fitness_tile(c->dtype, &p->tile_n, &p->tile_p);
   p->N = c->n_patterns;
   p->N_pad = round_up(p->N, p->tile_n);
@@ -147,6 +197,47 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   const bool f32x = c->dtype != GAME_F64;
   p->off_x = take(f32x ? (size_t)p->N * c->n_features * 4 : 0);
   p->off_rpart = take(f32x ? (size_t)rescore_grid() * 2 * kMaxRescore * 8 : 0);
+  if (offspring) {
+    const size_t Lz = (size_t)L;
+    const int evrows = std::max<int>((int)P, p->P_eval);
+    p->off_O = take((size_t)n_off * Lz * 4);
+    p->off_keys = take((size_t)n_off * 8);
+    p->off_sel = take((size_t)p->k_sel * 4);
+    p->off_aud = take((size_t)std::max(p->audit, 1) * 4);
+    p->off_surv = take((size_t)P * 4);
+    p->off_evg = take((size_t)evrows * Lz * 4);
+    p->off_emse = take((size_t)evrows * 8);
+    p->off_emis = take((size_t)evrows * 8);
+    p->off_efit = take((size_t)evrows * 8);
+    p->off_snap = take((size_t)kMaxElite * 3 * 8);
+    p->off_yhat = take((size_t)n_off * 4);
+    p->off_rho = take(16);
+    p->off_loss = take(16);
+    p->off_sst = take(sizeof(SurState));
+    p->off_log = take((size_t)kLogCap * 4 * 4);
+    if (c->surrogate == GAME_SURROGATE_MLP) {
+      const size_t np = (size_t)mlp_layout((int)L, p->H, p->H).total;
+      p->rows_max = std::max<int>((int)n_off, std::max<int>(p->batch, (int)P));
+      const size_t rows = (size_t)p->rows_max, H = (size_t)p->H, B = (size_t)p->batch;
+      p->off_prm = take(np * 4);
+      p->off_grd = take(np * 4);
+      p->off_am = take(np * 4);
+      p->off_av = take(np * 4);
+      p->off_step = take(16);
+      p->off_a1 = take(rows * H * 4);
+      p->off_h1 = take(rows * H * 4);
+      p->off_a2 = take(rows * H * 4);
+      p->off_h2 = take(rows * H * 4);
+      p->off_y = take(rows * 4);
+      p->off_dy = take(B * 4);
+      p->off_da2 = take(B * H * 4);
+      p->off_da1 = take(B * H * 4);
+      p->off_Xb = take(B * Lz * 4);
+      p->off_tb = take(B * 4);
+      p->off_buf = take((size_t)p->cap * Lz * 4);
+      p->off_bufy = take((size_t)p->cap * 4);
+    }
+  }
   p->total = off;
   return GAME_OK;
 }
@@ -302,7 +393,128 @@ game_status enqueue_evolve(game_ctx* c, const double* fit, hipStream_t s) {
   return GAME_OK;
 }
 
+MlpDims mlp_dims(const game_ctx* c) { return MlpDims{c->plan.L, c->plan.H, c->plan.H}; }
+
+// S Adam steps on minibatches drawn from the replay buffer.
+game_status enqueue_train(game_ctx* c, hipStream_t s) {
+  const Plan& p = c->plan;
+  const MlpDims d = mlp_dims(c);
+  for (int i = 0; i < p.steps; ++i) {
+    GAME_TRY(dev(c,
+                 sur_minibatch(c->buf, c->bufy, p.L, p.batch, p.n_recent, p.cap, c->sst, c->step,
+                               c->cfg.seed, c->Xb, c->tb, c->state, s),
+                 "minibatch"));
+    GAME_TRY(dev(c, mlp_grads(d, c->prm, c->Xb, c->tb, p.batch, c->scr, c->grd, c->loss, c->state, s),
+                 "mlp grads"));
+    GAME_TRY(dev(c,
+                 mlp_adam(d, c->prm, c->grd, c->am, c->av, c->step, (float)c->cfg.surrogate_lr,
+                          c->state, s),
+                 "mlp adam"));
+  }
+  return GAME_OK;
+}
+
+// Offspring form, first use: the population is evaluated exactly (and, with
+// the MLP prescreen, stored in the replay buffer and learned from).
+game_status enqueue_offspring_warmup(game_ctx* c, hipStream_t s) {
+  const Plan& p = c->plan;
+  if (!c->have_eval) GAME_TRY(enqueue_eval_population(c, nullptr, nullptr, nullptr, s));
+  if (p.sur == GAME_SURROGATE_MLP) {
+    GAME_TRY(dev(c, launch_pop_copy(c->pop0, c->pop1, c->state, c->evg, (int64_t)p.P * p.L, 0, s),
+                 "population copy"));
+    GAME_TRY(dev(c, sur_append(c->evg, c->mse, p.P, p.L, c->buf, c->bufy, p.cap, c->sst, c->state, s),
+                 "replay append"));
+    GAME_TRY(enqueue_train(c, s));
+  }
+  c->have_eval = true;
+  c->sur_warm = true;
+  return GAME_OK;
+}
+
+// Offspring form, one generation (see surrogate.hip for the order of steps).
+game_status enqueue_offspring_generation(game_ctx* c, hipStream_t s) {
+  const Plan& p = c->plan;
+  DevState* st = c->state;
+  const int k = p.k_sel, A = p.audit;
+  // children of the current population
+  BreedArgs a{};
+  a.pop0 = c->pop0;
+  a.pop1 = c->pop1;
+  a.fit = c->fit;
+  a.elite = c->elite;
+  a.P = p.P;
+  a.L = p.L;
+  a.E = 0;
+  a.n_children = p.n_off;
+  a.k = p.k;
+  a.thr_c = c->thr_c;
+  a.thr_m = c->thr_m;
+  a.sigma = (float)c->cfg.mutation_sigma;
+  a.k0 = (uint32_t)c->cfg.seed;
+  a.k1 = (uint32_t)(c->cfg.seed >> 32);
+  a.M = p.M;
+  a.M_pad = p.M_pad;
+  a.bias = c->cfg.bias;
+  a.out = c->O;
+  GAME_TRY(dev(c, launch_breed(c->cfg.dtype, a, st, s), "breed offspring"));
+  // prescreen: which children are evaluated exactly
+  const int* sel = nullptr;
+  if (p.sur == GAME_SURROGATE_MLP) {
+    GAME_TRY(dev(c,
+                 mlp_forward(mlp_dims(c), c->prm, c->O, p.n_off, nullptr, c->scr.h1, nullptr,
+                             c->scr.h2, c->yhat, st, s),
+                 "mlp forward"));
+    GAME_TRY(dev(c, sur_keys(0, c->yhat, nullptr, p.n_off, 0, st, c->cfg.seed, c->keys, s), "keys"));
+    GAME_TRY(dev(c, sur_select(c->keys, p.n_off, k, c->sel, st, s), "prescreen"));
+    sel = c->sel;
+  } else if (p.sur == GAME_SURROGATE_RANDOM) {
+    GAME_TRY(dev(c, sur_keys(1, nullptr, nullptr, p.n_off, kTagPrescreen, st, c->cfg.seed, c->keys, s), "keys"));
+    GAME_TRY(dev(c, sur_select(c->keys, p.n_off, k, c->sel, st, s), "prescreen"));
+    sel = c->sel;
+  }
+  if (A > 0) {
+    GAME_TRY(dev(c, sur_keys(1, nullptr, nullptr, p.n_off, kTagAudit, st, c->cfg.seed, c->keys, s), "keys"));
+    GAME_TRY(dev(c, sur_select(c->keys, p.n_off, A, c->aud, st, s), "audit"));
+  }
+  // exact fitness of the selected children and the audit sample
+  GAME_TRY(dev(c, sur_gather(c->O, sel, k, p.L, c->evg, st, s), "gather"));
+  if (A > 0) GAME_TRY(dev(c, sur_gather(c->O, c->aud, A, p.L, c->evg + (size_t)k * p.L, st, s), "gather"));
+  const int Ppad = (p.P_eval + p.tile_p - 1) / p.tile_p * p.tile_p;
+  GAME_TRY(dev(c,
+               launch_pack(c->cfg.dtype, c->evg, nullptr, nullptr, p.P_eval, p.L, p.M, c->cfg.bias,
+                           p.M_pad, Ppad, c->tile, c->biasv, s),
+               "pack"));
+  c->tile_fresh = false;
+  FitTail t = make_tail(c, p.P_eval, false, c->emse, c->emis, c->efit);
+  GAME_TRY(enqueue_fitness(c, p.P_eval, t, s));
+  if (p.sur == GAME_SURROGATE_MLP) {
+    if (A > 0)
+      GAME_TRY(dev(c, sur_spearman(c->yhat, c->aud, c->emse + k, A, c->rho, st, s), "spearman"));
+    GAME_TRY(dev(c, sur_spearman(c->yhat, c->sel, c->emse, k, c->rho + 1, st, s), "spearman"));
+    GAME_TRY(dev(c, sur_append(c->evg, c->emse, p.P_eval, p.L, c->buf, c->bufy, p.cap, c->sst, st, s),
+                 "replay append"));
+  }
+  // next population: elites + best P - E of the selected children
+  GAME_TRY(dev(c, sur_keys(2, nullptr, c->efit, k, 0, st, c->cfg.seed, c->keys, s), "keys"));
+  GAME_TRY(dev(c, sur_select(c->keys, k, p.P - p.E, c->surv, st, s), "survivors"));
+  GAME_TRY(dev(c, sur_snapshot(c->elite, p.E, c->fit, c->mse, c->miscls, c->snap, st, s), "snapshot"));
+  GAME_TRY(dev(c,
+               sur_merge(c->pop0, c->pop1, c->elite, c->snap, p.E, c->evg, c->surv, c->efit, c->emse,
+                         c->emis, p.P, p.L, c->fit, c->mse, c->miscls, st, s),
+               "merge"));
+  if (p.sur == GAME_SURROGATE_MLP) GAME_TRY(enqueue_train(c, s));
+  GAME_TRY(dev(c, sur_log(c->rho, p.sur == GAME_SURROGATE_MLP ? c->loss : nullptr, c->log, kLogCap,
+                          c->sst, st, s),
+               "log"));
+  GAME_TRY(dev(c,
+               sur_rank_track(c->fit, c->mse, c->miscls, p.P, p.E > 0 ? p.E : 1, c->elite, c->pop0,
+                              c->pop1, p.L, c->best, st, 1, s),
+               "rank"));
+  return GAME_OK;
+}
+
 game_status enqueue_generation(game_ctx* c, hipStream_t s) {
+  if (c->plan.offspring) return enqueue_offspring_generation(c, s);
   GAME_TRY(enqueue_eval_population(c, nullptr, nullptr, nullptr, s));
   GAME_TRY(enqueue_evolve(c, c->fit, s));
   return GAME_OK;
@@ -313,7 +525,7 @@ game_status build_graph(game_ctx* c, int n_gen, hipGraph_t* graph, hipGraphExec_
   if (!c->cap) GAME_TRY(dev(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking), "stream create"));
   GAME_TRY(dev(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "begin capture"));
   game_status st = GAME_OK;
-  c->tile_fresh = true;  // callers pack the population before replaying the graph
+  if (!c->plan.offspring) c->tile_fresh = true;  // callers pack the population before replay
   for (int i = 0; i < n_gen && st == GAME_OK; ++i) st = enqueue_generation(c, c->cap);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->cap, &g);
@@ -361,6 +573,16 @@ void game_config_default(game_config* c) {
   c->mutation_sigma = 0.1;
   c->mse_threshold = 0.0;
   c->seed = 0;
+  c->rescore_top = 0;
+  c->surrogate = GAME_SURROGATE_NONE;
+  c->surrogate_hidden = 256;
+  c->surrogate_buffer = 50000;
+  c->surrogate_steps = 32;
+  c->surrogate_batch = 1024;
+  c->audit = 256;
+  c->prescreen_frac = 0.25;
+  c->surrogate_lr = 3e-3;
+  c->surrogate_recent = 0.75;
 }
 
 game_status game_query(const game_config* cfg, game_dims* d) {
@@ -427,6 +649,39 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
   c->counters = reinterpret_cast<uint32_t*>(c->ws + p.off_cnt);
   c->xf = reinterpret_cast<float*>(c->ws + p.off_x);
   c->rpart = reinterpret_cast<double*>(c->ws + p.off_rpart);
+  if (p.offspring) {
+    auto F = [&](size_t o) { return reinterpret_cast<float*>(c->ws + o); };
+    auto D = [&](size_t o) { return reinterpret_cast<double*>(c->ws + o); };
+    auto I = [&](size_t o) { return reinterpret_cast<int*>(c->ws + o); };
+    c->O = F(p.off_O);
+    c->keys = reinterpret_cast<uint64_t*>(c->ws + p.off_keys);
+    c->sel = I(p.off_sel);
+    c->aud = I(p.off_aud);
+    c->surv = I(p.off_surv);
+    c->evg = F(p.off_evg);
+    c->emse = D(p.off_emse);
+    c->emis = D(p.off_emis);
+    c->efit = D(p.off_efit);
+    c->snap = D(p.off_snap);
+    c->yhat = F(p.off_yhat);
+    c->rho = F(p.off_rho);
+    c->loss = F(p.off_loss);
+    c->sst = reinterpret_cast<SurState*>(c->ws + p.off_sst);
+    c->log = F(p.off_log);
+    if (p.sur == GAME_SURROGATE_MLP) {
+      c->prm = F(p.off_prm);
+      c->grd = F(p.off_grd);
+      c->am = F(p.off_am);
+      c->av = F(p.off_av);
+      c->step = reinterpret_cast<int32_t*>(c->ws + p.off_step);
+      c->scr = MlpScratch{F(p.off_a1), F(p.off_h1), F(p.off_a2), F(p.off_h2),
+                          F(p.off_y), F(p.off_dy), F(p.off_da2), F(p.off_da1)};
+      c->Xb = F(p.off_Xb);
+      c->tb = F(p.off_tb);
+      c->buf = F(p.off_buf);
+      c->bufy = F(p.off_bufy);
+    }
+  }
   c->psse = reinterpret_cast<double*>(c->ws + p.off_psse);
   c->pmiss = reinterpret_cast<uint32_t*>(c->ws + p.off_pmiss);
   c->mse = reinterpret_cast<double*>(c->ws + p.off_mse);
@@ -447,6 +702,19 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
     r = dev(c, hipMemcpyAsync(c->xf, X, (size_t)p.N * cfg->n_features * 4, hipMemcpyDeviceToDevice, st),
             "pattern copy");
   if (r == GAME_OK) r = enqueue_pack_population(c, st);
+  if (r == GAME_OK) {  // prime per-kernel attributes outside any graph capture
+    (void)fitness_geometry(p, cfg->task, cfg->dtype, p.P_max);
+    if (p.offspring) r = dev(c, sur_prepare(), "prepare");
+  }
+  if (r == GAME_OK && p.offspring) {
+    r = dev(c, hipMemsetAsync(c->sst, 0, sizeof(SurState), st), "surrogate state");
+    if (r == GAME_OK) r = dev(c, hipMemsetAsync(c->rho, 0, 16, st), "surrogate state");
+    if (r == GAME_OK) r = dev(c, hipMemsetAsync(c->loss, 0, 16, st), "surrogate state");
+    if (r == GAME_OK && p.sur == GAME_SURROGATE_MLP) {
+      r = dev(c, mlp_init(MlpDims{p.L, p.H, p.H}, c->prm, c->am, c->av, cfg->seed, st), "mlp init");
+      if (r == GAME_OK) r = dev(c, hipMemsetAsync(c->step, 0, 16, st), "mlp init");
+    }
+  }
   if (r != GAME_OK) {
     delete c;
     return r;
@@ -478,6 +746,13 @@ game_status game_eval_fitness(game_ctx* c, const float* genes, int32_t P, double
 game_status game_step(game_ctx* c, const double* fit) {
   GAME_TRY(check_ctx(c));
   const Plan& p = c->plan;
+  if (p.offspring) {
+    if (fit) return fail(GAME_E_UNSUPPORTED, "the offspring form keeps its own exact fitness: pass NULL");
+    if (!c->sur_warm) GAME_TRY(enqueue_offspring_warmup(c, c->stream));
+    GAME_TRY(enqueue_offspring_generation(c, c->stream));
+    c->have_eval = true;
+    return GAME_OK;
+  }
   if (fit == nullptr) {
     if (!c->have_eval) return fail(GAME_E_STATE, "game_step(NULL) needs game_eval_fitness(NULL) on the current population first");
     GAME_TRY(enqueue_evolve(c, c->fit, c->stream));
@@ -494,13 +769,14 @@ game_status game_advance(game_ctx* c, int32_t n) {
   GAME_TRY(check_ctx(c));
   if (n < 0) return fail(GAME_E_INVALID, "n_generations must be >= 0");
   if (n == 0) return GAME_OK;
+  if (c->plan.offspring && !c->sur_warm) GAME_TRY(enqueue_offspring_warmup(c, c->stream));
   if (n >= kChunk) GAME_TRY(build_graph(c, kChunk, &c->graphC, &c->execC));
   if (n % kChunk) GAME_TRY(build_graph(c, 1, &c->graph1, &c->exec1));
-  GAME_TRY(enqueue_pack_population(c, c->stream));
+  if (!c->plan.offspring) GAME_TRY(enqueue_pack_population(c, c->stream));
   for (int i = 0; i + kChunk <= n; i += kChunk)
     GAME_TRY(dev(c, hipGraphLaunch(c->execC, c->stream), "graph launch"));
   for (int i = 0; i < n % kChunk; ++i) GAME_TRY(dev(c, hipGraphLaunch(c->exec1, c->stream), "graph launch"));
-  c->have_eval = false;
+  c->have_eval = c->plan.offspring;
   return GAME_OK;
 }
 
@@ -526,8 +802,9 @@ game_status game_run(game_ctx* c, game_result* res) {
   GAME_TRY(check_ctx(c));
   if (!res) return fail(GAME_E_INVALID, "result is NULL");
   const int G = c->cfg.max_generations;
+  if (c->plan.offspring && !c->sur_warm) GAME_TRY(enqueue_offspring_warmup(c, c->stream));
   GAME_TRY(build_graph(c, kChunk, &c->graphC, &c->execC));
-  if (!c->tile_fresh) GAME_TRY(enqueue_pack_population(c, c->stream));
+  if (!c->plan.offspring && !c->tile_fresh) GAME_TRY(enqueue_pack_population(c, c->stream));
   game_state s0;
   GAME_TRY(game_get_state(c, &s0, nullptr));
   GAME_TRY(dev(c, launch_run_arm(c->state, G, c->cfg.mse_threshold, c->stream), "arm"));
@@ -544,7 +821,9 @@ game_status game_run(game_ctx* c, game_result* res) {
   res->best_mse = s.best_mse;
   res->best_fitness = s.best_fitness;
   res->best_miscls = s.best_miscls;
-  res->generations = s.generation - s0.generation + 1;
+  // classic form: generations evaluated (the stopping one is not bred from);
+  // offspring form: offspring generations produced
+  res->generations = s.generation - s0.generation + (c->plan.offspring ? 0 : 1);
   res->stop_reason = s.stop_reason;
   c->have_eval = true;  // the population is the last evaluated generation
   return GAME_OK;
@@ -562,6 +841,87 @@ game_status game_rescore(game_ctx* c, const float* genes, int32_t n, double* mse
   return enqueue_rescore(c, genes, n, mse, miscls, false, c->stream);
 }
 
+game_status game_surrogate_log(game_ctx* c, float* out, int32_t n_max, int32_t* n_out) {
+  GAME_TRY(check_ctx(c));
+  if (!out || !n_out || n_max < 0) return fail(GAME_E_INVALID, "log buffer and count are required");
+  if (!c->plan.offspring) return fail(GAME_E_UNSUPPORTED, "no offspring form in this context");
+  SurState h;
+  std::vector<float> all((size_t)kLogCap * 4);
+  GAME_TRY(dev(c, hipMemcpyAsync(&h, c->sst, sizeof(h), hipMemcpyDeviceToHost, c->stream), "log copy"));
+  GAME_TRY(dev(c, hipMemcpyAsync(all.data(), c->log, all.size() * 4, hipMemcpyDeviceToHost, c->stream), "log copy"));
+  GAME_TRY(dev(c, hipStreamSynchronize(c->stream), "synchronize"));
+  const int n = std::min(std::min(h.n_logged, kLogCap), n_max);
+  const int start = h.n_logged - n;
+  for (int i = 0; i < n; ++i) {
+    const int slot = (start + i) % kLogCap;
+    for (int q = 0; q < 4; ++q) out[4 * i + q] = all[4 * slot + q];
+  }
+  *n_out = n;
+  return GAME_OK;
+}
+
+game_status game_surrogate_buffer(game_ctx* c, float* genes, float* y, int32_t* count_head,
+                                  float* mu_sigma) {
+  GAME_TRY(check_ctx(c));
+  if (c->plan.sur != GAME_SURROGATE_MLP) return fail(GAME_E_UNSUPPORTED, "no surrogate MLP in this context");
+  const Plan& p = c->plan;
+  if (genes)
+    GAME_TRY(dev(c, hipMemcpyAsync(genes, c->buf, (size_t)p.cap * p.L * 4, hipMemcpyDeviceToDevice, c->stream), "buffer copy"));
+  if (y) GAME_TRY(dev(c, hipMemcpyAsync(y, c->bufy, (size_t)p.cap * 4, hipMemcpyDeviceToDevice, c->stream), "buffer copy"));
+  if (count_head || mu_sigma) {
+    SurState h;
+    GAME_TRY(dev(c, hipMemcpyAsync(&h, c->sst, sizeof(h), hipMemcpyDeviceToHost, c->stream), "buffer copy"));
+    GAME_TRY(dev(c, hipStreamSynchronize(c->stream), "synchronize"));
+    if (count_head) {
+      count_head[0] = h.count;
+      count_head[1] = h.head;
+    }
+    if (mu_sigma) {
+      mu_sigma[0] = h.mu;
+      mu_sigma[1] = h.sigma;
+    }
+  }
+  return GAME_OK;
+}
+
+static game_status need_mlp(game_ctx* c) {
+  GAME_TRY(check_ctx(c));
+  if (c->plan.sur != GAME_SURROGATE_MLP) return fail(GAME_E_UNSUPPORTED, "no surrogate MLP in this context");
+  return GAME_OK;
+}
+
+game_status game_mlp_params(game_ctx* c, float* params, int32_t dir) {
+  GAME_TRY(need_mlp(c));
+  if (!params || (dir != 0 && dir != 1)) return fail(GAME_E_INVALID, "params and dir 0|1 required");
+  const size_t bytes = (size_t)mlp_layout(c->plan.L, c->plan.H, c->plan.H).total * 4;
+  if (dir == 0) return dev(c, hipMemcpyAsync(params, c->prm, bytes, hipMemcpyDeviceToDevice, c->stream), "params");
+  return dev(c, hipMemcpyAsync(c->prm, params, bytes, hipMemcpyDeviceToDevice, c->stream), "params");
+}
+
+game_status game_mlp_forward(game_ctx* c, const float* X, int32_t n, float* y) {
+  GAME_TRY(need_mlp(c));
+  if (!X || !y || n < 1 || n > c->plan.rows_max) return fail(GAME_E_INVALID, "n must be in [1, %d]", c->plan.rows_max);
+  return dev(c, mlp_forward(mlp_dims(c), c->prm, X, n, nullptr, c->scr.h1, nullptr, c->scr.h2, y, nullptr, c->stream),
+             "mlp forward");
+}
+
+game_status game_mlp_grads(game_ctx* c, const float* X, const float* target, int32_t n, float* grads,
+                           float* loss) {
+  GAME_TRY(need_mlp(c));
+  if (!X || !target || !grads || n < 1 || n > c->plan.batch)
+    return fail(GAME_E_INVALID, "n must be in [1, %d]", c->plan.batch);
+  return dev(c, mlp_grads(mlp_dims(c), c->prm, X, target, n, c->scr, grads, loss, nullptr, c->stream),
+             "mlp grads");
+}
+
+game_status game_mlp_adam(game_ctx* c, const float* grads) {
+  GAME_TRY(need_mlp(c));
+  if (!grads) return fail(GAME_E_INVALID, "grads is NULL");
+  return dev(c, mlp_adam(mlp_dims(c), c->prm, grads, c->am, c->av, c->step, (float)c->cfg.surrogate_lr,
+                         nullptr, c->stream),
+             "mlp adam");
+}
+
 game_status game_get_population(game_ctx* c, float* genes) {
   GAME_TRY(check_ctx(c));
   if (!genes) return fail(GAME_E_INVALID, "genes is NULL");
@@ -573,6 +933,7 @@ game_status game_set_population(game_ctx* c, const float* genes) {
   if (!genes) return fail(GAME_E_INVALID, "genes is NULL");
   c->have_eval = false;
   c->tile_fresh = false;
+  c->sur_warm = false;
   return dev(c, launch_pop_copy(c->pop0, c->pop1, c->state, const_cast<float*>(genes), (int64_t)c->plan.P * c->plan.L, 1, c->stream), "population copy");
 }
 

@@ -109,6 +109,7 @@ __device__ __forceinline__ float mutate_gene(float gene, uint32_t c, uint32_t l,
 template <typename O, typename B>
 __device__ __forceinline__ void put_gene(const BreedArgs& a, float* dst, int row, int l, float v) {
   dst[(int64_t)row * a.L + l] = v;
+  if (!a.tile) return;
   if (l < a.M)
     static_cast<O*>(a.tile)[(int64_t)row * a.M_pad + l] = cvt_gene<O>(v);
   else
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(256) void breed_kernel(BreedArgs a, DevState* st) {
   const int lane = threadIdx.x & 63;
   const uint32_t g = (uint32_t)st->generation;
   const float* src = (g & 1u) ? a.pop1 : a.pop0;
-  float* dst = (g & 1u) ? a.pop0 : a.pop1;
+  float* dst = a.out ? a.out : ((g & 1u) ? a.pop0 : a.pop1);
   if (wave < a.E) {
     const float* row = src + (int64_t)a.elite[wave] * a.L;
     for (int l = lane; l < a.L; l += 64) put_gene<O, B>(a, dst, wave, l, row[l]);
@@ -148,6 +149,7 @@ __global__ __launch_bounds__(256) void breed_kernel(BreedArgs a, DevState* st) {
   // The last workgroup to arrive advances the generation.  The barrier waits
   // for this workgroup's loads (its read of the generation included) before
   // the arrival; the new genes are read only by later launches.
+  if (!a.counter) return;
   __shared__ int s_last;
   __syncthreads();
   if (threadIdx.x == 0) s_last = atomicAdd(a.counter, 1u) == gridDim.x - 1;

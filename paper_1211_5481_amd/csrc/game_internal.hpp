@@ -23,6 +23,10 @@ enum : uint32_t {
   kTagMut1 = 4,
   kTagMut2 = 5,
   kTagMut3 = 6,
+  kTagMlpInit = 7,
+  kTagMinibatch = 8,
+  kTagAudit = 9,
+  kTagPrescreen = 10,
 };
 
 // ------------------------------------------------- Philox4x32-10 (device)
@@ -114,8 +118,17 @@ struct Plan {
   int n_counters;              // arrival counters: tiles, tiles done, breed, re-score
   size_t off_phi, off_t, off_tile, off_bias, off_pop0, off_pop1, off_psse, off_pmiss;
   size_t off_mse, off_miscls, off_fit, off_elite, off_state, off_best, off_cnt;
-  size_t off_x, off_rpart, total;   // float32 patterns and re-score partials (16-bit forms)
+  size_t off_x, off_rpart;          // float32 patterns and re-score partials (16-bit forms)
+  // offspring form (n_offspring != P - E, or a prescreen)
+  bool offspring;
+  int k_sel, audit, P_eval, sur, H, cap, steps, batch, n_recent, rows_max;
+  size_t off_O, off_keys, off_sel, off_aud, off_surv, off_evg, off_emse, off_emis, off_efit;
+  size_t off_snap, off_yhat, off_rho, off_loss, off_prm, off_grd, off_am, off_av, off_step;
+  size_t off_a1, off_h1, off_a2, off_h2, off_y, off_dy, off_da2, off_da1, off_Xb, off_tb;
+  size_t off_buf, off_bufy, off_sst, off_log;
+  size_t total;
 };
+constexpr int kLogCap = 4096;  // generations of surrogate statistics kept
 
 game_status make_plan(const game_config* cfg, Plan* p, char* err, size_t errlen);
 
@@ -169,6 +182,7 @@ struct BreedArgs {
   void* biasv;
   int M, M_pad, bias;
   uint32_t* counter;  // zero between launches
+  float* out;         // offspring form: children go here (no tile, no advance)
 };
 hipError_t launch_breed(int dtype, const BreedArgs& a, DevState* st, hipStream_t s);
 
@@ -182,6 +196,64 @@ hipError_t launch_rescore(const float* X, const float* t, int64_t N, int F, int 
                           const float* pop0, const float* pop1, const int* top, double* part,
                           uint32_t* counter, double* mse, double* miscls, const DevState* sel,
                           DevState* st, float* best, hipStream_t s);
+
+// ------------------------------------------------------ offspring form
+struct SurState {  // replay ring buffer, target statistics, log position
+  int32_t head, count;
+  float mu, sigma;
+  int32_t n_logged;
+  int32_t last;  // rows the latest append stored (they end at head - 1)
+};
+hipError_t sur_prepare();
+hipError_t sur_keys(int mode, const float* fsrc, const double* dsrc, int n, uint32_t tag,
+                    const DevState* st, uint64_t seed, uint64_t* keys, hipStream_t s);
+hipError_t sur_select(const uint64_t* keys, int n, int k, int* out, const DevState* st,
+                      hipStream_t s);
+hipError_t sur_spearman(const float* x, const int* xi, const double* y, int n, float* out,
+                        const DevState* st, hipStream_t s);
+hipError_t sur_gather(const float* src, const int* idx, int n, int L, float* dst, const DevState* st,
+                      hipStream_t s);
+hipError_t sur_append(const float* genes, const double* mse, int n, int L, float* buf, float* buf_y,
+                      int cap, SurState* ss, const DevState* st, hipStream_t s);
+// rows i < B - n_recent come uniformly from the whole buffer, the others from
+// the latest append
+hipError_t sur_minibatch(const float* buf, const float* buf_y, int L, int B, int n_recent, int cap,
+                         const SurState* ss, const int32_t* step, uint64_t seed, float* Xb, float* tb,
+                         const DevState* st, hipStream_t s);
+hipError_t sur_snapshot(const int* elite, int E, const double* fit, const double* mse,
+                        const double* miscls, double* snap, const DevState* st, hipStream_t s);
+hipError_t sur_merge(float* pop0, float* pop1, const int* elite, const double* snap, int E,
+                     const float* cand, const int* surv, const double* cfit, const double* cmse,
+                     const double* cmis, int P, int L, double* fit, double* mse, double* miscls,
+                     const DevState* st, hipStream_t s);
+hipError_t sur_rank_track(const double* fit, const double* mse, const double* miscls, int P, int n_top,
+                          int* top, const float* pop0, const float* pop1, int L, float* best,
+                          DevState* st, int advance, hipStream_t s);
+hipError_t sur_log(const float* rho, const float* loss, float* log, int cap, SurState* ss,
+                   const DevState* st, hipStream_t s);
+
+// ------------------------------------------------------ surrogate MLP
+struct MlpDims {
+  int L, H1, H2;
+};
+struct MlpLayout {  // offsets into the flat parameter array
+  int64_t W1, b1, W2, b2, w3, b3, total;
+};
+struct MlpScratch {  // activations and gradients of one batch (rows x width)
+  float *a1, *h1, *a2, *h2, *y, *dy, *da2, *da1;
+};
+MlpLayout mlp_layout(int L, int H1, int H2);
+hipError_t mlp_init(const MlpDims& d, float* params, float* m, float* v, uint64_t seed,
+                    hipStream_t s);
+// halt: kernels return at once once a run has stopped (may be null)
+hipError_t mlp_forward(const MlpDims& d, const float* params, const float* X, int B, float* a1,
+                       float* h1, float* a2, float* h2, float* y, const DevState* halt,
+                       hipStream_t s);
+hipError_t mlp_grads(const MlpDims& d, const float* params, const float* X, const float* target,
+                     int B, const MlpScratch& w, float* grads, float* loss, const DevState* halt,
+                     hipStream_t s);
+hipError_t mlp_adam(const MlpDims& d, float* params, const float* grads, float* m, float* v,
+                    int32_t* step, float lr, const DevState* halt, hipStream_t s);
 
 hipError_t launch_state_init(DevState* st, uint32_t* counters, int n_counters, hipStream_t s);
 hipError_t launch_run_arm(DevState* st, int max_generations, double threshold, hipStream_t s);

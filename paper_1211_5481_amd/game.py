@@ -31,6 +31,15 @@ class Config:
     tournament_k: int = 3
     max_generations: int = 100
     rescore_top: int = 0              # per-generation float32 re-score of the top-k
+    surrogate: str = "none"           # offspring form prescreen: none | mlp | random
+    surrogate_hidden: int = 256
+    surrogate_buffer: int = 50000
+    surrogate_steps: int = 32
+    surrogate_batch: int = 1024
+    audit: int = 256
+    prescreen_frac: float = 0.25
+    surrogate_lr: float = 3e-3
+    surrogate_recent: float = 0.75
     p_crossover: float = 0.9
     p_mutation: float = 0.05
     mutation_sigma: float = 0.1
@@ -54,6 +63,15 @@ class Config:
         c.tournament_k = int(self.tournament_k)
         c.max_generations = int(self.max_generations)
         c.rescore_top = int(self.rescore_top)
+        c.surrogate = L.SURROGATE[self.surrogate]
+        c.surrogate_hidden = int(self.surrogate_hidden)
+        c.surrogate_buffer = int(self.surrogate_buffer)
+        c.surrogate_steps = int(self.surrogate_steps)
+        c.surrogate_batch = int(self.surrogate_batch)
+        c.audit = int(self.audit)
+        c.prescreen_frac = float(self.prescreen_frac)
+        c.surrogate_lr = float(self.surrogate_lr)
+        c.surrogate_recent = float(self.surrogate_recent)
         c.p_crossover = float(self.p_crossover)
         c.p_mutation = float(self.p_mutation)
         c.mutation_sigma = float(self.mutation_sigma)
@@ -194,6 +212,70 @@ class Game:
         L.check(L.lib().game_rescore(self._ctx, _ptr(genes), int(n), _ptr(out[0]), _ptr(out[1])),
                 "game_rescore")
         return out[0], out[1]
+
+    def surrogate_log(self, n_max: int = 4096):
+        """Per-generation (rho_audit, rho_selected, loss) of the offspring form, oldest first."""
+        buf = (C.c_float * (4 * n_max))()
+        n = C.c_int32()
+        L.check(L.lib().game_surrogate_log(self._ctx, buf, int(n_max), C.byref(n)), "game_surrogate_log")
+        return np.frombuffer(buf, dtype=np.float32)[:4 * n.value].reshape(n.value, 4)[:, :3].copy()
+
+    def surrogate_buffer(self):
+        """Replay buffer: (genes cap x L, log-MSE targets, count, head, mu, sigma)."""
+        torch = _torch()
+        cap = self.cfg.surrogate_buffer
+        genes = torch.empty((cap, self.L), dtype=torch.float32, device=self.device)
+        y = torch.empty(cap, dtype=torch.float32, device=self.device)
+        ch = (C.c_int32 * 2)()
+        ms = (C.c_float * 2)()
+        L.check(L.lib().game_surrogate_buffer(self._ctx, _ptr(genes), _ptr(y), ch, ms),
+                "game_surrogate_buffer")
+        return genes, y, int(ch[0]), int(ch[1]), float(ms[0]), float(ms[1])
+
+    def mlp_params(self, params=None):
+        """Get (params None) or set the surrogate's flat float32 parameter vector."""
+        torch = _torch()
+        if params is None:
+            n = self.mlp_size()
+            out = torch.empty(n, dtype=torch.float32, device=self.device)
+            L.check(L.lib().game_mlp_params(self._ctx, _ptr(out), 0), "game_mlp_params")
+            return out
+        params = params.contiguous()
+        L.check(L.lib().game_mlp_params(self._ctx, _ptr(params), 1), "game_mlp_params")
+        self._mlp_keep = params
+
+    def mlp_size(self) -> int:
+        H, Lg = self.cfg.surrogate_hidden, self.L
+        return H * Lg + H + H * H + H + H + 1
+
+    def _rows(self, X):
+        X = X.contiguous()
+        if X.dtype != _torch().float32 or X.dim() != 2 or X.shape[1] != self.L or not X.is_cuda:
+            raise ValueError("rows must be a float32 n x L CUDA tensor")
+        return X
+
+    def mlp_forward(self, X):
+        torch = _torch()
+        X = self._rows(X)
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=self.device)
+        L.check(L.lib().game_mlp_forward(self._ctx, _ptr(X), X.shape[0], _ptr(y)), "game_mlp_forward")
+        return y
+
+    def mlp_grads(self, X, target):
+        torch = _torch()
+        X, target = self._rows(X), target.contiguous()
+        if target.dtype != torch.float32 or target.shape != (X.shape[0],):
+            raise ValueError("target must be a float32 CUDA tensor of n entries")
+        g = torch.empty(self.mlp_size(), dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        L.check(L.lib().game_mlp_grads(self._ctx, _ptr(X), _ptr(target), X.shape[0], _ptr(g),
+                                       _ptr(loss)), "game_mlp_grads")
+        return g, loss
+
+    def mlp_adam(self, grads):
+        grads = grads.contiguous()
+        L.check(L.lib().game_mlp_adam(self._ctx, _ptr(grads)), "game_mlp_adam")
+        self._grad_keep = grads
 
     @property
     def population(self):

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_function():
 
 def test_struct_layouts_match_the_header():
     # sizes computed by the C compiler for the declared structs
-    assert C.sizeof(L.GameConfig) == 104
+    assert C.sizeof(L.GameConfig) == 152
     assert C.sizeof(L.GameDims) == 40
     assert C.sizeof(L.GameResult) == 40
     assert C.sizeof(L.GameState) == 40
@@ -73,12 +73,30 @@ def test_query_derived_sizes():
     (dict(max_generations=0), L.GAME_E_INVALID),
     (dict(bias=2), L.GAME_E_INVALID),
     (dict(n_features=600, degree=8, basis="trig"), L.GAME_E_INVALID),
-    (dict(n_offspring=7), L.GAME_E_UNSUPPORTED),
+    (dict(n_offspring=7), L.GAME_E_INVALID),            # cannot refill P - elitism
+    (dict(n_offspring=9000), L.GAME_E_INVALID),
+    (dict(surrogate="mlp", n_offspring=80, prescreen_frac=0.1), L.GAME_E_INVALID),
+    (dict(surrogate="mlp", n_offspring=80, prescreen_frac=0.0), L.GAME_E_INVALID),
+    (dict(surrogate="mlp", n_offspring=80, surrogate_hidden=8), L.GAME_E_INVALID),
+    (dict(surrogate="mlp", n_offspring=80, surrogate_buffer=10, surrogate_batch=64), L.GAME_E_INVALID),
+    (dict(surrogate="mlp", n_offspring=80, audit=5000), L.GAME_E_INVALID),
+    (dict(surrogate="random", n_offspring=80, surrogate_lr=0.0), L.GAME_OK),
+    (dict(surrogate="mlp", n_offspring=80, surrogate_recent=1.5), L.GAME_E_INVALID),
+    (dict(n_offspring=40, dtype="f32", rescore_top=1), L.GAME_E_UNSUPPORTED),
 ])
 def test_invalid_configs_rejected(kw, status):
     st, _ = _query(**kw)
     assert st == status
-    assert L.lib().game_last_error()
+    if status != L.GAME_OK:
+        assert L.lib().game_last_error()
+
+
+def test_offspring_form_sizes():
+    st, d = _query(n_offspring=40)
+    assert st == L.GAME_OK and d.n_offspring == 40
+    st0, d0 = _query()
+    st1, d1 = _query(surrogate="mlp", n_offspring=80, prescreen_frac=0.25, audit=16)
+    assert st1 == L.GAME_OK and d1.workspace_bytes > d0.workspace_bytes
 
 
 def test_bad_enum_and_struct_size():

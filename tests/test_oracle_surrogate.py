@@ -99,6 +99,25 @@ def test_minibatch_slots_range_and_spread():
     assert not np.array_equal(s, mlp.minibatch_slots(18, 4096, 50000, seed=3))
 
 
+def test_minibatch_recent_rows_come_from_latest_append():
+    # ring of 1000 slots, full, latest append of 120 rows ended just before slot 50:
+    # those rows sit in slots 930..999 and 0..49
+    B, n_rec = 512, mlp.recent_rows(512, 0.75)
+    assert n_rec == 384
+    s = mlp.minibatch_slots(5, B, 1000, seed=11, n_recent=n_rec, head=50, last=120, cap=1000)
+    old, rec = s[:B - n_rec], s[B - n_rec:]
+    window = set(range(930, 1000)) | set(range(0, 50))
+    assert set(rec.tolist()) <= window
+    assert len(set(rec.tolist())) > 100          # spread over the window
+    # the uniform part is the plain rule on the same words
+    np.testing.assert_array_equal(old, mlp.minibatch_slots(5, B, 1000, seed=11)[:B - n_rec])
+    # brute force on a tiny case: with last = 1 every recent row is slot head - 1
+    s1 = mlp.minibatch_slots(2, 8, 10, seed=1, n_recent=3, head=0, last=1, cap=10)
+    assert s1[5:].tolist() == [9, 9, 9]
+    assert mlp.recent_rows(1024, 0.0) == 0 and mlp.recent_rows(1024, 1.0) == 1024
+    assert mlp.recent_rows(3, 0.5) == 2           # halves round up
+
+
 def test_merge_survivors_keeps_elites_and_best_candidates():
     pop = synth.random_population(10, 4, seed=1)
     fit_pop = synth.random_fitness(10, seed=2)
