@@ -110,6 +110,14 @@ typedef struct {
                             /* chromosomes in float32 and tracks the best and     */
                             /* tests the stop rule on those float32 MSEs (meant   */
                             /* for BF16/F16; not available with F64)              */
+  int32_t  tile_p;          /* chromosomes per fitness workgroup tile: 0 = chosen */
+                            /* by the library; 32 | 64 | 128 select the LDS-staged */
+                            /* kernel with that tile (F32/BF16/F16; the tile must */
+                            /* fit the kernel's 96 KiB of LDS); F64 uses 64       */
+  int32_t  row_groups;      /* 0 = chosen by the library; R > 0 splits the rows  */
+                            /* into R ranges whose partial sums are added in      */
+                            /* order (this fixes the summation order, so equal    */
+                            /* tile_p and row_groups give bit-identical sums)     */
   int32_t  surrogate;       /* offspring form prescreen: game_surrogate           */
   int32_t  surrogate_hidden;/* hidden width of both MLP layers, 16..1024          */
   int32_t  surrogate_buffer;/* replay ring capacity (pairs), >= surrogate_batch    */

@@ -35,6 +35,8 @@ class GameConfig(C.Structure):
         ("tournament_k", C.c_int32),
         ("max_generations", C.c_int32),
         ("rescore_top", C.c_int32),
+        ("tile_p", C.c_int32),
+        ("row_groups", C.c_int32),
         ("surrogate", C.c_int32),
         ("surrogate_hidden", C.c_int32),
         ("surrogate_buffer", C.c_int32),

@@ -14,7 +14,6 @@
 #include "game_internal.hpp"
 
 namespace game {
-void fitness_tile(int dtype, int* tile_n, int* tile_p);
 }
 
 using namespace game;
@@ -161,11 +160,32 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   p->E = c->elitism;
   p->k = c->tournament_k;
   p->P_max = (int)(offspring ? std::max<int64_t>(P, p->P_eval) : std::max<int64_t>(P, n_off));
-  fitness_tile(c->dtype, &p->tile_n, &p->tile_p);
+  // fitness tile: tile_n patterns x tile_p chromosomes; buffers are sized for
+  // every tile width, so a context can switch tile_p without a new workspace
+  if (c->row_groups < 0) return bad("row_groups must be >= 0");
+  p->row_groups = c->row_groups;
+  if (c->dtype == GAME_F64) {
+    if (c->tile_p != 0 && c->tile_p != 64) return bad("tile_p must be 0 or 64 with F64");
+    p->tile_n = 64;
+    p->tile_p = 64;
+    p->lds = false;
+  } else {
+    p->tile_n = 128;
+    if (c->tile_p == 0) {
+      p->tile_p = fitness_lds_fits(c->dtype, p->M_pad, 128) ? 128 : 64;
+      p->lds = fitness_lds_fits(c->dtype, p->M_pad, p->tile_p) != 0;
+      if (!p->lds) p->tile_p = 128;  // streaming kernel, 128 x 128 tiles
+    } else {
+      if (c->tile_p != 32 && c->tile_p != 64 && c->tile_p != 128) return bad("tile_p must be 0, 32, 64 or 128");
+      if (!fitness_lds_fits(c->dtype, p->M_pad, c->tile_p)) return bad("a tile of tile_p chromosomes does not fit in LDS at this gene count");
+      p->tile_p = c->tile_p;
+      p->lds = true;
+    }
+  }
   p->N = c->n_patterns;
   p->N_pad = round_up(p->N, p->tile_n);
   p->n_rt = p->N_pad / p->tile_n;
-  p->P_max_pad = (int)round_up(p->P_max, p->tile_p);
+  p->P_max_pad = (int)round_up(p->P_max, 128);
   p->n_rg_max = p->n_rt < 8193 ? p->n_rt : 8193;
   p->rt_per_wg_max = (int)((p->n_rt + p->n_rg_max - 1) / p->n_rg_max);
   p->elt = c->dtype == GAME_F64 ? 8 : c->dtype == GAME_F32 ? 4 : 2;
@@ -190,7 +210,7 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   p->off_elite = take(kMaxElite * 4);
   p->off_state = take(sizeof(DevState));
   p->off_best = take((size_t)L * 4);
-  p->n_pt_cap = p->P_max_pad / p->tile_p;
+  p->n_pt_cap = (int)round_up(p->P_max, 32) / 32;  // tiles at the narrowest width
   p->n_counters = p->n_pt_cap + 3;
   p->off_cnt = take((size_t)p->n_counters * 4);
   // float32 copy of the patterns and re-score partials (not kept for F64)
@@ -248,7 +268,7 @@ FitnessGeom fitness_geometry(const Plan& p, int task, int dtype, int P_eval) {
   const int slots = fitness_persistent_slots(p, task, dtype);
   if (slots > 0) {
     // persistent: one workgroup per (row range, chromosome tile), as many as are resident
-    int64_t R = slots / g.n_pt;
+    int64_t R = p.row_groups > 0 ? p.row_groups : slots / g.n_pt;
     if (R < 1) R = 1;
     if (R > p.n_rt) R = p.n_rt;
     if (R > p.n_rg_max) R = p.n_rg_max;
@@ -261,7 +281,8 @@ FitnessGeom fitness_geometry(const Plan& p, int task, int dtype, int P_eval) {
   // Enough workgroups to fill 256 CUs many times over, few enough that the
   // partial sums stay small next to the Phi traffic.
   const int64_t target = 8192;
-  int64_t rpw = (p.n_rt * g.n_pt + target - 1) / target;
+  int64_t rpw = p.row_groups > 0 ? (p.n_rt + p.row_groups - 1) / p.row_groups
+                                 : (p.n_rt * g.n_pt + target - 1) / target;
   if (rpw < 1) rpw = 1;
   if ((p.n_rt + rpw - 1) / rpw > p.n_rg_max) rpw = (p.n_rt + p.n_rg_max - 1) / p.n_rg_max;
   g.rt_per_wg = (int)rpw;

@@ -371,31 +371,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // blocks of 16 x 16), so every Phi row is read by exactly one wave.  The next
 // row tile's targets and first Phi K-block are fetched before the current
 // epilogue.  One partial row per workgroup: part[wr][p].
-template <class Tr, bool kCls>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fitness_lds_kernel(
-    const typename Tr::T* __restrict__ phi, const typename Tr::T* __restrict__ tile,
-    const typename Tr::Acc* __restrict__ biasv, const typename Tr::Acc* __restrict__ tvec,
-    int64_t N, int M_pad, int ldsw, int64_t n_rt, int n_pt, int n_ranges, int64_t n_items,
-    int part_ld, double* __restrict__ part_sse, uint32_t* __restrict__ part_miss,
-    const DevState* st, const FitTail tail) {
+// One work item of the LDS-staged kernels: chromosome tile pt (TP = 16 WN
+// chromosomes, staged in LDS) against row range wr of n_ranges (consecutive
+// 128-pattern row tiles, 32 rows per wave); writes the range's partial sums
+// part_sse / part_miss[wr][pt * TP ..].  The single-context and the batched
+// kernels run exactly this code, so a chromosome's sums do not depend on
+// which of them evaluated it.
+template <class Tr, bool kCls, int WN>
+__device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
+                                         const typename Tr::T* __restrict__ tile,
+                                         const typename Tr::Acc* __restrict__ biasv,
+                                         const typename Tr::Acc* __restrict__ tvec, int64_t N,
+                                         int M_pad, int ldsw, int64_t n_rt, int n_ranges, int pt,
+                                         int wr, int part_ld, double* __restrict__ part_sse,
+                                         uint32_t* __restrict__ part_miss, uint32_t* lds) {
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
   using AccV = typename Tr::AccV;
   using Ld = typename Tr::Ld;
-  constexpr int WM = 2, WN = 8, TN = 128, TP = 128;
+  constexpr int WM = 2, TN = 128, TP = 16 * WN;
   constexpr int kLdWords = (int)(sizeof(Ld) / 4);
   constexpr int kBlkWords = Tr::kBlk * (int)sizeof(T) / 4;
-  extern __shared__ __align__(16) uint32_t lds[];
-  __shared__ double s_sse[4][TP];
-  __shared__ uint32_t s_miss[4][TP];
+  // LDS: the gene tile (TP rows of ldsw words), then the per-wave column sums
+  double (*s_sse)[TP] = reinterpret_cast<double (*)[TP]>(lds + TP * ldsw);
+  uint32_t (*s_miss)[TP] = reinterpret_cast<uint32_t (*)[TP]>(lds + TP * ldsw + 8 * TP);
 
-  if (run_halted(st)) return;
-  const int64_t nwg = gridDim.x;
-  const int64_t w = blockIdx.x;
-  const int64_t lt = (w & 7) * (nwg >> 3) + (w >> 3);
-  if (lt >= n_items) return;
-  const int pt = (int)(lt % n_pt);
-  const int wr = (int)(lt / n_pt);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lrow = lane & 15, lgrp = lane >> 4;
   const int KB = M_pad / Tr::kBlk;
@@ -580,7 +580,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     st_agent(part_sse + o, ((s_sse[0][tid] + s_sse[1][tid]) + s_sse[2][tid]) + s_sse[3][tid]);
     st_agent(part_miss + o, s_miss[0][tid] + s_miss[1][tid] + s_miss[2][tid] + s_miss[3][tid]);
   }
-  fitness_tail<TP>(tail, pt, n_pt, n_ranges, part_ld, part_sse, part_miss);
+}
+
+template <class Tr, bool kCls, int WN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fitness_lds_kernel(
+    const typename Tr::T* __restrict__ phi, const typename Tr::T* __restrict__ tile,
+    const typename Tr::Acc* __restrict__ biasv, const typename Tr::Acc* __restrict__ tvec,
+    int64_t N, int M_pad, int ldsw, int64_t n_rt, int n_pt, int n_ranges, int64_t n_items,
+    int part_ld, double* __restrict__ part_sse, uint32_t* __restrict__ part_miss,
+    const DevState* st, const FitTail tail) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  if (run_halted(st)) return;
+  const int64_t nwg = gridDim.x;
+  const int64_t w = blockIdx.x;
+  const int64_t lt = (w & 7) * (nwg >> 3) + (w >> 3);
+  if (lt >= n_items) return;
+  const int pt = (int)(lt % n_pt);
+  const int wr = (int)(lt / n_pt);
+  lds_item<Tr, kCls, WN>(phi, tile, biasv, tvec, N, M_pad, ldsw, n_rt, n_ranges, pt, wr, part_ld,
+                         part_sse, part_miss, lds);
+  fitness_tail<16 * WN>(tail, pt, n_pt, n_ranges, part_ld, part_sse, part_miss);
 }
 
 template <class Tr, int WM, int WN>
@@ -613,86 +632,132 @@ int lds_stride_words(int M_pad) {
   return s;
 }
 
+// Dynamic LDS of one LDS-kernel workgroup: gene tile plus column sums.
 template <class Tr>
-auto lds_kernel_for(int task) {
-  return task == GAME_CLASSIFICATION ? fitness_lds_kernel<Tr, true> : fitness_lds_kernel<Tr, false>;
+size_t lds_bytes(int M_pad, int tp) {
+  return (size_t)tp * lds_stride_words<Tr>(M_pad) * 4 + (size_t)tp * 48;
 }
+constexpr size_t kLdsMax = 98304;  // dynamic LDS one workgroup may take
+
+template <class Tr, int WN>
+auto lds_kernel_wn(int task) {
+  return task == GAME_CLASSIFICATION ? fitness_lds_kernel<Tr, true, WN> : fitness_lds_kernel<Tr, false, WN>;
+}
+template <class Tr>
+const void* lds_kernel_for(int task, int tp) {
+  if (tp == 128) return reinterpret_cast<const void*>(lds_kernel_wn<Tr, 8>(task));
+  if (tp == 64) return reinterpret_cast<const void*>(lds_kernel_wn<Tr, 4>(task));
+  return reinterpret_cast<const void*>(lds_kernel_wn<Tr, 2>(task));
+}
+int tp_index(int tp) { return tp == 128 ? 0 : tp == 64 ? 1 : 2; }
 
 // Dynamic LDS above 64 KiB has to be enabled per kernel once.
 template <class Tr>
-hipError_t lds_prepare(int task) {
-  static bool done[2] = {false, false};
-  const int ai = task == GAME_CLASSIFICATION ? 1 : 0;
-  if (done[ai]) return hipSuccess;
-  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(lds_kernel_for<Tr>(task)),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 98304);
-  if (e == hipSuccess) done[ai] = true;
+hipError_t lds_prepare(int task, int tp) {
+  static bool done[2][3] = {};
+  const int ai = task == GAME_CLASSIFICATION ? 1 : 0, ti = tp_index(tp);
+  if (done[ai][ti]) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(lds_kernel_for<Tr>(task, tp),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+  if (e == hipSuccess) done[ai][ti] = true;
   return e;
+}
+
+template <class Tr, int WN>
+hipError_t launch_lds_wn(int task, const FitnessGeom& g, const Plan& p, const void* phi,
+                         const void* tile, const void* biasv, const void* tvec, double* psse,
+                         uint32_t* pmiss, const DevState* st, const FitTail& tail, hipStream_t s) {
+  using T = typename Tr::T;
+  using Acc = typename Tr::Acc;
+  const int ldsw = lds_stride_words<Tr>(p.M_pad);
+  const size_t lds = lds_bytes<Tr>(p.M_pad, 16 * WN);
+  const hipError_t e = lds_prepare<Tr>(task, 16 * WN);
+  if (e != hipSuccess) return e;
+  if (task == GAME_CLASSIFICATION)
+    hipLaunchKernelGGL((fitness_lds_kernel<Tr, true, WN>), dim3((unsigned)g.grid), dim3(256), lds, s,
+                       (const T*)phi, (const T*)tile, (const Acc*)biasv, (const Acc*)tvec, p.N,
+                       p.M_pad, ldsw, p.n_rt, g.n_pt, (int)g.n_rg, g.n_items, p.P_max_pad, psse,
+                       pmiss, st, tail);
+  else
+    hipLaunchKernelGGL((fitness_lds_kernel<Tr, false, WN>), dim3((unsigned)g.grid), dim3(256), lds,
+                       s, (const T*)phi, (const T*)tile, (const Acc*)biasv, (const Acc*)tvec, p.N,
+                       p.M_pad, ldsw, p.n_rt, g.n_pt, (int)g.n_rg, g.n_items, p.P_max_pad, psse,
+                       pmiss, st, tail);
+  return hipGetLastError();
 }
 
 template <class Tr>
 hipError_t launch_lds(int task, const FitnessGeom& g, const Plan& p, const void* phi,
                       const void* tile, const void* biasv, const void* tvec, double* psse,
                       uint32_t* pmiss, const DevState* st, const FitTail& tail, hipStream_t s) {
-  using T = typename Tr::T;
-  using Acc = typename Tr::Acc;
-  const int ldsw = lds_stride_words<Tr>(p.M_pad);
-  const size_t lds = (size_t)128 * ldsw * 4;
-  const hipError_t e = lds_prepare<Tr>(task);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(lds_kernel_for<Tr>(task), dim3((unsigned)g.grid), dim3(256), lds, s,
-                     (const T*)phi, (const T*)tile, (const Acc*)biasv, (const Acc*)tvec, p.N,
-                     p.M_pad, ldsw, p.n_rt, g.n_pt, (int)g.n_rg, g.n_items, p.P_max_pad, psse,
-                     pmiss, st, tail);
-  return hipGetLastError();
+  switch (p.tile_p) {
+    case 128:
+      return launch_lds_wn<Tr, 8>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
+    case 64:
+      return launch_lds_wn<Tr, 4>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
+    case 32:
+      return launch_lds_wn<Tr, 2>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
+  }
+  return hipErrorInvalidValue;
 }
 
-// Workgroups of the LDS kernel that are resident at once on the device.
-template <class Tr>
-int lds_resident(int task, int M_pad) {
-  static int cache[2][8192 / 8 + 1] = {};
-  const int ai = task == GAME_CLASSIFICATION ? 1 : 0;
-  const int ci = M_pad / 8 < 1024 ? M_pad / 8 : 1024;
-  if (cache[ai][ci]) return cache[ai][ci];
-  if (lds_prepare<Tr>(task) != hipSuccess) return 0;
-  const size_t lds = (size_t)128 * lds_stride_words<Tr>(M_pad) * 4;
-  int blocks = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &blocks, reinterpret_cast<const void*>(lds_kernel_for<Tr>(task)), 256, lds) != hipSuccess)
-    return 0;
+// Workgroups of an LDS kernel that are resident at once on the device.
+int device_cus() {
+  static int cus = 0;
+  if (cus) return cus;
+  int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  cache[ai][ci] = blocks * cus;
-  return cache[ai][ci];
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+  return cus;
 }
 
-// The LDS variant needs 128 rows of the padded gene tile in at most 96 KiB.
 template <class Tr>
-bool lds_fits(const Plan& p) {
-  return (size_t)128 * lds_stride_words<Tr>(p.M_pad) * 4 <= 98304;
+int lds_resident(int task, int M_pad, int tp) {
+  static int cache[2][3][8192 / 8 + 1] = {};
+  const int ai = task == GAME_CLASSIFICATION ? 1 : 0, ti = tp_index(tp);
+  const int ci = M_pad / 8 < 1024 ? M_pad / 8 : 1024;
+  if (cache[ai][ti][ci]) return cache[ai][ti][ci];
+  if (lds_prepare<Tr>(task, tp) != hipSuccess) return 0;
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, lds_kernel_for<Tr>(task, tp), 256,
+                                                   lds_bytes<Tr>(M_pad, tp)) != hipSuccess)
+    return 0;
+  cache[ai][ti][ci] = blocks * device_cus();
+  return cache[ai][ti][ci];
+}
+
+template <class Tr>
+bool lds_fits(int M_pad, int tp) {
+  return lds_bytes<Tr>(M_pad, tp) <= kLdsMax;
 }
 
 }  // namespace
 
-// Workgroup tile per dtype: rows x chromosomes = (32 WM) x (32 WN).
-void fitness_tile(int dtype, int* tile_n, int* tile_p) {
-  if (dtype == GAME_F64) {
-    *tile_n = 64;
-    *tile_p = 64;
-  } else {
-    *tile_n = 128;
-    *tile_p = 128;
+size_t fitness_lds_bytes(int dtype, int M_pad, int tp) {
+  switch (dtype) {
+    case GAME_F32: return lds_bytes<F32Tr>(M_pad, tp);
+    case GAME_BF16: return lds_bytes<BF16Tr>(M_pad, tp);
+    case GAME_F16: return lds_bytes<F16Tr>(M_pad, tp);
   }
+  return 0;
+}
+
+int fitness_lds_fits(int dtype, int M_pad, int tp) {
+  if (tp != 128 && tp != 64 && tp != 32) return 0;
+  switch (dtype) {
+    case GAME_F32: return lds_fits<F32Tr>(M_pad, tp);
+    case GAME_BF16: return lds_fits<BF16Tr>(M_pad, tp);
+    case GAME_F16: return lds_fits<F16Tr>(M_pad, tp);
+  }
+  return 0;
 }
 
 int fitness_persistent_slots(const Plan& p, int task, int dtype) {
+  if (!p.lds) return 0;
   switch (dtype) {
-    case GAME_F32:
-      return lds_fits<F32Tr>(p) ? lds_resident<F32Tr>(task, p.M_pad) : 0;
-    case GAME_BF16:
-      return lds_fits<BF16Tr>(p) ? lds_resident<BF16Tr>(task, p.M_pad) : 0;
-    case GAME_F16:
-      return lds_fits<F16Tr>(p) ? lds_resident<F16Tr>(task, p.M_pad) : 0;
+    case GAME_F32: return lds_resident<F32Tr>(task, p.M_pad, p.tile_p);
+    case GAME_BF16: return lds_resident<BF16Tr>(task, p.M_pad, p.tile_p);
+    case GAME_F16: return lds_resident<F16Tr>(task, p.M_pad, p.tile_p);
   }
   return 0;
 }
@@ -705,15 +770,15 @@ hipError_t launch_fitness(const Plan& p, int task, int dtype, const FitnessGeom&
     case GAME_F64:
       return launch_tr<F64Tr, 2, 2>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
     case GAME_F32:
-      if (lds_fits<F32Tr>(p))
+      if (p.lds)
         return launch_lds<F32Tr>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
       return launch_tr<F32Tr, 4, 4>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
     case GAME_BF16:
-      if (lds_fits<BF16Tr>(p))
+      if (p.lds)
         return launch_lds<BF16Tr>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
       return launch_tr<BF16Tr, 4, 4>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
     case GAME_F16:
-      if (lds_fits<F16Tr>(p))
+      if (p.lds)
         return launch_lds<F16Tr>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
       return launch_tr<F16Tr, 4, 4>(task, g, p, phi, tile, biasv, tvec, psse, pmiss, st, tail, s);
   }

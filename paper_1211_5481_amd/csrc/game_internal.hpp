@@ -107,6 +107,8 @@ struct Plan {
   int K, M, L, M_pad, P, n_off, E, P_max, k;
   int64_t N, N_pad;
   int tile_n, tile_p;          // fitness workgroup tile (rows x chromosomes)
+  bool lds;                    // LDS-staged fitness kernel (else the streaming one)
+  int row_groups;              // fixed row ranges of the fitness sums (0: automatic)
   int64_t n_rt;                // row tiles
   int P_max_pad;               // P_max rounded up to tile_p
   int rt_per_wg_max;           // bounds the partial buffer
@@ -155,6 +157,9 @@ struct FitnessGeom {
 // Workgroups of the persistent (LDS) fitness kernel resident at once, or 0
 // when the configuration uses the non-persistent kernel.
 int fitness_persistent_slots(const Plan& p, int task, int dtype);
+// LDS-staged kernel: does a tile of tp chromosomes fit, and its dynamic LDS
+int fitness_lds_fits(int dtype, int M_pad, int tp);
+size_t fitness_lds_bytes(int dtype, int M_pad, int tp);
 FitnessGeom fitness_geometry(const Plan& p, int task, int dtype, int P_eval);
 
 hipError_t launch_fitness(const Plan& p, int task, int dtype, const FitnessGeom& g, const void* phi,

@@ -31,6 +31,8 @@ class Config:
     tournament_k: int = 3
     max_generations: int = 100
     rescore_top: int = 0              # per-generation float32 re-score of the top-k
+    tile_p: int = 0                   # fitness tile width: 0 (library's choice) | 32 | 64 | 128
+    row_groups: int = 0               # fitness row ranges: 0 (library's choice) | R
     surrogate: str = "none"           # offspring form prescreen: none | mlp | random
     surrogate_hidden: int = 256
     surrogate_buffer: int = 50000
@@ -63,6 +65,8 @@ class Config:
         c.tournament_k = int(self.tournament_k)
         c.max_generations = int(self.max_generations)
         c.rescore_top = int(self.rescore_top)
+        c.tile_p = int(self.tile_p)
+        c.row_groups = int(self.row_groups)
         c.surrogate = L.SURROGATE[self.surrogate]
         c.surrogate_hidden = int(self.surrogate_hidden)
         c.surrogate_buffer = int(self.surrogate_buffer)

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_function():
 
 def test_struct_layouts_match_the_header():
     # sizes computed by the C compiler for the declared structs
-    assert C.sizeof(L.GameConfig) == 152
+    assert C.sizeof(L.GameConfig) == 160
     assert C.sizeof(L.GameDims) == 40
     assert C.sizeof(L.GameResult) == 40
     assert C.sizeof(L.GameState) == 40
@@ -83,6 +83,11 @@ def test_query_derived_sizes():
     (dict(surrogate="random", n_offspring=80, surrogate_lr=0.0), L.GAME_OK),
     (dict(surrogate="mlp", n_offspring=80, surrogate_recent=1.5), L.GAME_E_INVALID),
     (dict(n_offspring=40, dtype="f32", rescore_top=1), L.GAME_E_UNSUPPORTED),
+    (dict(tile_p=128), L.GAME_E_INVALID),                       # F64 tiles are 64 wide
+    (dict(dtype="f32", tile_p=48), L.GAME_E_INVALID),
+    (dict(dtype="f32", tile_p=128, n_features=20, degree=8, basis="trig"), L.GAME_E_INVALID),
+    (dict(dtype="f32", tile_p=64, n_features=20, degree=8, basis="trig"), L.GAME_OK),
+    (dict(dtype="f32", row_groups=-1), L.GAME_E_INVALID),
 ])
 def test_invalid_configs_rejected(kw, status):
     st, _ = _query(**kw)

@@ -164,3 +164,37 @@ def test_workload_c3_full_size_sampled(dtype):
     check_against_oracle(X, t, pop[idx], "legendre", D, "classification", 0, dtype, mse[idx],
                          miscls[idx], fit[idx], label="c3")
     g.close()
+
+
+TILE_CASES = [
+    # basis, dtype, task, N, F, D, P, tile_p, row_groups
+    ("legendre", "f32", "regression", 3001, 5, 3, 200, 32, 0),
+    ("legendre", "f32", "regression", 3001, 5, 3, 200, 64, 7),
+    ("legendre", "f32", "regression", 3001, 5, 3, 200, 128, 1),
+    ("trig", "f32", "classification", 5000, 20, 8, 130, 0, 0),     # M = 320: 64-wide tiles
+    ("trig", "f32", "classification", 5000, 20, 8, 130, 32, 3),
+    ("legendre", "bf16", "classification", 4097, 16, 8, 300, 32, 5),
+    ("legendre", "f16", "regression", 4097, 16, 8, 300, 64, 0),
+]
+
+
+@pytest.mark.parametrize("case", TILE_CASES, ids=lambda c: "-".join(map(str, c)))
+def test_tile_widths_and_row_groups(case):
+    """Every tile width and row split agrees with the oracle; a fixed
+    (tile_p, row_groups) pair gives the same bits in a second context."""
+    torch = require_gpu()
+    from paper_1211_5481_amd import Config, Game
+    basis, dtype, task, N, F, D, P, tp, rg = case
+    X, t = make_data(task, N, F, seed=N + P)
+    cfg = Config(n_patterns=N, n_features=F, degree=D, basis=basis, task=task, dtype=dtype,
+                 pop_size=P, tile_p=tp, row_groups=rg, seed=3)
+    announce(f"tile widths {case}")
+    g = Game(cfg, dev(X, torch.float32), dev(t, torch.float32))
+    G = synth.random_population(P, g.L, seed=P + 1)
+    mse, miscls, fit = (host(a) for a in g.eval_fitness(dev(G, torch.float32)))
+    check_against_oracle(X, t, G, basis, D, task, 0, dtype, mse, miscls, fit, label=str(case))
+    h = Game(cfg, dev(X, torch.float32), dev(t, torch.float32))
+    again = host(h.eval_fitness(dev(G, torch.float32))[0])
+    assert np.array_equal(again.view(np.uint64), mse.view(np.uint64))
+    g.close()
+    h.close()
