@@ -320,6 +320,61 @@ game_status game_time_fitness(game_ctx* ctx, int32_t reps, float* ms);
 /* Release the context (host memory only; the workspace stays the caller's). */
 void game_destroy(game_ctx* ctx);
 
+/*
+ * Batched form: many independent GA runs (each one context with its own
+ * configuration, patterns, population and stop rule) advanced together.
+ * Every generation is one persistent fitness launch in which workgroups take
+ * (run, chromosome tile, row range) items from a device queue, followed by
+ * one breed launch over all runs; chunks of generations are replayed from a
+ * captured HIP graph.  Requirements: 1..4096 runs, one dtype for all (F32,
+ * BF16 or F16), the generational GA (no offspring form, no re-score), gene
+ * counts whose tiles fit the LDS-staged kernel.  Each run computes exactly
+ * what game_run would on a context created with the same configuration and
+ * the tile_p / row_groups the batch uses (game_batch_tiles).
+ */
+typedef struct game_batch game_batch;
+
+/* Workspace bytes for the batch (the runs' workspaces plus the batch's tables). */
+game_status game_batch_workspace_size(const game_config* cfgs, int32_t n_runs, size_t* bytes);
+
+/*
+ * Create the runs (as game_init: basis, targets, initial population) in one
+ * workspace, then pick each run's tile width and row ranges: configurations
+ * with tile_p and row_groups both set keep them when every run sets them;
+ * otherwise the tuner times candidate assignments of the batched fitness
+ * launch on the device and keeps the fastest.  Blocking.
+ *   X_devs[i], t_devs[i]: run i's patterns and targets, as for game_init.
+ */
+game_status game_batch_init(const game_config* cfgs, int32_t n_runs, const void* const* X_devs,
+                            const void* const* t_devs, void* workspace_dev, size_t ws_bytes,
+                            void* stream, game_batch** out);
+
+/* Tile width and row ranges each run uses (host arrays of n_runs, either may be NULL). */
+game_status game_batch_tiles(game_batch* batch, int32_t* tile_p_host, int32_t* row_groups_host);
+
+/* Run i's context, for inspection (population, state, fitness); owned by the batch. */
+game_status game_batch_context(game_batch* batch, int32_t i, game_ctx** out);
+
+/* Mean duration (ms) of one batched fitness launch over the current populations; blocking. */
+game_status game_batch_time_fitness(game_batch* batch, int32_t reps, float* ms);
+
+/*
+ * Run every run until its own stop rule holds (as game_run), blocking.
+ *   results: n_runs records (best_genes may be NULL or L_i host floats).
+ *   latency_us: NULL, or n_runs x G doubles (G = largest max_generations):
+ *     entry [i][g] = microseconds from the start of batched generation g's
+ *     fitness launch to the end of run i's breed in it, -1 where run i did
+ *     not breed in generation g.
+ */
+game_status game_batch_run(game_batch* batch, game_result* results, double* latency_us);
+
+void game_batch_destroy(game_batch* batch);
+
+/* game_batch_init + game_batch_run + game_batch_destroy. */
+game_status game_run_batched(const game_config* cfgs, int32_t n_runs, const void* const* X_devs,
+                             const void* const* t_devs, void* workspace_dev, size_t ws_bytes,
+                             void* stream, game_result* results, double* latency_us);
+
 const char* game_status_str(game_status s);
 const char* game_last_error(void);
 

@@ -109,6 +109,14 @@ SIGNATURES = {
     "game_mlp_forward": (C.c_int, [_VP, _VP, C.c_int32, _VP]),
     "game_mlp_grads": (C.c_int, [_VP, _VP, _VP, C.c_int32, _VP, _VP]),
     "game_mlp_adam": (C.c_int, [_VP, _VP]),
+    "game_batch_workspace_size": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_size_t)]),
+    "game_batch_init": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, C.c_size_t, _VP, C.POINTER(_VP)]),
+    "game_batch_tiles": (C.c_int, [_VP, _VP, _VP]),
+    "game_batch_context": (C.c_int, [_VP, C.c_int32, C.POINTER(_VP)]),
+    "game_batch_time_fitness": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_float)]),
+    "game_batch_run": (C.c_int, [_VP, _VP, _VP]),
+    "game_batch_destroy": (None, [_VP]),
+    "game_run_batched": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, C.c_size_t, _VP, _VP, _VP]),
     "game_get_population": (C.c_int, [_VP, _VP]),
     "game_set_population": (C.c_int, [_VP, _VP]),
     "game_get_state": (C.c_int, [_VP, C.POINTER(GameState), _VP]),

@@ -256,6 +256,7 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
       p->off_tb = take(B * 4);
       p->off_buf = take((size_t)p->cap * Lz * 4);
       p->off_bufy = take((size_t)p->cap * 4);
+      p->off_part = take((size_t)kMlpPartFloats * 4);
     }
   }
   p->total = off;
@@ -386,7 +387,9 @@ game_status enqueue_eval_population(game_ctx* c, double* mse, double* miscls, do
   return GAME_OK;
 }
 
-game_status enqueue_evolve(game_ctx* c, const double* fit, hipStream_t s) {
+// Breed arguments of the generational form: E elites and P - E children
+// written to the next population buffer and the gene tile.
+BreedArgs evolve_args(game_ctx* c, const double* fit) {
   const Plan& p = c->plan;
   BreedArgs a{};
   a.pop0 = c->pop0;
@@ -409,6 +412,11 @@ game_status enqueue_evolve(game_ctx* c, const double* fit, hipStream_t s) {
   a.M_pad = p.M_pad;
   a.bias = c->cfg.bias;
   a.counter = c->counters + p.n_pt_cap + 1;
+  return a;
+}
+
+game_status enqueue_evolve(game_ctx* c, const double* fit, hipStream_t s) {
+  const BreedArgs a = evolve_args(c, fit);
   GAME_TRY(dev(c, launch_breed(c->cfg.dtype, a, c->state, s), "breed"));
   c->tile_fresh = true;  // breed writes the new population into the tile
   return GAME_OK;
@@ -483,7 +491,7 @@ game_status enqueue_offspring_generation(game_ctx* c, hipStream_t s) {
   if (p.sur == GAME_SURROGATE_MLP) {
     GAME_TRY(dev(c,
                  mlp_forward(mlp_dims(c), c->prm, c->O, p.n_off, nullptr, c->scr.h1, nullptr,
-                             c->scr.h2, c->yhat, st, s),
+                             c->scr.h2, c->yhat, c->scr.part, c->scr.part_cap, st, s),
                  "mlp forward"));
     GAME_TRY(dev(c, sur_keys(0, c->yhat, nullptr, p.n_off, 0, st, c->cfg.seed, c->keys, s), "keys"));
     GAME_TRY(dev(c, sur_select(c->keys, p.n_off, k, c->sel, st, s), "prescreen"));
@@ -695,8 +703,8 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
       c->am = F(p.off_am);
       c->av = F(p.off_av);
       c->step = reinterpret_cast<int32_t*>(c->ws + p.off_step);
-      c->scr = MlpScratch{F(p.off_a1), F(p.off_h1), F(p.off_a2), F(p.off_h2),
-                          F(p.off_y), F(p.off_dy), F(p.off_da2), F(p.off_da1)};
+      c->scr = MlpScratch{F(p.off_a1), F(p.off_h1), F(p.off_a2), F(p.off_h2), F(p.off_y),
+                          F(p.off_dy), F(p.off_da2), F(p.off_da1), F(p.off_part), kMlpPartFloats};
       c->Xb = F(p.off_Xb);
       c->tb = F(p.off_tb);
       c->buf = F(p.off_buf);
@@ -922,7 +930,8 @@ game_status game_mlp_params(game_ctx* c, float* params, int32_t dir) {
 game_status game_mlp_forward(game_ctx* c, const float* X, int32_t n, float* y) {
   GAME_TRY(need_mlp(c));
   if (!X || !y || n < 1 || n > c->plan.rows_max) return fail(GAME_E_INVALID, "n must be in [1, %d]", c->plan.rows_max);
-  return dev(c, mlp_forward(mlp_dims(c), c->prm, X, n, nullptr, c->scr.h1, nullptr, c->scr.h2, y, nullptr, c->stream),
+  return dev(c, mlp_forward(mlp_dims(c), c->prm, X, n, nullptr, c->scr.h1, nullptr, c->scr.h2, y,
+                            c->scr.part, c->scr.part_cap, nullptr, c->stream),
              "mlp forward");
 }
 
@@ -1002,5 +1011,455 @@ const char* game_status_str(game_status s) {
 }
 
 const char* game_last_error(void) { return g_err; }
+
+}  // extern "C"
+
+// ====================================================== batched form
+// Many independent contexts advanced in lockstep: each generation is one
+// persistent fitness launch over a queue of (context, chromosome tile, row
+// range) items and one breed launch over every context's workgroups, both
+// replayed from a captured graph.  Each context keeps its own workspace,
+// state and stop rule; a stopped context's items and workgroups are skipped.
+struct game_batch {
+  std::vector<game_ctx*> ctx;
+  std::vector<size_t> ws_off;
+  int n = 0, dtype = 0;
+  hipStream_t stream = nullptr, cap = nullptr;
+  unsigned char* tab = nullptr;  // device tables
+  BatchFitRun* dfit = nullptr;
+  BatchBreedRun* dbreed = nullptr;
+  DevState** dstates = nullptr;
+  BatchQueue* q = nullptr;
+  uint64_t *t_start = nullptr, *t_done = nullptr;
+  int G = 0;  // timestamp slots per context
+  int64_t n_items = 0;
+  int fit_grid = 0, breed_grid = 0;
+  size_t fit_lds = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool poisoned = false;
+  std::vector<int> tile_p, row_groups;  // per context, as tuned
+  float tune_ms = 0.0f;
+};
+
+namespace {
+
+constexpr int kBatchChunk = 8;
+
+struct BatchLayout {
+  std::vector<size_t> ws_off;
+  size_t tab_off, fit_off, breed_off, states_off, q_off, ts_off, td_off, total;
+  int G;
+};
+
+game_status batch_layout(const game_config* cfgs, int n, BatchLayout* L, int* dtype) {
+  if (!cfgs || n < 1 || n > 4096) return fail(GAME_E_INVALID, "n_runs must be in [1, 4096]");
+  size_t off = 0;
+  int G = 1;
+  L->ws_off.resize(n);
+  for (int i = 0; i < n; ++i) {
+    Plan p;
+    char err[256];
+    const game_status s = game::make_plan(&cfgs[i], &p, err, sizeof(err));
+    if (s != GAME_OK) return fail(s, "run %d: %s", i, err);
+    if (i == 0) *dtype = cfgs[i].dtype;
+    if (cfgs[i].dtype != *dtype) return fail(GAME_E_INVALID, "all runs of a batch share one dtype");
+    if (cfgs[i].dtype == GAME_F64) return fail(GAME_E_UNSUPPORTED, "the batched form runs F32, BF16 or F16");
+    if (p.offspring || cfgs[i].rescore_top > 0)
+      return fail(GAME_E_UNSUPPORTED, "run %d: the batched form runs the generational GA only", i);
+    if (!p.lds) return fail(GAME_E_UNSUPPORTED, "run %d: too many genes for the LDS-staged kernel", i);
+    L->ws_off[i] = off;
+    off = align256(off + p.total);
+    G = std::max(G, cfgs[i].max_generations);
+  }
+  L->G = G;
+  L->tab_off = off;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L->fit_off = take(sizeof(BatchFitRun) * n);
+  L->breed_off = take(sizeof(BatchBreedRun) * n);
+  L->states_off = take(sizeof(DevState*) * n);
+  L->q_off = take(sizeof(BatchQueue));
+  L->ts_off = take(sizeof(uint64_t) * G);
+  L->td_off = take(sizeof(uint64_t) * (size_t)G * n);
+  L->total = off;
+  return GAME_OK;
+}
+
+game_status bdev(game_batch* b, hipError_t e, const char* what) {
+  if (e == hipSuccess) return GAME_OK;
+  b->poisoned = true;
+  return fail(GAME_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Device tables for the contexts' current tile widths and row ranges: items
+// of the contexts with the largest items first, so the queue ends on small
+// ones.
+game_status batch_tables(game_batch* b) {
+  std::vector<BatchFitRun> fit(b->n);
+  std::vector<BatchBreedRun> br(b->n);
+  std::vector<DevState*> states(b->n);
+  std::vector<double> cost(b->n);
+  std::vector<int> order(b->n);
+  b->fit_lds = 0;
+  for (int i = 0; i < b->n; ++i) {
+    game_ctx* c = b->ctx[i];
+    const Plan& p = c->plan;
+    const FitnessGeom g = fitness_geometry(p, c->cfg.task, c->cfg.dtype, p.P);
+    BatchFitRun& f = fit[i];
+    f.phi = c->phi;
+    f.tile = c->tile;
+    f.biasv = c->cfg.bias ? c->biasv : nullptr;
+    f.tvec = c->tvec;
+    f.psse = c->psse;
+    f.pmiss = c->pmiss;
+    f.st = c->state;
+    f.tail = make_tail(c, p.P, true, nullptr, nullptr, nullptr);
+    f.N = p.N;
+    f.n_rt = p.n_rt;
+    f.M_pad = p.M_pad;
+    f.ldsw = fitness_lds_stride(c->cfg.dtype, p.M_pad);
+    f.n_pt = g.n_pt;
+    f.n_ranges = (int)g.n_rg;
+    f.part_ld = p.P_max_pad;
+    f.task = c->cfg.task;
+    f.tile_p = p.tile_p;
+    cost[i] = (double)((p.n_rt + g.n_rg - 1) / g.n_rg) * p.tile_p * p.M_pad;
+    order[i] = i;
+    b->fit_lds = std::max(b->fit_lds, fitness_lds_bytes(c->cfg.dtype, p.M_pad, p.tile_p));
+    states[i] = c->state;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<BatchFitRun> sorted(b->n);
+  int64_t item = 0;
+  for (int k = 0; k < b->n; ++k) {
+    sorted[k] = fit[order[k]];
+    sorted[k].item0 = item;
+    item += (int64_t)sorted[k].n_pt * sorted[k].n_ranges;
+  }
+  b->n_items = item;
+  int block = 0;
+  for (int i = 0; i < b->n; ++i) {
+    br[i].a = evolve_args(b->ctx[i], b->ctx[i]->fit);
+    br[i].st = b->ctx[i]->state;
+    br[i].t_done = b->t_done + (size_t)i * b->G;
+    br[i].block0 = block;
+    br[i].n_blocks = breed_blocks(br[i].a);
+    br[i].gen0 = 0;
+    block += br[i].n_blocks;
+  }
+  b->breed_grid = block;
+  const int slots = fitness_batch_slots(b->dtype, b->fit_lds);
+  if (slots <= 0) return fail(GAME_E_DEVICE, "batched fitness kernel cannot be resident");
+  b->fit_grid = (int)std::min<int64_t>(slots, std::max<int64_t>(b->n_items, 1));
+  GAME_TRY(bdev(b, hipMemcpyAsync(b->dfit, sorted.data(), sizeof(BatchFitRun) * b->n, hipMemcpyHostToDevice, b->stream), "batch tables"));
+  GAME_TRY(bdev(b, hipMemcpyAsync(b->dbreed, br.data(), sizeof(BatchBreedRun) * b->n, hipMemcpyHostToDevice, b->stream), "batch tables"));
+  GAME_TRY(bdev(b, hipMemcpyAsync(b->dstates, states.data(), sizeof(DevState*) * b->n, hipMemcpyHostToDevice, b->stream), "batch tables"));
+  GAME_TRY(bdev(b, hipStreamSynchronize(b->stream), "synchronize"));
+  return GAME_OK;
+}
+
+game_status batch_fitness(game_batch* b, hipStream_t s, bool stamps) {
+  return bdev(b,
+              launch_fitness_batch(b->dtype, b->dfit, b->n, b->n_items, b->fit_grid, b->fit_lds, b->q,
+                                   stamps ? b->t_start : nullptr, b->G, s),
+              "batched fitness");
+}
+
+// Apply per-context tile widths and row ranges (each must fit), rebuild tables.
+game_status batch_apply(game_batch* b, const std::vector<int>& tp, const std::vector<int>& rg) {
+  for (int i = 0; i < b->n; ++i) {
+    Plan& p = b->ctx[i]->plan;
+    if (!fitness_lds_fits(b->dtype, p.M_pad, tp[i])) return fail(GAME_E_INVALID, "tile does not fit");
+    p.tile_p = tp[i];
+    p.row_groups = rg[i];
+  }
+  b->tile_p = tp;
+  b->row_groups = rg;
+  return batch_tables(b);
+}
+
+// Mean duration (ms) of one batched fitness launch over the current populations.
+game_status batch_time(game_batch* b, int reps, float* ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  GAME_TRY(bdev(b, hipEventCreate(&e0), "event"));
+  game_status st = bdev(b, hipEventCreate(&e1), "event");
+  if (st == GAME_OK) st = batch_fitness(b, b->stream, false);  // warm
+  if (st == GAME_OK) st = bdev(b, hipEventRecord(e0, b->stream), "event");
+  for (int r = 0; r < reps && st == GAME_OK; ++r) st = batch_fitness(b, b->stream, false);
+  if (st == GAME_OK) st = bdev(b, hipEventRecord(e1, b->stream), "event");
+  if (st == GAME_OK) st = bdev(b, hipEventSynchronize(e1), "event");
+  float t = 0.0f;
+  if (st == GAME_OK) st = bdev(b, hipEventElapsedTime(&t, e0, e1), "event");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st == GAME_OK) *ms = t / (float)reps;
+  return st;
+}
+
+// The tuner: every context takes the widest tile that fits the LDS budget of
+// the candidate, and as many row ranges as give items of about W row-tile x
+// chromosome x gene units; the (budget, W) pair with the fastest batched
+// fitness launch wins.  Contexts whose configuration fixes tile_p and
+// row_groups keep them.
+game_status batch_tune(game_batch* b) {
+  const size_t budgets[] = {98304, 49152};
+  const double works[] = {1.0 * (1 << 20), 2.0 * (1 << 20), 4.0 * (1 << 20), 8.0 * (1 << 20),
+                          16.0 * (1 << 20)};
+  float best = 0.0f;
+  std::vector<int> best_tp, best_rg;
+  for (size_t budget : budgets) {
+    for (double W : works) {
+      std::vector<int> tp(b->n), rg(b->n);
+      for (int i = 0; i < b->n; ++i) {
+        const game_config& cfg = b->ctx[i]->cfg;
+        const Plan& p = b->ctx[i]->plan;
+        int t = cfg.tile_p;
+        if (t == 0) {
+          // widest tile within the budget that a population of P fills
+          t = 32;
+          for (int cand : {128, 64})
+            if (cand <= round_up(p.P, 32) && fitness_lds_bytes(b->dtype, p.M_pad, cand) <= budget) {
+              t = cand;
+              break;
+            }
+          if (!fitness_lds_fits(b->dtype, p.M_pad, t)) t = p.tile_p;
+        }
+        int r = cfg.row_groups;
+        if (r == 0) {
+          const double per_rt = (double)t * p.M_pad;
+          const int64_t rts = std::max<int64_t>(1, (int64_t)std::llround(W / per_rt));
+          r = (int)std::min<int64_t>(std::max<int64_t>((p.n_rt + rts - 1) / rts, 1), p.n_rg_max);
+        }
+        tp[i] = t;
+        rg[i] = r;
+      }
+      GAME_TRY(batch_apply(b, tp, rg));
+      float ms = 0.0f;
+      GAME_TRY(batch_time(b, 3, &ms));
+      if (best_tp.empty() || ms < best) {
+        best = ms;
+        best_tp = tp;
+        best_rg = rg;
+      }
+    }
+  }
+  b->tune_ms = best;
+  return batch_apply(b, best_tp, best_rg);
+}
+
+game_status batch_graph(game_batch* b) {
+  if (b->exec) return GAME_OK;
+  if (!b->cap) GAME_TRY(bdev(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "stream create"));
+  GAME_TRY(bdev(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture"));
+  game_status st = GAME_OK;
+  for (int i = 0; i < kBatchChunk && st == GAME_OK; ++i) {
+    st = batch_fitness(b, b->cap, true);
+    if (st == GAME_OK)
+      st = bdev(b, launch_breed_batch(b->dtype, b->dbreed, b->n, b->breed_grid, b->q, b->G, b->cap), "batched breed");
+  }
+  if (st == GAME_OK) st = bdev(b, launch_batch_status(b->dstates, b->dbreed, b->n, b->q, 0, b->cap), "status");
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->cap, &g);
+  if (st != GAME_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  GAME_TRY(bdev(b, e, "end capture"));
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return bdev(b, ei, "graph instantiate");
+  }
+  b->graph = g;
+  b->exec = x;
+  return GAME_OK;
+}
+
+game_status check_batch(game_batch* b) {
+  if (!b) return fail(GAME_E_INVALID, "batch is NULL");
+  if (b->poisoned) return fail(GAME_E_STATE, "batch poisoned by an earlier device error");
+  for (game_ctx* c : b->ctx)
+    if (c->poisoned) return fail(GAME_E_STATE, "batch poisoned by an earlier device error");
+  return GAME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+game_status game_batch_workspace_size(const game_config* cfgs, int32_t n_runs, size_t* bytes) {
+  if (!bytes) return fail(GAME_E_INVALID, "bytes is NULL");
+  BatchLayout L;
+  int dtype = 0;
+  GAME_TRY(batch_layout(cfgs, n_runs, &L, &dtype));
+  *bytes = L.total;
+  return GAME_OK;
+}
+
+void game_batch_destroy(game_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (game_ctx* c : b->ctx) game_destroy(c);
+  delete b;
+}
+
+game_status game_batch_init(const game_config* cfgs, int32_t n_runs, const void* const* X_devs,
+                            const void* const* t_devs, void* ws, size_t ws_bytes, void* stream,
+                            game_batch** out) {
+  if (!out) return fail(GAME_E_INVALID, "out is NULL");
+  *out = nullptr;
+  BatchLayout L;
+  int dtype = 0;
+  GAME_TRY(batch_layout(cfgs, n_runs, &L, &dtype));
+  if (!X_devs || !t_devs || !ws) return fail(GAME_E_INVALID, "X_devs, t_devs and workspace are required");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(GAME_E_INVALID, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total) return fail(GAME_E_OOM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, L.total);
+  for (int i = 0; i < n_runs; ++i)
+    if (!X_devs[i] || !t_devs[i]) return fail(GAME_E_INVALID, "run %d: X and t must be device pointers", i);
+  game_batch* b = new (std::nothrow) game_batch();
+  if (!b) return fail(GAME_E_OOM, "host allocation of the batch failed");
+  b->n = n_runs;
+  b->dtype = dtype;
+  b->stream = (hipStream_t)stream;
+  b->G = L.G;
+  b->ws_off = L.ws_off;
+  unsigned char* base = static_cast<unsigned char*>(ws);
+  for (int i = 0; i < n_runs; ++i) {
+    game_ctx* c = nullptr;
+    const size_t next = i + 1 < n_runs ? L.ws_off[i + 1] : L.tab_off;
+    const game_status s = game_init(&cfgs[i], X_devs[i], t_devs[i], base + L.ws_off[i],
+                                    next - L.ws_off[i], stream, &c);
+    if (s != GAME_OK) {
+      game_batch_destroy(b);
+      return s;
+    }
+    b->ctx.push_back(c);
+  }
+  b->tab = base + L.tab_off;
+  b->dfit = reinterpret_cast<BatchFitRun*>(base + L.fit_off);
+  b->dbreed = reinterpret_cast<BatchBreedRun*>(base + L.breed_off);
+  b->dstates = reinterpret_cast<DevState**>(base + L.states_off);
+  b->q = reinterpret_cast<BatchQueue*>(base + L.q_off);
+  b->t_start = reinterpret_cast<uint64_t*>(base + L.ts_off);
+  b->t_done = reinterpret_cast<uint64_t*>(base + L.td_off);
+  game_status s = bdev(b, hipMemsetAsync(b->q, 0, sizeof(BatchQueue), b->stream), "batch init");
+  if (s == GAME_OK) {
+    bool fixed = true;
+    for (int i = 0; i < n_runs; ++i) fixed = fixed && cfgs[i].tile_p > 0 && cfgs[i].row_groups > 0;
+    if (fixed) {
+      std::vector<int> tp(n_runs), rg(n_runs);
+      for (int i = 0; i < n_runs; ++i) {
+        tp[i] = cfgs[i].tile_p;
+        rg[i] = cfgs[i].row_groups;
+      }
+      s = batch_apply(b, tp, rg);
+    } else {
+      s = batch_tune(b);
+    }
+  }
+  if (s != GAME_OK) {
+    game_batch_destroy(b);
+    return s;
+  }
+  *out = b;
+  return GAME_OK;
+}
+
+game_status game_batch_tiles(game_batch* b, int32_t* tile_p, int32_t* row_groups) {
+  GAME_TRY(check_batch(b));
+  for (int i = 0; i < b->n; ++i) {
+    if (tile_p) tile_p[i] = b->tile_p[i];
+    if (row_groups) row_groups[i] = b->row_groups[i];
+  }
+  return GAME_OK;
+}
+
+game_status game_batch_context(game_batch* b, int32_t i, game_ctx** out) {
+  GAME_TRY(check_batch(b));
+  if (!out || i < 0 || i >= b->n) return fail(GAME_E_INVALID, "run index out of range");
+  *out = b->ctx[i];
+  return GAME_OK;
+}
+
+game_status game_batch_time_fitness(game_batch* b, int32_t reps, float* ms) {
+  GAME_TRY(check_batch(b));
+  if (!ms || reps < 1) return fail(GAME_E_INVALID, "reps must be >= 1 and ms non-NULL");
+  return batch_time(b, reps, ms);
+}
+
+game_status game_batch_run(game_batch* b, game_result* results, double* latency_us) {
+  GAME_TRY(check_batch(b));
+  if (!results) return fail(GAME_E_INVALID, "results is NULL");
+  GAME_TRY(batch_graph(b));
+  std::vector<game_state> s0(b->n);
+  for (int i = 0; i < b->n; ++i) {
+    game_ctx* c = b->ctx[i];
+    if (!c->tile_fresh) GAME_TRY(enqueue_pack_population(c, b->stream));
+    GAME_TRY(game_get_state(c, &s0[i], nullptr));
+    GAME_TRY(dev(c, launch_run_arm(c->state, c->cfg.max_generations, c->cfg.mse_threshold, b->stream), "arm"));
+  }
+  GAME_TRY(bdev(b, launch_batch_status(b->dstates, b->dbreed, b->n, b->q, 1, b->stream), "arm"));
+  BatchQueue hq{};
+  for (int launched = 0; launched < b->G + kBatchChunk; launched += kBatchChunk) {
+    GAME_TRY(bdev(b, hipGraphLaunch(b->exec, b->stream), "graph launch"));
+    GAME_TRY(bdev(b, hipMemcpyAsync(&hq, b->q, sizeof(hq), hipMemcpyDeviceToHost, b->stream), "status copy"));
+    GAME_TRY(bdev(b, hipStreamSynchronize(b->stream), "synchronize"));
+    if (hq.active == 0) break;
+  }
+  if (hq.active != 0) return fail(GAME_E_STATE, "batch did not reach its stop conditions");
+  std::vector<uint64_t> ts, td;
+  if (latency_us) {
+    ts.resize(b->G);
+    td.resize((size_t)b->G * b->n);
+    GAME_TRY(bdev(b, hipMemcpyAsync(ts.data(), b->t_start, ts.size() * 8, hipMemcpyDeviceToHost, b->stream), "stamps"));
+    GAME_TRY(bdev(b, hipMemcpyAsync(td.data(), b->t_done, td.size() * 8, hipMemcpyDeviceToHost, b->stream), "stamps"));
+  }
+  int dev_id = 0, rate_khz = 0;
+  if (latency_us) {
+    GAME_TRY(bdev(b, hipGetDevice(&dev_id), "device"));
+    GAME_TRY(bdev(b, hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev_id), "clock rate"));
+  }
+  for (int i = 0; i < b->n; ++i) {
+    game_ctx* c = b->ctx[i];
+    GAME_TRY(dev(c, launch_run_disarm(c->state, b->stream), "disarm"));
+    game_state s;
+    GAME_TRY(game_get_state(c, &s, results[i].best_genes));
+    results[i].best_mse = s.best_mse;
+    results[i].best_fitness = s.best_fitness;
+    results[i].best_miscls = s.best_miscls;
+    results[i].generations = s.generation - s0[i].generation + 1;
+    results[i].stop_reason = s.stop_reason;
+    c->have_eval = true;
+    c->tile_fresh = true;
+    if (latency_us) {
+      // generation g of context i: from the start of the batched fitness
+      // launch to the end of its breed (bred generations only)
+      for (int g = 0; g < b->G; ++g) {
+        double v = -1.0;
+        const uint64_t a = ts[g], e = td[(size_t)i * b->G + g];
+        if (g + 1 < results[i].generations && e > a && rate_khz > 0) v = (double)(e - a) * 1e3 / rate_khz;
+        latency_us[(size_t)i * b->G + g] = v;
+      }
+    }
+  }
+  return GAME_OK;
+}
+
+game_status game_run_batched(const game_config* cfgs, int32_t n_runs, const void* const* X_devs,
+                             const void* const* t_devs, void* ws, size_t ws_bytes, void* stream,
+                             game_result* results, double* latency_us) {
+  game_batch* b = nullptr;
+  GAME_TRY(game_batch_init(cfgs, n_runs, X_devs, t_devs, ws, ws_bytes, stream, &b));
+  const game_status s = game_batch_run(b, results, latency_us);
+  game_batch_destroy(b);
+  return s;
+}
 
 }  // extern "C"

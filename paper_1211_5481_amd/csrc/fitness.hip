@@ -132,13 +132,25 @@ __device__ __forceinline__ bool in_class(double z, int mask) { return __builtin_
 // segments in order.  For a population evaluation the last tile to finish
 // ranks the population and tracks the best chromosome.  Counters return to
 // zero, so the kernel can be replayed from a graph.
+// One copy of the tail's LDS per kernel, whatever tile widths it serves.
+struct TailLds {
+  double red[256];
+  uint64_t redm[256];
+  int flag;
+};
+__device__ __forceinline__ TailLds& tail_lds() {
+  __shared__ TailLds s;
+  return s;
+}
+
 template <int TP>
 __device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, int part_ld,
                              const double* psse, const uint32_t* pmiss) {
   constexpr int S = 256 / TP;
-  __shared__ int s_flag;
-  __shared__ double s_red[256];
-  __shared__ uint64_t s_redm[256];
+  TailLds& sh = tail_lds();
+  int& s_flag = sh.flag;
+  double* s_red = sh.red;
+  uint64_t* s_redm = sh.redm;
   // the partial row was stored at agent scope; order it before the arrival
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
@@ -602,6 +614,70 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   fitness_tail<16 * WN>(tail, pt, n_pt, n_ranges, part_ld, part_sse, part_miss);
 }
 
+// Batched form: one persistent launch evaluates the populations of many
+// contexts.  Workgroups take (context, chromosome tile, row range) items from
+// a device queue in order; an item is the single-context kernel's work item
+// and tail, so each context's sums are those its own kernel would produce
+// with the same tile width and row ranges.  The last workgroup to leave
+// resets the queue for the next launch.
+template <class Tr>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fitness_batch_kernel(
+    const BatchFitRun* __restrict__ runs, int n_runs, int64_t n_items, BatchQueue* q,
+    uint64_t* t_start, int t_cap) {
+  using T = typename Tr::T;
+  using Acc = typename Tr::Acc;
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ int64_t s_item;
+  for (;;) {
+    __syncthreads();  // the previous item's LDS is no longer read
+    if (threadIdx.x == 0) {
+      s_item = (int64_t)atomicAdd(&q->next, 1u);
+      if (s_item == 0 && t_start) {
+        const int g = q->gen - q->base;
+        if (g >= 0 && g < t_cap) t_start[g] = wall_clock64();
+      }
+    }
+    __syncthreads();
+    const int64_t item = s_item;
+    if (item >= n_items) break;
+    int lo = 0, hi = n_runs - 1;  // last run whose first item is <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (runs[mid].item0 <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchFitRun& r = runs[lo];
+    if (run_halted(r.st)) continue;
+    const int64_t local = item - r.item0;
+    const int pt = (int)(local % r.n_pt);
+    const int wr = (int)(local / r.n_pt);
+    const T* phi = static_cast<const T*>(r.phi);
+    const T* tile = static_cast<const T*>(r.tile);
+    const Acc* biasv = static_cast<const Acc*>(r.biasv);
+    const Acc* tvec = static_cast<const Acc*>(r.tvec);
+#define GAME_BATCH_ITEM(CLS, WN)                                                                   \
+  do {                                                                                             \
+    lds_item<Tr, CLS, WN>(phi, tile, biasv, tvec, r.N, r.M_pad, r.ldsw, r.n_rt, r.n_ranges, pt, wr, \
+                          r.part_ld, r.psse, r.pmiss, lds);                                        \
+    fitness_tail<16 * WN>(r.tail, pt, r.n_pt, r.n_ranges, r.part_ld, r.psse, r.pmiss);             \
+  } while (0)
+    if (r.task == GAME_CLASSIFICATION) {
+      if (r.tile_p == 128) GAME_BATCH_ITEM(true, 8);
+      else if (r.tile_p == 64) GAME_BATCH_ITEM(true, 4);
+      else GAME_BATCH_ITEM(true, 2);
+    } else {
+      if (r.tile_p == 128) GAME_BATCH_ITEM(false, 8);
+      else if (r.tile_p == 64) GAME_BATCH_ITEM(false, 4);
+      else GAME_BATCH_ITEM(false, 2);
+    }
+#undef GAME_BATCH_ITEM
+  }
+  if (threadIdx.x == 0 && atomicAdd(&q->done, 1u) == gridDim.x - 1) {
+    q->next = 0u;
+    q->done = 0u;
+  }
+}
+
 template <class Tr, int WM, int WN>
 hipError_t launch_tr(int task, const FitnessGeom& g, const Plan& p, const void* phi,
                      const void* tile, const void* biasv, const void* tvec, double* psse,
@@ -742,6 +818,15 @@ size_t fitness_lds_bytes(int dtype, int M_pad, int tp) {
   return 0;
 }
 
+int fitness_lds_stride(int dtype, int M_pad) {
+  switch (dtype) {
+    case GAME_F32: return lds_stride_words<F32Tr>(M_pad);
+    case GAME_BF16: return lds_stride_words<BF16Tr>(M_pad);
+    case GAME_F16: return lds_stride_words<F16Tr>(M_pad);
+  }
+  return 0;
+}
+
 int fitness_lds_fits(int dtype, int M_pad, int tp) {
   if (tp != 128 && tp != 64 && tp != 32) return 0;
   switch (dtype) {
@@ -750,6 +835,58 @@ int fitness_lds_fits(int dtype, int M_pad, int tp) {
     case GAME_F16: return lds_fits<F16Tr>(M_pad, tp);
   }
   return 0;
+}
+
+namespace {
+template <class Tr>
+hipError_t batch_prepare() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fitness_batch_kernel<Tr>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+template <class Tr>
+int batch_slots(size_t lds) {
+  if (batch_prepare<Tr>() != hipSuccess) return 0;
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &blocks, reinterpret_cast<const void*>(fitness_batch_kernel<Tr>), 256, lds) != hipSuccess)
+    return 0;
+  return blocks * device_cus();
+}
+
+template <class Tr>
+hipError_t batch_launch(const BatchFitRun* runs, int n_runs, int64_t n_items, int grid, size_t lds,
+                        BatchQueue* q, uint64_t* t_start, int t_cap, hipStream_t s) {
+  const hipError_t e = batch_prepare<Tr>();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fitness_batch_kernel<Tr>, dim3((unsigned)grid), dim3(256), lds, s, runs, n_runs,
+                     n_items, q, t_start, t_cap);
+  return hipGetLastError();
+}
+}  // namespace
+
+int fitness_batch_slots(int dtype, size_t lds) {
+  switch (dtype) {
+    case GAME_F32: return batch_slots<F32Tr>(lds);
+    case GAME_BF16: return batch_slots<BF16Tr>(lds);
+    case GAME_F16: return batch_slots<F16Tr>(lds);
+  }
+  return 0;
+}
+
+hipError_t launch_fitness_batch(int dtype, const BatchFitRun* runs, int n_runs, int64_t n_items,
+                                int grid, size_t lds, BatchQueue* q, uint64_t* t_start, int t_cap,
+                                hipStream_t s) {
+  switch (dtype) {
+    case GAME_F32: return batch_launch<F32Tr>(runs, n_runs, n_items, grid, lds, q, t_start, t_cap, s);
+    case GAME_BF16: return batch_launch<BF16Tr>(runs, n_runs, n_items, grid, lds, q, t_start, t_cap, s);
+    case GAME_F16: return batch_launch<F16Tr>(runs, n_runs, n_items, grid, lds, q, t_start, t_cap, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 int fitness_persistent_slots(const Plan& p, int task, int dtype) {

@@ -116,10 +116,15 @@ __device__ __forceinline__ void put_gene(const BreedArgs& a, float* dst, int row
     static_cast<B*>(a.biasv)[row] = (B)v;
 }
 
+// Workgroup `blk` of the n_blocks a context's breed takes (4 waves each: the
+// first E waves copy elites, then one wave per child pair).  The last of them
+// to finish advances the context's generation and, when t_done is given,
+// stamps the time in slot generation - t_gen0.
 template <typename O, typename B>
-__global__ __launch_bounds__(256) void breed_kernel(BreedArgs a, DevState* st) {
+__device__ __forceinline__ void breed_block(const BreedArgs& a, DevState* st, int blk, int n_blocks,
+                                            uint64_t* t_done, int t_cap, int t_gen0) {
   if (run_halted(st)) return;
-  const int wave = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+  const int wave = (int)(((unsigned)blk * 256u + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   const uint32_t g = (uint32_t)st->generation;
   const float* src = (g & 1u) ? a.pop1 : a.pop0;
@@ -152,11 +157,65 @@ __global__ __launch_bounds__(256) void breed_kernel(BreedArgs a, DevState* st) {
   if (!a.counter) return;
   __shared__ int s_last;
   __syncthreads();
-  if (threadIdx.x == 0) s_last = atomicAdd(a.counter, 1u) == gridDim.x - 1;
+  if (threadIdx.x == 0) s_last = atomicAdd(a.counter, 1u) == (uint32_t)(n_blocks - 1);
   __syncthreads();
   if (s_last && threadIdx.x == 0) {
+    if (t_done) {
+      const int rel = (int)g - t_gen0;
+      if (rel >= 0 && rel < t_cap) t_done[rel] = (uint64_t)wall_clock64();
+    }
     st->generation += 1;
     *a.counter = 0u;
+  }
+}
+
+template <typename O, typename B>
+__global__ __launch_bounds__(256) void breed_kernel(BreedArgs a, DevState* st) {
+  breed_block<O, B>(a, st, (int)blockIdx.x, (int)gridDim.x, nullptr, 0, 0);
+}
+
+// Batched form: workgroup b serves the context whose range of workgroups
+// holds b; the last workgroup of the launch advances the batch generation.
+template <typename O, typename B>
+__global__ __launch_bounds__(256) void breed_batch_kernel(const BatchBreedRun* __restrict__ runs,
+                                                          int n_runs, BatchQueue* q, int t_cap) {
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = n_runs - 1;  // last context whose first workgroup is <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (runs[mid].block0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchBreedRun& r = runs[lo];
+  breed_block<O, B>(r.a, r.st, b - r.block0, r.n_blocks, r.t_done, t_cap, r.gen0);
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = atomicAdd(&q->bred, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (s_last && threadIdx.x == 0) {
+    q->gen += 1;
+    q->bred = 0u;
+  }
+}
+
+// After a chunk of batched generations: count the contexts still running;
+// with arm set, also note the starting generations for the timestamps.
+__global__ void batch_status_kernel(DevState* const* __restrict__ states, BatchBreedRun* runs,
+                                    int n_runs, BatchQueue* q, int arm) {
+  __shared__ int s_active[256];
+  int act = 0;
+  for (int i = threadIdx.x; i < n_runs; i += 256) {
+    const DevState* st = states[i];
+    act += run_halted(st) ? 0 : 1;
+    if (arm) runs[i].gen0 = st->generation;
+  }
+  s_active[threadIdx.x] = act;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int i = 0; i < 256; ++i) tot += s_active[i];
+    q->active = tot;
+    if (arm) q->base = q->gen;
   }
 }
 
@@ -241,8 +300,7 @@ hipError_t launch_rank(const double* fit, int P, int n_top, int* top_idx, const 
 }
 
 hipError_t launch_breed(int dtype, const BreedArgs& a, DevState* st, hipStream_t s) {
-  const int waves = a.E + (a.n_children + 1) / 2;
-  const dim3 grid((unsigned)((waves + 3) / 4 > 0 ? (waves + 3) / 4 : 1)), block(256);
+  const dim3 grid((unsigned)breed_blocks(a)), block(256);
   switch (dtype) {
     case GAME_F64:
       hipLaunchKernelGGL((breed_kernel<double, double>), grid, block, 0, s, a, st);
@@ -259,6 +317,36 @@ hipError_t launch_breed(int dtype, const BreedArgs& a, DevState* st, hipStream_t
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+int breed_blocks(const BreedArgs& a) {
+  const int waves = a.E + (a.n_children + 1) / 2;
+  return (waves + 3) / 4 > 0 ? (waves + 3) / 4 : 1;
+}
+
+hipError_t launch_breed_batch(int dtype, const BatchBreedRun* runs, int n_runs, int n_blocks,
+                              BatchQueue* q, int t_cap, hipStream_t s) {
+  const dim3 grid((unsigned)n_blocks), block(256);
+  switch (dtype) {
+    case GAME_F32:
+      hipLaunchKernelGGL((breed_batch_kernel<float, float>), grid, block, 0, s, runs, n_runs, q, t_cap);
+      break;
+    case GAME_BF16:
+      hipLaunchKernelGGL((breed_batch_kernel<uint16_t, float>), grid, block, 0, s, runs, n_runs, q, t_cap);
+      break;
+    case GAME_F16:
+      hipLaunchKernelGGL((breed_batch_kernel<_Float16, float>), grid, block, 0, s, runs, n_runs, q, t_cap);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_status(DevState* const* states, BatchBreedRun* runs, int n_runs, BatchQueue* q,
+                               int arm, hipStream_t s) {
+  hipLaunchKernelGGL(batch_status_kernel, dim3(1), dim3(256), 0, s, states, runs, n_runs, q, arm);
   return hipGetLastError();
 }
 

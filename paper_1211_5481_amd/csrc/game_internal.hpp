@@ -127,7 +127,7 @@ struct Plan {
   size_t off_O, off_keys, off_sel, off_aud, off_surv, off_evg, off_emse, off_emis, off_efit;
   size_t off_snap, off_yhat, off_rho, off_loss, off_prm, off_grd, off_am, off_av, off_step;
   size_t off_a1, off_h1, off_a2, off_h2, off_y, off_dy, off_da2, off_da1, off_Xb, off_tb;
-  size_t off_buf, off_bufy, off_sst, off_log;
+  size_t off_buf, off_bufy, off_sst, off_log, off_part;
   size_t total;
 };
 constexpr int kLogCap = 4096;  // generations of surrogate statistics kept
@@ -160,6 +160,7 @@ int fitness_persistent_slots(const Plan& p, int task, int dtype);
 // LDS-staged kernel: does a tile of tp chromosomes fit, and its dynamic LDS
 int fitness_lds_fits(int dtype, int M_pad, int tp);
 size_t fitness_lds_bytes(int dtype, int M_pad, int tp);
+int fitness_lds_stride(int dtype, int M_pad);  // LDS words per staged gene row
 FitnessGeom fitness_geometry(const Plan& p, int task, int dtype, int P_eval);
 
 hipError_t launch_fitness(const Plan& p, int task, int dtype, const FitnessGeom& g, const void* phi,
@@ -246,19 +247,62 @@ struct MlpLayout {  // offsets into the flat parameter array
 };
 struct MlpScratch {  // activations and gradients of one batch (rows x width)
   float *a1, *h1, *a2, *h2, *y, *dy, *da2, *da1;
+  float* part;         // split-K partial products
+  int64_t part_cap;    // floats in part
 };
+constexpr int64_t kMlpPartFloats = int64_t(1) << 20;
 MlpLayout mlp_layout(int L, int H1, int H2);
 hipError_t mlp_init(const MlpDims& d, float* params, float* m, float* v, uint64_t seed,
                     hipStream_t s);
 // halt: kernels return at once once a run has stopped (may be null)
 hipError_t mlp_forward(const MlpDims& d, const float* params, const float* X, int B, float* a1,
-                       float* h1, float* a2, float* h2, float* y, const DevState* halt,
-                       hipStream_t s);
+                       float* h1, float* a2, float* h2, float* y, float* part, int64_t part_cap,
+                       const DevState* halt, hipStream_t s);
 hipError_t mlp_grads(const MlpDims& d, const float* params, const float* X, const float* target,
                      int B, const MlpScratch& w, float* grads, float* loss, const DevState* halt,
                      hipStream_t s);
 hipError_t mlp_adam(const MlpDims& d, float* params, const float* grads, float* m, float* v,
                     int32_t* step, float lr, const DevState* halt, hipStream_t s);
+
+// ------------------------------------------------------ batched form
+// One context's share of a batched fitness launch (device table entry).
+struct BatchFitRun {
+  const void* phi;
+  const void* tile;
+  const void* biasv;  // null without the bias gene
+  const void* tvec;
+  double* psse;
+  uint32_t* pmiss;
+  const DevState* st;
+  FitTail tail;
+  int64_t N, n_rt;
+  int64_t item0;      // queue position of this context's first item
+  int M_pad, ldsw, n_pt, n_ranges, part_ld, task, tile_p, pad;
+};
+// One context's share of a batched breed launch.
+struct BatchBreedRun {
+  BreedArgs a;
+  DevState* st;
+  uint64_t* t_done;   // per generation: when this context's breed finished
+  int block0, n_blocks;
+  int gen0, pad;      // the context's generation when the batch run started
+};
+struct BatchQueue {   // device side of a batch
+  uint32_t next, done;  // fitness item queue, workgroups finished (zero between launches)
+  uint32_t bred, pad;   // breed workgroups finished (zero between launches)
+  int32_t gen, base;    // batched generations launched; value at the start of the run
+  int32_t active, pad2; // contexts not yet stopped (written after each chunk)
+};
+int fitness_batch_slots(int dtype, size_t lds);
+hipError_t launch_fitness_batch(int dtype, const BatchFitRun* runs, int n_runs, int64_t n_items,
+                                int grid, size_t lds, BatchQueue* q, uint64_t* t_start, int t_cap,
+                                hipStream_t s);
+hipError_t launch_breed_batch(int dtype, const BatchBreedRun* runs, int n_runs, int n_blocks,
+                              BatchQueue* q, int t_cap, hipStream_t s);
+hipError_t launch_batch_status(DevState* const* states, BatchBreedRun* runs, int n_runs,
+                               BatchQueue* q, int arm, hipStream_t s);
+// a context's workgroups in a breed launch
+int breed_blocks(const BreedArgs& a);
 
 hipError_t launch_state_init(DevState* st, uint32_t* counters, int n_counters, hipStream_t s);
 hipError_t launch_run_arm(DevState* st, int max_generations, double threshold, hipStream_t s);

@@ -316,8 +316,98 @@ class Game:
 
     def close(self):
         if getattr(self, "_ctx", None):
-            L.lib().game_destroy(self._ctx)
+            if getattr(self, "_owned", True):
+                L.lib().game_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent GA runs advanced together (game_batch_init ... game_batch_destroy).
+
+    runs: list of (Config, X, t) with device tensors as for Game."""
+
+    def __init__(self, runs, stream=None):
+        torch = _torch()
+        if not runs:
+            raise ValueError("at least one run is required")
+        self.cfgs = [r[0] for r in runs]
+        self._X = [r[1].contiguous() for r in runs]
+        self._t = [r[2].contiguous() for r in runs]
+        for cfg, X, t in zip(self.cfgs, self._X, self._t):
+            if X.shape != (cfg.n_patterns, cfg.n_features) or t.shape != (cfg.n_patterns,):
+                raise ValueError("X must be N x F and t must have N entries")
+            if X.dtype != cfg.io_dtype or t.dtype != cfg.io_dtype or not X.is_cuda or not t.is_cuda:
+                raise ValueError(f"X and t must be {cfg.io_dtype} CUDA tensors")
+        n = len(runs)
+        self.n = n
+        carr = (L.GameConfig * n)(*[c.to_c() for c in self.cfgs])
+        self._carr = carr
+        need = C.c_size_t()
+        L.check(L.lib().game_batch_workspace_size(carr, n, C.byref(need)), "game_batch_workspace_size")
+        self.device = self._X[0].device
+        self.workspace = torch.empty(need.value + 256, dtype=torch.uint8, device=self.device)
+        ws = (self.workspace.data_ptr() + 255) & ~255
+        xs = (C.c_void_p * n)(*[x.data_ptr() for x in self._X])
+        ts = (C.c_void_p * n)(*[t.data_ptr() for t in self._t])
+        b = C.c_void_p()
+        L.check(L.lib().game_batch_init(carr, n, xs, ts, ws, need.value, _stream_handle(stream),
+                                        C.byref(b)), "game_batch_init")
+        self._b = b
+
+    def tiles(self):
+        """(tile_p, row_groups) the batch uses, one entry per run."""
+        tp = (C.c_int32 * self.n)()
+        rg = (C.c_int32 * self.n)()
+        L.check(L.lib().game_batch_tiles(self._b, tp, rg), "game_batch_tiles")
+        return list(tp), list(rg)
+
+    def context(self, i: int) -> Game:
+        """Run i as a Game view (owned by the batch: closing it releases nothing)."""
+        ctx = C.c_void_p()
+        L.check(L.lib().game_batch_context(self._b, int(i), C.byref(ctx)), "game_batch_context")
+        g = Game.__new__(Game)
+        g.cfg = self.cfgs[i]
+        g.dims = query(self.cfgs[i])
+        g.device = self.device
+        g._stream = None
+        g._ctx = ctx
+        g._owned = False
+        return g
+
+    def time_fitness(self, reps: int = 10) -> float:
+        ms = C.c_float()
+        L.check(L.lib().game_batch_time_fitness(self._b, int(reps), C.byref(ms)),
+                "game_batch_time_fitness")
+        return ms.value
+
+    def run(self, latency: bool = False):
+        """Per-run result dicts (as Game.run) and, with latency, an n x G array (us, -1 = none)."""
+        n = self.n
+        res = (L.GameResult * n)()
+        genes = [(C.c_float * query(c).L)() for c in self.cfgs]
+        for r, g in zip(res, genes):
+            r.best_genes = C.cast(g, C.POINTER(C.c_float))
+        G = max(c.max_generations for c in self.cfgs)
+        lat = np.full(n * G, -1.0) if latency else None
+        L.check(L.lib().game_batch_run(self._b, res,
+                                       lat.ctypes.data_as(C.c_void_p) if latency else None),
+                "game_batch_run")
+        out = [dict(best_mse=r.best_mse, best_fitness=r.best_fitness, best_miscls=r.best_miscls,
+                    generations=r.generations, stop_reason=L.STOP.get(r.stop_reason),
+                    best_genes=np.frombuffer(g, dtype=np.float32).copy())
+               for r, g in zip(res, genes)]
+        return (out, lat.reshape(n, G)) if latency else out
+
+    def close(self):
+        if getattr(self, "_b", None):
+            L.lib().game_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

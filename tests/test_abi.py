@@ -132,3 +132,35 @@ def test_init_rejects_bad_arguments_without_launching():
     assert L.lib().game_eval_fitness(None, None, 8, None, None, None) == L.GAME_E_INVALID
     assert L.lib().game_step(None, None) == L.GAME_E_INVALID
     assert L.lib().game_status_str(L.GAME_E_OOM) == b"GAME_E_OOM"
+
+
+def _batch_size(cfgs):
+    arr = (L.GameConfig * len(cfgs))(*[c.to_c() for c in cfgs])
+    need = C.c_size_t()
+    return L.lib().game_batch_workspace_size(arr, len(cfgs), C.byref(need)), need.value
+
+
+def test_batch_validation_without_launching():
+    a = Config(n_patterns=1000, n_features=4, degree=3, dtype="f32", pop_size=64)
+    b = Config(n_patterns=5000, n_features=6, degree=4, basis="trig", task="classification",
+               dtype="f32", pop_size=256)
+    st, need = _batch_size([a, b])
+    assert st == L.GAME_OK
+    sa, na = _query_ws(a)
+    sb, nb = _query_ws(b)
+    assert need > na + nb
+    assert _batch_size([a, Config(**{**b.__dict__, "dtype": "bf16"})])[0] == L.GAME_E_INVALID
+    assert _batch_size([Config(**{**a.__dict__, "dtype": "f64"})])[0] == L.GAME_E_UNSUPPORTED
+    assert _batch_size([Config(**{**a.__dict__, "n_offspring": 128})])[0] == L.GAME_E_UNSUPPORTED
+    assert _batch_size([Config(**{**a.__dict__, "rescore_top": 1})])[0] == L.GAME_E_UNSUPPORTED
+    assert _batch_size([])[0] == L.GAME_E_INVALID
+    # a batch needs device memory: init refuses a NULL workspace before any launch
+    arr = (L.GameConfig * 1)(a.to_c())
+    xs = (C.c_void_p * 1)(None)
+    out = C.c_void_p()
+    assert L.lib().game_batch_init(arr, 1, xs, xs, None, 0, None, C.byref(out)) != L.GAME_OK
+
+
+def _query_ws(cfg):
+    need = C.c_size_t()
+    return L.lib().game_workspace_size(C.byref(cfg.to_c()), C.byref(need)), need.value

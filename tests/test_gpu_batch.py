@@ -1,0 +1,133 @@
+"""Batched form: many GA runs of uneven size in one persistent launch per
+generation.  Every run must end exactly (bit for bit: best MSE, best genes,
+final population, generation count) where the same configuration run alone
+ends, given the tile width and row ranges the batch chose for it."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import announce, dev, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def bits(a, dt=np.uint32):
+    return np.ascontiguousarray(a).view(dt)
+
+
+def make_runs(specs, dtype="f32"):
+    """specs: (task, N, F, D, P, max_generations, threshold, seed)."""
+    torch = require_gpu()
+    from paper_1211_5481_amd import Config
+    runs = []
+    for task, N, F, D, P, G, thr, seed in specs:
+        if task == "classification":
+            X, t = synth.classification_dataset(N, F, seed=seed)
+            basis = "trig"
+        else:
+            X, t, _ = synth.regression_dataset(N, F, 3, 0.05, seed=seed)
+            basis = "chebyshev"
+        cfg = Config(n_patterns=N, n_features=F, degree=D, basis=basis, task=task, dtype=dtype,
+                     pop_size=P, max_generations=G, mse_threshold=thr, seed=seed + 1000)
+        runs.append((cfg, dev(X, torch.float32), dev(t, torch.float32)))
+    return runs
+
+
+SPECS = [
+    ("classification", 20011, 10, 6, 256, 9, 0.0, 1),
+    ("regression", 3001, 5, 4, 64, 6, 0.0, 2),
+    ("classification", 7777, 20, 8, 130, 11, 0.0, 3),   # M = 320: narrow tiles
+    ("regression", 40000, 8, 8, 512, 5, 0.0, 4),
+    ("regression", 1500, 12, 6, 33, 12, 0.0, 5),
+    ("classification", 12345, 6, 4, 1000, 7, 0.0, 6),
+]
+
+
+def run_alone(cfg, X, t, tp, rg):
+    from paper_1211_5481_amd import Config, Game
+    g = Game(Config(**{**cfg.__dict__, "tile_p": tp, "row_groups": rg}), X, t)
+    r = g.run()
+    pop = host(g.population)
+    st = g.state()
+    g.close()
+    return r, pop, st
+
+
+def compare_with_alone(batch, runs, results):
+    tps, rgs = batch.tiles()
+    for i, (cfg, X, t) in enumerate(runs):
+        assert tps[i] in (32, 64, 128) and rgs[i] >= 1
+        ref, pop, st = run_alone(cfg, X, t, tps[i], rgs[i])
+        got = results[i]
+        label = f"run {i} tile {tps[i]} ranges {rgs[i]}"
+        assert got["generations"] == ref["generations"], label
+        assert got["stop_reason"] == ref["stop_reason"], label
+        assert bits(np.float64(got["best_mse"]), np.uint64) == bits(np.float64(ref["best_mse"]), np.uint64), label
+        assert np.array_equal(bits(got["best_genes"]), bits(ref["best_genes"])), label
+        view = batch.context(i)
+        assert np.array_equal(bits(host(view.population)), bits(pop)), label
+        assert view.state()["generation"] == st["generation"], label
+
+
+def test_batch_equals_runs_alone():
+    from paper_1211_5481_amd import Batch
+    runs = make_runs(SPECS)
+    announce("batched f32 runs (tuned) vs the same runs alone")
+    b = Batch(runs)
+    results, lat = b.run(latency=True)
+    compare_with_alone(b, runs, results)
+    G = max(s[5] for s in SPECS)
+    assert lat.shape == (len(SPECS), G)
+    for i, s in enumerate(SPECS):
+        bred = results[i]["generations"] - 1
+        assert np.all(lat[i, :bred] > 0.0) and np.all(lat[i, bred:] == -1.0)
+    b.close()
+
+
+def test_batch_threshold_and_second_run():
+    from paper_1211_5481_amd import Batch, Config, Game
+    specs = [("regression", 5000, 6, 4, 128, 30, 0.0, 11),
+             ("classification", 9000, 8, 4, 256, 30, 0.0, 12)]
+    runs = make_runs(specs)
+    # a threshold the first run reaches early: take its best MSE after 4 generations
+    cfg0, X0, t0 = runs[0]
+    probe = Game(Config(**{**cfg0.__dict__, "max_generations": 4}), X0, t0)
+    thr = probe.run()["best_mse"] * (1.0 + 1e-5)   # summation order may differ by an ulp
+    probe.close()
+    runs[0] = (Config(**{**cfg0.__dict__, "mse_threshold": thr}), X0, t0)
+    announce("batched runs with a threshold stop, run twice")
+    b = Batch(runs)
+    first = b.run()
+    assert first[0]["stop_reason"] == "threshold" and first[0]["generations"] <= 4
+    assert first[1]["generations"] == 30
+    compare_with_alone(b, runs, first)
+    # a second batched run continues every run like a second game_run would
+    second = b.run()
+    tps, rgs = b.tiles()
+    for i, (cfg, X, t) in enumerate(runs):
+        g = Game(Config(**{**cfg.__dict__, "tile_p": tps[i], "row_groups": rgs[i]}), X, t)
+        g.run()
+        r2 = g.run()
+        assert r2["generations"] == second[i]["generations"]
+        assert np.array_equal(bits(r2["best_genes"]), bits(second[i]["best_genes"]))
+        assert np.array_equal(bits(host(g.population)), bits(host(b.context(i).population)))
+        g.close()
+    b.close()
+
+
+def test_batch_fixed_tiles_and_bf16():
+    from paper_1211_5481_amd import Batch, Config
+    specs = [("classification", 6000, 16, 8, 300, 6, 0.0, 21),
+             ("regression", 3000, 10, 6, 200, 8, 0.0, 22),
+             ("classification", 2500, 5, 4, 64, 5, 0.0, 23)]
+    runs = make_runs(specs, dtype="bf16")
+    fixed = [(32, 5), (64, 2), (128, 1)]
+    runs = [(Config(**{**c.__dict__, "tile_p": tp, "row_groups": rg}), X, t)
+            for (c, X, t), (tp, rg) in zip(runs, fixed)]
+    announce("batched bf16 runs with fixed tiles vs alone")
+    b = Batch(runs)
+    assert b.tiles() == ([f[0] for f in fixed], [f[1] for f in fixed])
+    results = b.run()
+    compare_with_alone(b, runs, results)
+    assert b.time_fitness(reps=3) > 0.0
+    b.close()
