@@ -130,3 +130,36 @@ def test_merge_survivors_keeps_elites_and_best_candidates():
     best = np.lexsort((np.arange(30), -key))[:8]
     np.testing.assert_array_equal(genes[2:], cand[best])
     np.testing.assert_array_equal(fit[2:], fit_cand[best])
+
+
+def test_gradients_and_adam_against_torch():
+    """The same network in torch float64: autograd gradients and torch.optim.Adam."""
+    import torch
+    p = tiny_params(5)
+    rng = np.random.default_rng(4)
+    X = rng.uniform(-1, 1, (9, 5))
+    y = rng.normal(0, 1, 9)
+    loss, g = mlp.loss_and_grads(p, X, y)
+    tp = {k: torch.tensor(np.asarray(v, np.float64), requires_grad=True) for k, v in p.items()}
+    Xt = torch.tensor(X)
+    h1 = torch.nn.functional.gelu(Xt @ tp["W1"].T + tp["b1"])
+    h2 = torch.nn.functional.gelu(h1 @ tp["W2"].T + tp["b2"])
+    out = h2 @ tp["w3"] + tp["b3"][0]
+    tl = ((out - torch.tensor(y)) ** 2).mean()
+    tl.backward()
+    assert abs(tl.item() - loss) <= 1e-12 * loss
+    for k in p:
+        np.testing.assert_allclose(np.asarray(g[k]), tp[k].grad.numpy(), rtol=1e-10, atol=1e-14,
+                                   err_msg=k)
+    # three Adam steps with the same gradients
+    opt = torch.optim.Adam(list(tp.values()), lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    cur = {k: np.asarray(v, np.float64) for k, v in p.items()}
+    m = {k: np.zeros_like(v) for k, v in cur.items()}
+    v = {k: np.zeros_like(val) for k, val in cur.items()}
+    for step in (1, 2, 3):
+        for k in tp:
+            tp[k].grad = torch.tensor(np.asarray(g[k], np.float64) * step)
+        opt.step()
+        cur, m, v = mlp.adam_step(cur, {k: np.asarray(g[k]) * step for k in g}, m, v, step, lr=3e-3)
+    for k in p:
+        np.testing.assert_allclose(cur[k], tp[k].detach().numpy(), rtol=1e-12, atol=1e-15, err_msg=k)
