@@ -63,10 +63,10 @@ struct game_ctx {
   uint64_t* keys = nullptr;
   int *sel = nullptr, *aud = nullptr, *surv = nullptr;
   double *emse = nullptr, *emis = nullptr, *efit = nullptr, *snap = nullptr;
-  float *prm = nullptr, *grd = nullptr, *am = nullptr, *av = nullptr;
+  float *prm = nullptr, *am = nullptr, *av = nullptr;
   int32_t* step = nullptr;
-  MlpScratch scr{};
-  float *Xb = nullptr, *tb = nullptr, *buf = nullptr, *bufy = nullptr, *log = nullptr;
+  float *WT = nullptr, *slab = nullptr;
+  float *buf = nullptr, *bufy = nullptr, *log = nullptr;
   SurState* sst = nullptr;
 };
 
@@ -136,6 +136,8 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
     p->P_eval = p->k_sel + p->audit;
     if (c->surrogate == GAME_SURROGATE_MLP) {
       if (c->surrogate_hidden < 16 || c->surrogate_hidden > 1024) return bad("surrogate_hidden must be in [16, 1024]");
+      if (!mlp_fits(MlpDims{(int)L, c->surrogate_hidden, c->surrogate_hidden}))
+        return bad("surrogate_hidden too large for this gene count");
       if (c->surrogate_batch < 1 || c->surrogate_batch > 8192) return bad("surrogate_batch must be in [1, 8192]");
       if (c->surrogate_buffer < c->surrogate_batch) return bad("surrogate_buffer must be >= surrogate_batch");
       if (c->surrogate_buffer > (1 << 24)) return bad("surrogate_buffer too large");
@@ -238,25 +240,16 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
     if (c->surrogate == GAME_SURROGATE_MLP) {
       const size_t np = (size_t)mlp_layout((int)L, p->H, p->H).total;
       p->rows_max = std::max<int>((int)n_off, std::max<int>(p->batch, (int)P));
-      const size_t rows = (size_t)p->rows_max, H = (size_t)p->H, B = (size_t)p->batch;
+      const MlpDims md{(int)L, p->H, p->H};
       p->off_prm = take(np * 4);
-      p->off_grd = take(np * 4);
       p->off_am = take(np * 4);
       p->off_av = take(np * 4);
       p->off_step = take(16);
-      p->off_a1 = take(rows * H * 4);
-      p->off_h1 = take(rows * H * 4);
-      p->off_a2 = take(rows * H * 4);
-      p->off_h2 = take(rows * H * 4);
-      p->off_y = take(rows * 4);
-      p->off_dy = take(B * 4);
-      p->off_da2 = take(B * H * 4);
-      p->off_da1 = take(B * H * 4);
-      p->off_Xb = take(B * Lz * 4);
-      p->off_tb = take(B * 4);
+      p->off_WT = take(((size_t)L * p->H + (size_t)p->H * p->H) * 4);
+      p->slab_cap = mlp_slab_floats(md, p->batch);
+      p->off_slab = take((size_t)p->slab_cap * 4);
       p->off_buf = take((size_t)p->cap * Lz * 4);
       p->off_bufy = take((size_t)p->cap * 4);
-      p->off_part = take((size_t)kMlpPartFloats * 4);
     }
   }
   p->total = off;
@@ -428,18 +421,12 @@ MlpDims mlp_dims(const game_ctx* c) { return MlpDims{c->plan.L, c->plan.H, c->pl
 game_status enqueue_train(game_ctx* c, hipStream_t s) {
   const Plan& p = c->plan;
   const MlpDims d = mlp_dims(c);
-  for (int i = 0; i < p.steps; ++i) {
+  for (int i = 0; i < p.steps; ++i)
     GAME_TRY(dev(c,
-                 sur_minibatch(c->buf, c->bufy, p.L, p.batch, p.n_recent, p.cap, c->sst, c->step,
-                               c->cfg.seed, c->Xb, c->tb, c->state, s),
-                 "minibatch"));
-    GAME_TRY(dev(c, mlp_grads(d, c->prm, c->Xb, c->tb, p.batch, c->scr, c->grd, c->loss, c->state, s),
-                 "mlp grads"));
-    GAME_TRY(dev(c,
-                 mlp_adam(d, c->prm, c->grd, c->am, c->av, c->step, (float)c->cfg.surrogate_lr,
-                          c->state, s),
-                 "mlp adam"));
-  }
+                 mlp_train_step(d, c->prm, c->WT, c->am, c->av, c->step, (float)c->cfg.surrogate_lr,
+                                c->buf, c->bufy, c->sst, c->cfg.seed, p.batch, p.n_recent, p.cap,
+                                c->slab, p.slab_cap, c->loss, c->state, s),
+                 "mlp train"));
   return GAME_OK;
 }
 
@@ -490,8 +477,7 @@ game_status enqueue_offspring_generation(game_ctx* c, hipStream_t s) {
   const int* sel = nullptr;
   if (p.sur == GAME_SURROGATE_MLP) {
     GAME_TRY(dev(c,
-                 mlp_forward(mlp_dims(c), c->prm, c->O, p.n_off, nullptr, c->scr.h1, nullptr,
-                             c->scr.h2, c->yhat, c->scr.part, c->scr.part_cap, st, s),
+                 mlp_forward(mlp_dims(c), c->prm, c->WT, c->O, p.n_off, c->yhat, st, s),
                  "mlp forward"));
     GAME_TRY(dev(c, sur_keys(0, c->yhat, nullptr, p.n_off, 0, st, c->cfg.seed, c->keys, s), "keys"));
     GAME_TRY(dev(c, sur_select(c->keys, p.n_off, k, c->sel, st, s), "prescreen"));
@@ -699,14 +685,11 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
     c->log = F(p.off_log);
     if (p.sur == GAME_SURROGATE_MLP) {
       c->prm = F(p.off_prm);
-      c->grd = F(p.off_grd);
       c->am = F(p.off_am);
       c->av = F(p.off_av);
       c->step = reinterpret_cast<int32_t*>(c->ws + p.off_step);
-      c->scr = MlpScratch{F(p.off_a1), F(p.off_h1), F(p.off_a2), F(p.off_h2), F(p.off_y),
-                          F(p.off_dy), F(p.off_da2), F(p.off_da1), F(p.off_part), kMlpPartFloats};
-      c->Xb = F(p.off_Xb);
-      c->tb = F(p.off_tb);
+      c->WT = F(p.off_WT);
+      c->slab = F(p.off_slab);
       c->buf = F(p.off_buf);
       c->bufy = F(p.off_bufy);
     }
@@ -740,7 +723,7 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
     if (r == GAME_OK) r = dev(c, hipMemsetAsync(c->rho, 0, 16, st), "surrogate state");
     if (r == GAME_OK) r = dev(c, hipMemsetAsync(c->loss, 0, 16, st), "surrogate state");
     if (r == GAME_OK && p.sur == GAME_SURROGATE_MLP) {
-      r = dev(c, mlp_init(MlpDims{p.L, p.H, p.H}, c->prm, c->am, c->av, cfg->seed, st), "mlp init");
+      r = dev(c, mlp_init(MlpDims{p.L, p.H, p.H}, c->prm, c->am, c->av, c->WT, cfg->seed, st), "mlp init");
       if (r == GAME_OK) r = dev(c, hipMemsetAsync(c->step, 0, 16, st), "mlp init");
     }
   }
@@ -924,15 +907,14 @@ game_status game_mlp_params(game_ctx* c, float* params, int32_t dir) {
   if (!params || (dir != 0 && dir != 1)) return fail(GAME_E_INVALID, "params and dir 0|1 required");
   const size_t bytes = (size_t)mlp_layout(c->plan.L, c->plan.H, c->plan.H).total * 4;
   if (dir == 0) return dev(c, hipMemcpyAsync(params, c->prm, bytes, hipMemcpyDeviceToDevice, c->stream), "params");
-  return dev(c, hipMemcpyAsync(c->prm, params, bytes, hipMemcpyDeviceToDevice, c->stream), "params");
+  GAME_TRY(dev(c, hipMemcpyAsync(c->prm, params, bytes, hipMemcpyDeviceToDevice, c->stream), "params"));
+  return dev(c, mlp_transpose(mlp_dims(c), c->prm, c->WT, c->stream), "params");
 }
 
 game_status game_mlp_forward(game_ctx* c, const float* X, int32_t n, float* y) {
   GAME_TRY(need_mlp(c));
   if (!X || !y || n < 1 || n > c->plan.rows_max) return fail(GAME_E_INVALID, "n must be in [1, %d]", c->plan.rows_max);
-  return dev(c, mlp_forward(mlp_dims(c), c->prm, X, n, nullptr, c->scr.h1, nullptr, c->scr.h2, y,
-                            c->scr.part, c->scr.part_cap, nullptr, c->stream),
-             "mlp forward");
+  return dev(c, mlp_forward(mlp_dims(c), c->prm, c->WT, X, n, y, nullptr, c->stream), "mlp forward");
 }
 
 game_status game_mlp_grads(game_ctx* c, const float* X, const float* target, int32_t n, float* grads,
@@ -940,15 +922,18 @@ game_status game_mlp_grads(game_ctx* c, const float* X, const float* target, int
   GAME_TRY(need_mlp(c));
   if (!X || !target || !grads || n < 1 || n > c->plan.batch)
     return fail(GAME_E_INVALID, "n must be in [1, %d]", c->plan.batch);
-  return dev(c, mlp_grads(mlp_dims(c), c->prm, X, target, n, c->scr, grads, loss, nullptr, c->stream),
+  return dev(c,
+             mlp_grads(mlp_dims(c), c->prm, c->WT, X, target, n, c->slab, c->plan.slab_cap, grads, loss,
+                       nullptr, c->stream),
              "mlp grads");
 }
 
 game_status game_mlp_adam(game_ctx* c, const float* grads) {
   GAME_TRY(need_mlp(c));
   if (!grads) return fail(GAME_E_INVALID, "grads is NULL");
-  return dev(c, mlp_adam(mlp_dims(c), c->prm, grads, c->am, c->av, c->step, (float)c->cfg.surrogate_lr,
-                         nullptr, c->stream),
+  return dev(c,
+             mlp_adam(mlp_dims(c), c->prm, c->WT, grads, c->am, c->av, c->step,
+                      (float)c->cfg.surrogate_lr, nullptr, c->stream),
              "mlp adam");
 }
 

@@ -388,8 +388,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // 128-pattern row tiles, 32 rows per wave); writes the range's partial sums
 // part_sse / part_miss[wr][pt * TP ..].  The single-context and the batched
 // kernels run exactly this code, so a chromosome's sums do not depend on
-// which of them evaluated it.
-template <class Tr, bool kCls, int WN>
+// which of them evaluated it.  kDepth is how many K-blocks ahead the Phi
+// fragments are loaded (1 or 2): it moves loads, not arithmetic.
+template <class Tr, bool kCls, int WN, int kDepth>
 __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
                                          const typename Tr::T* __restrict__ tile,
                                          const typename Tr::Acc* __restrict__ biasv,
@@ -465,6 +466,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
   if (rt_begin < rt_end) {
     load_t(rt_begin);
     loadA(a0, rt_begin, 0);
+    if (kDepth == 2 && KB > 1) loadA(a1, rt_begin, 1);
   }
   __syncthreads();
 
@@ -491,6 +493,49 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
     // double-buffered (LDS reads are issued right before their MFMAs)
     constexpr bool kDoubleB = sizeof(Ld) == 8;
     int kb = 0;
+    if constexpr (kDepth == 2) {
+    // Phi fragments two K-blocks ahead: a0..a3 hold blocks kb..kb+3
+    Ld a2[WM], a3[WM];
+    if constexpr (kDoubleB) loadB(b0, 0);
+    for (; kb < KB; kb += 4) {
+      if (kb + 2 < KB) loadA(a2, rt, kb + 2);
+      if constexpr (kDoubleB) {
+        if (kb + 1 < KB) loadB(b1, kb + 1);
+      } else {
+        loadB(b0, kb);
+      }
+      mma_all(a0, b0);
+      if (kb + 3 < KB) loadA(a3, rt, kb + 3);
+      if (kb + 1 < KB) {
+        if constexpr (kDoubleB) {
+          if (kb + 2 < KB) loadB(b0, kb + 2);
+          mma_all(a1, b1);
+        } else {
+          loadB(b0, kb + 1);
+          mma_all(a1, b0);
+        }
+      }
+      if (kb + 4 < KB) loadA(a0, rt, kb + 4);
+      if (kb + 2 < KB) {
+        if constexpr (kDoubleB) {
+          if (kb + 3 < KB) loadB(b1, kb + 3);
+        } else {
+          loadB(b0, kb + 2);
+        }
+        mma_all(a2, b0);
+      }
+      if (kb + 5 < KB) loadA(a1, rt, kb + 5);
+      if (kb + 3 < KB) {
+        if constexpr (kDoubleB) {
+          if (kb + 4 < KB) loadB(b0, kb + 4);
+          mma_all(a3, b1);
+        } else {
+          loadB(b0, kb + 3);
+          mma_all(a3, b0);
+        }
+      }
+    }
+    } else {
     if constexpr (kDoubleB) {
       loadB(b0, 0);
       for (; kb + 1 < KB; kb += 2) {
@@ -518,6 +563,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
         mma_all(a0, b0);
       }
     }
+    }
     (void)b1;
 
     // this tile's targets -> per-pattern coefficients, then prefetch the next tile
@@ -537,6 +583,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
     if (rt + 1 < rt_end) {
       load_t(rt + 1);
       loadA(a0, rt + 1, 0);
+      if (kDepth == 2 && KB > 1) loadA(a1, rt + 1, 1);
     }
 
     // epilogue: element r of block (i, j) is pattern nw0 + 16 i + row_in_block(r),
@@ -609,7 +656,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   if (lt >= n_items) return;
   const int pt = (int)(lt % n_pt);
   const int wr = (int)(lt / n_pt);
-  lds_item<Tr, kCls, WN>(phi, tile, biasv, tvec, N, M_pad, ldsw, n_rt, n_ranges, pt, wr, part_ld,
+  lds_item<Tr, kCls, WN, 2>(phi, tile, biasv, tvec, N, M_pad, ldsw, n_rt, n_ranges, pt, wr, part_ld,
                          part_sse, part_miss, lds);
   fitness_tail<16 * WN>(tail, pt, n_pt, n_ranges, part_ld, part_sse, part_miss);
 }
@@ -657,7 +704,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const Acc* tvec = static_cast<const Acc*>(r.tvec);
 #define GAME_BATCH_ITEM(CLS, WN)                                                                   \
   do {                                                                                             \
-    lds_item<Tr, CLS, WN>(phi, tile, biasv, tvec, r.N, r.M_pad, r.ldsw, r.n_rt, r.n_ranges, pt, wr, \
+    lds_item<Tr, CLS, WN, 1>(phi, tile, biasv, tvec, r.N, r.M_pad, r.ldsw, r.n_rt, r.n_ranges, pt, wr, \
                           r.part_ld, r.psse, r.pmiss, lds);                                        \
     fitness_tail<16 * WN>(r.tail, pt, r.n_pt, r.n_ranges, r.part_ld, r.psse, r.pmiss);             \
   } while (0)

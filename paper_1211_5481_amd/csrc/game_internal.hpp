@@ -124,10 +124,10 @@ struct Plan {
   // offspring form (n_offspring != P - E, or a prescreen)
   bool offspring;
   int k_sel, audit, P_eval, sur, H, cap, steps, batch, n_recent, rows_max;
+  int64_t slab_cap;            // floats of MLP partial-gradient slabs
   size_t off_O, off_keys, off_sel, off_aud, off_surv, off_evg, off_emse, off_emis, off_efit;
-  size_t off_snap, off_yhat, off_rho, off_loss, off_prm, off_grd, off_am, off_av, off_step;
-  size_t off_a1, off_h1, off_a2, off_h2, off_y, off_dy, off_da2, off_da1, off_Xb, off_tb;
-  size_t off_buf, off_bufy, off_sst, off_log, off_part;
+  size_t off_snap, off_yhat, off_rho, off_loss, off_prm, off_am, off_av, off_step;
+  size_t off_WT, off_slab, off_buf, off_bufy, off_sst, off_log;
   size_t total;
 };
 constexpr int kLogCap = 4096;  // generations of surrogate statistics kept
@@ -221,11 +221,6 @@ hipError_t sur_gather(const float* src, const int* idx, int n, int L, float* dst
                       hipStream_t s);
 hipError_t sur_append(const float* genes, const double* mse, int n, int L, float* buf, float* buf_y,
                       int cap, SurState* ss, const DevState* st, hipStream_t s);
-// rows i < B - n_recent come uniformly from the whole buffer, the others from
-// the latest append
-hipError_t sur_minibatch(const float* buf, const float* buf_y, int L, int B, int n_recent, int cap,
-                         const SurState* ss, const int32_t* step, uint64_t seed, float* Xb, float* tb,
-                         const DevState* st, hipStream_t s);
 hipError_t sur_snapshot(const int* elite, int E, const double* fit, const double* mse,
                         const double* miscls, double* snap, const DevState* st, hipStream_t s);
 hipError_t sur_merge(float* pop0, float* pop1, const int* elite, const double* snap, int E,
@@ -245,23 +240,29 @@ struct MlpDims {
 struct MlpLayout {  // offsets into the flat parameter array
   int64_t W1, b1, W2, b2, w3, b3, total;
 };
-struct MlpScratch {  // activations and gradients of one batch (rows x width)
-  float *a1, *h1, *a2, *h2, *y, *dy, *da2, *da1;
-  float* part;         // split-K partial products
-  int64_t part_cap;    // floats in part
-};
-constexpr int64_t kMlpPartFloats = int64_t(1) << 20;
+constexpr int64_t kMlpSlabFloats = int64_t(1) << 24;  // partial-gradient slabs, at most
 MlpLayout mlp_layout(int L, int H1, int H2);
-hipError_t mlp_init(const MlpDims& d, float* params, float* m, float* v, uint64_t seed,
+int mlp_rows_per_pass(const MlpDims& d);      // rows a workgroup takes per pass
+bool mlp_fits(const MlpDims& d);              // one row's activations fit in LDS
+int64_t mlp_slab_floats(const MlpDims& d, int rows);  // slab space a batch of rows uses
+// WT: transposed copies of W1 (L x H1) and W2 (H1 x H2), kept in step with the parameters
+hipError_t mlp_transpose(const MlpDims& d, const float* params, float* WT, hipStream_t s);
+hipError_t mlp_init(const MlpDims& d, float* params, float* m, float* v, float* WT, uint64_t seed,
                     hipStream_t s);
 // halt: kernels return at once once a run has stopped (may be null)
-hipError_t mlp_forward(const MlpDims& d, const float* params, const float* X, int B, float* a1,
-                       float* h1, float* a2, float* h2, float* y, float* part, int64_t part_cap,
-                       const DevState* halt, hipStream_t s);
-hipError_t mlp_grads(const MlpDims& d, const float* params, const float* X, const float* target,
-                     int B, const MlpScratch& w, float* grads, float* loss, const DevState* halt,
-                     hipStream_t s);
-hipError_t mlp_adam(const MlpDims& d, float* params, const float* grads, float* m, float* v,
+hipError_t mlp_forward(const MlpDims& d, const float* params, const float* WT, const float* X, int B,
+                       float* y, const DevState* halt, hipStream_t s);
+hipError_t mlp_grads(const MlpDims& d, const float* params, const float* WT, const float* X,
+                     const float* target, int B, float* slab, int64_t slab_cap, float* grads,
+                     float* loss, const DevState* halt, hipStream_t s);
+// one Adam step on a minibatch drawn from the replay ring (step[0]: steps
+// taken, step[1]: arrival counter, zero between launches)
+hipError_t mlp_train_step(const MlpDims& d, float* params, float* WT, float* m, float* v,
+                          int32_t* step, float lr, const float* buf, const float* bufy,
+                          const SurState* ss, uint64_t seed, int B, int n_recent, int cap,
+                          float* slab, int64_t slab_cap, float* loss, const DevState* halt,
+                          hipStream_t s);
+hipError_t mlp_adam(const MlpDims& d, float* params, float* WT, const float* grads, float* m, float* v,
                     int32_t* step, float lr, const DevState* halt, hipStream_t s);
 
 // ------------------------------------------------------ batched form

@@ -2,12 +2,21 @@
 // online with Adam (Kingma and Ba) on (chromosome, standardised log MSE)
 // pairs.  GELU is the exact form a * Phi(a) = a (1 + erf(a / sqrt 2)) / 2.
 //
-// All products go through one float32 GEMM kernel, C = op(A) op(B), with
-// arbitrary element strides (so the transposed products of the backward pass
-// need no copies) and a fused epilogue.  Products too small to fill the chip
-// split K into S slices whose partial tiles a second kernel adds in slice
-// order before the epilogue; every output element is a fixed-order sum, so
-// results are bit-reproducible.
+// The network is small (L = 128 inputs, H = 256 hidden at the surrogate
+// workload) and trained in many short steps, so a training step is two
+// launches instead of one per product:
+//   * rows kernel: a workgroup takes R minibatch rows at a time, draws them
+//     from the replay ring (or reads given rows), runs the forward pass and
+//     the whole backward pass for them in LDS and registers, and adds the
+//     rows' gradient contributions to its own slab of partial sums (the
+//     parameter layout plus the loss);
+//   * reduce kernel: one thread per parameter adds the slabs in workgroup
+//     order and applies Adam (or writes the gradient); the last workgroup to
+//     finish advances the step counter.
+// Every sum has a fixed order, so results are bit-reproducible.  Forward
+// products read transposed copies of W1 and W2 (kept in step with every
+// parameter update) so that lanes over output units load contiguous memory;
+// the backward product through W2 reads W2 itself for the same reason.
 //
 // Parameters are one flat float32 array: W1 (H1 x L), b1 (H1), W2 (H2 x H1),
 // b2 (H2), w3 (H2), b3 (1); gradients and Adam moments use the same layout.
@@ -22,14 +31,9 @@
 namespace game {
 namespace {
 
-constexpr int kTile = 64, kKStep = 16, kGemmThreads = 256;
-
-enum Epi : int {
-  kEpiStore = 0,      // C = acc
-  kEpiBiasGelu = 1,   // pre = acc + bias[n] -> P (if given); C = gelu(pre)
-  kEpiGeluGrad = 2,   // C = acc * gelu'(P[m, n])
-  kEpiPartial = 3,    // split K: slice z of the sum to part[z][m][n]
-};
+constexpr int kThreads = 256;
+constexpr int kMaxR = 8;            // rows per workgroup pass (registers)
+constexpr size_t kRowsLds = 65536;  // LDS budget of the rows kernel
 
 __device__ __forceinline__ float gelu(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float a) {
@@ -38,212 +42,296 @@ __device__ __forceinline__ float gelu_grad(float a) {
   return cdf + a * pdf;
 }
 
-struct GemmArgs {
-  int M, N, K;
-  const float* A;
-  int64_t as0, as1;  // A(m, k) = A[m * as0 + k * as1]
-  const float* B;
-  int64_t bs0, bs1;  // B(k, n) = B[k * bs0 + n * bs1]
-  float* C;
-  int64_t ldc;       // C(m, n) = C[m * ldc + n]
-  const float* bias; // kEpiBiasGelu
-  float* P;          // pre-activation store / read, row stride ldc
-  float* part;       // split K: S slices of M x N partial sums
-  int S;             // K slices (1: no split)
+struct RowsArgs {
+  const float* params;
+  const float* WT;  // W1^T (L x H1) then W2^T (H1 x H2)
+  int L, H1, H2, B, R, W;
+  // rows: explicit (X, target) or drawn from the replay ring
+  const float* X;
+  const float* target;
+  const float* buf;
+  const float* bufy;
+  const SurState* ss;
+  const int32_t* step;
+  uint32_t k0, k1;
+  int n_recent, cap;
+  float* y;       // forward only: scores of the B rows
+  float* slab;    // training: W slabs of (parameters + 1) floats
+  int64_t total;  // parameters
 };
 
-template <int EPI>
-__device__ __forceinline__ void epilogue(const GemmArgs& g, int m, int n, float acc) {
-  const int64_t o = (int64_t)m * g.ldc + n;
-  if constexpr (EPI == kEpiStore) {
-    g.C[o] = acc;
-  } else if constexpr (EPI == kEpiBiasGelu) {
-    const float pre = acc + g.bias[n];
-    if (g.P) g.P[o] = pre;
-    g.C[o] = gelu(pre);
-  } else {
-    g.C[o] = acc * gelu_grad(g.P[o]);
+// Block-wide sums of kMaxR per-thread values in a fixed order (each wave by
+// shuffles, then the four waves in order); the sums land in out[0..kMaxR).
+__device__ __forceinline__ void block_sum_rows(const float (&v)[kMaxR], float* red, float* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < kMaxR; ++r) {
+    float x = v[r];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    if (lane == 0) red[wave * kMaxR + r] = x;
   }
+  __syncthreads();
+  if (threadIdx.x < kMaxR) {
+    float t = 0.0f;
+    for (int w = 0; w < kThreads / 64; ++w) t += red[w * kMaxR + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
 }
 
-template <int EPI>
-__global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g, const DevState* halt) {
+template <bool kTrain>
+__global__ __launch_bounds__(kThreads) void rows_kernel(RowsArgs a, const DevState* halt) {
   if (run_halted(halt)) return;
-  __shared__ float As[kKStep][kTile + 1];
-  __shared__ float Bs[kKStep][kTile + 1];
+  extern __shared__ __align__(16) float sm[];
+  const int L = a.L, H1 = a.H1, H2 = a.H2, R = a.R;
+  float* X = sm;              // R x L
+  float* A1 = X + R * L;      // R x H1 pre-activations
+  float* Hd1 = A1 + R * H1;   // R x H1 activations
+  float* D1 = Hd1 + R * H1;   // R x H1: dLoss/dA1
+  float* A2 = D1 + R * H1;    // R x H2
+  float* Hd2 = A2 + R * H2;   // R x H2
+  float* D2 = Hd2 + R * H2;   // R x H2: dLoss/dA2
+  __shared__ float s_t[kMaxR], s_y[kMaxR], s_dy[kMaxR], s_red[(kThreads / 64) * kMaxR];
+  __shared__ int s_slot[kMaxR];
   const int tid = threadIdx.x;
-  const int tm = tid / 16, tn = tid % 16;  // 16 x 16 threads, 4 x 4 outputs each
-  const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
-  // K slice of this workgroup (whole K without a split)
-  const int kc = (g.K + g.S - 1) / g.S;
-  const int kbeg = blockIdx.z * kc, kend = min(g.K, kbeg + kc);
-  float acc[4][4] = {};
-  for (int k0 = kbeg; k0 < kend; k0 += kKStep) {
-    for (int e = tid; e < kTile * kKStep; e += kGemmThreads) {
-      const int r = e / kKStep, kk = e % kKStep;  // A tile: 64 rows x 16 k
-      const int m = m0 + r, k = k0 + kk;
-      As[kk][r] = (m < g.M && k < kend) ? g.A[m * g.as0 + k * g.as1] : 0.0f;
-      const int c = e % kTile, kb = e / kTile;    // B tile: 16 k x 64 cols
-      const int n = n0 + c, k2 = k0 + kb;
-      Bs[kb][c] = (n < g.N && k2 < kend) ? g.B[k2 * g.bs0 + n * g.bs1] : 0.0f;
+  const int64_t oW1 = 0, ob1 = (int64_t)H1 * L, oW2 = ob1 + H1, ob2 = oW2 + (int64_t)H2 * H1,
+                ow3 = ob2 + H2, ob3 = ow3 + H2;
+  const float* P = a.params;
+  const float* W1T = a.WT;
+  const float* W2T = a.WT + (int64_t)L * H1;
+  float* slab = kTrain ? a.slab + (int64_t)blockIdx.x * (a.total + 1) : nullptr;
+  bool first = true;
+  auto put = [&](int64_t o, float v) { slab[o] = first ? v : slab[o] + v; };
+
+  for (int r0 = blockIdx.x * R; r0 < a.B; r0 += a.W * R) {
+    const int nr = min(R, a.B - r0);
+    // ---- rows and targets
+    if (tid < nr) {
+      if (a.X == nullptr) {
+        const int i = r0 + tid;
+        const uint32_t w = philox((uint32_t)*a.step, (uint32_t)i, 0u, kTagMinibatch, a.k0, a.k1).x;
+        int slot;
+        if (i < a.B - a.n_recent) {
+          slot = (int)__umulhi(w, (uint32_t)a.ss->count);
+        } else {
+          const int back = (int)__umulhi(w, (uint32_t)a.ss->last);
+          slot = (int)(((int64_t)a.ss->head - 1 - back + a.cap) % a.cap);
+        }
+        s_slot[tid] = slot;
+        if (kTrain) s_t[tid] = (a.bufy[slot] - a.ss->mu) / a.ss->sigma;
+      } else if (kTrain) {
+        s_t[tid] = a.target[r0 + tid];
+      }
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < kKStep; ++kk) {
-      float a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tm * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+    for (int e = tid; e < R * L; e += kThreads) {
+      const int r = e / L, l = e - r * L;
+      float v = 0.0f;
+      if (r < nr) v = a.X ? a.X[(int64_t)(r0 + r) * L + l] : a.buf[(int64_t)s_slot[r] * L + l];
+      X[e] = v;
     }
+    __syncthreads();
+    // ---- layer 1: A1 = X W1^T + b1
+    for (int j = tid; j < H1; j += kThreads) {
+      float acc[kMaxR];
+      const float b = P[ob1 + j];
+#pragma unroll
+      for (int r = 0; r < kMaxR; ++r) acc[r] = b;
+      for (int l = 0; l < L; ++l) {
+        const float w = W1T[(int64_t)l * H1 + j];
+#pragma unroll
+        for (int r = 0; r < kMaxR; ++r)
+          if (r < R) acc[r] = fmaf(w, X[r * L + l], acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < kMaxR; ++r)
+        if (r < R) {
+          A1[r * H1 + j] = acc[r];
+          Hd1[r * H1 + j] = gelu(acc[r]);
+        }
+    }
+    __syncthreads();
+    // ---- layer 2: A2 = H1 W2^T + b2, and the head's per-thread terms
+    float yp[kMaxR];
+#pragma unroll
+    for (int r = 0; r < kMaxR; ++r) yp[r] = 0.0f;
+    for (int j = tid; j < H2; j += kThreads) {
+      float acc[kMaxR];
+      const float b = P[ob2 + j];
+#pragma unroll
+      for (int r = 0; r < kMaxR; ++r) acc[r] = b;
+      for (int i = 0; i < H1; ++i) {
+        const float w = W2T[(int64_t)i * H2 + j];
+#pragma unroll
+        for (int r = 0; r < kMaxR; ++r)
+          if (r < R) acc[r] = fmaf(w, Hd1[r * H1 + i], acc[r]);
+      }
+      const float w3 = P[ow3 + j];
+#pragma unroll
+      for (int r = 0; r < kMaxR; ++r)
+        if (r < R) {
+          A2[r * H2 + j] = acc[r];
+          const float h = gelu(acc[r]);
+          Hd2[r * H2 + j] = h;
+          yp[r] = fmaf(h, w3, yp[r]);
+        }
+    }
+    // ---- head: y = H2 w3 + b3
+    block_sum_rows(yp, s_red, s_y);
+    if (!kTrain) {
+      if (tid < nr) a.y[r0 + tid] = s_y[tid] + P[ob3];
+      __syncthreads();
+      continue;
+    }
+    // ---- loss and output gradient: residual = y - t, dy = 2 residual / B
+    if (tid < kMaxR) {
+      const float res = tid < nr ? (s_y[tid] + P[ob3]) - s_t[tid] : 0.0f;
+      s_dy[tid] = 2.0f * res / (float)a.B;
+      s_y[tid] = res * res;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      float dsum = 0.0f, lsum = 0.0f;
+      for (int r = 0; r < nr; ++r) {
+        dsum += s_dy[r];
+        lsum += s_y[r];
+      }
+      put(ob3, dsum);
+      put(a.total, lsum);
+    }
+    // ---- dA2 = dy w3 gelu'(A2); gradients of w3 and b2
+    for (int j = tid; j < H2; j += kThreads) {
+      const float w3 = P[ow3 + j];
+      float gw3 = 0.0f, gb2 = 0.0f;
+      for (int r = 0; r < R; ++r) {
+        const float dy = s_dy[r];  // zero for rows past the batch
+        gw3 = fmaf(Hd2[r * H2 + j], dy, gw3);
+        const float d = dy * w3 * gelu_grad(A2[r * H2 + j]);
+        D2[r * H2 + j] = d;
+        gb2 += d;
+      }
+      put(ow3 + j, gw3);
+      put(ob2 + j, gb2);
+    }
+    __syncthreads();
+    // ---- gradient of W2: dA2^T H1
+    for (int64_t e = tid; e < (int64_t)H2 * H1; e += kThreads) {
+      const int j = (int)(e / H1), i = (int)(e - (int64_t)j * H1);
+      float g = 0.0f;
+      for (int r = 0; r < R; ++r) g = fmaf(D2[r * H2 + j], Hd1[r * H1 + i], g);
+      put(oW2 + e, g);
+    }
+    // ---- dA1 = (dA2 W2) gelu'(A1); gradient of b1
+    for (int i = tid; i < H1; i += kThreads) {
+      float acc[kMaxR];
+#pragma unroll
+      for (int r = 0; r < kMaxR; ++r) acc[r] = 0.0f;
+      for (int j = 0; j < H2; ++j) {
+        const float w = P[oW2 + (int64_t)j * H1 + i];
+#pragma unroll
+        for (int r = 0; r < kMaxR; ++r)
+          if (r < R) acc[r] = fmaf(D2[r * H2 + j], w, acc[r]);
+      }
+      float gb1 = 0.0f;
+#pragma unroll
+      for (int r = 0; r < kMaxR; ++r)
+        if (r < R) {
+          const float d = acc[r] * gelu_grad(A1[r * H1 + i]);
+          D1[r * H1 + i] = d;
+          gb1 += d;
+        }
+      put(ob1 + i, gb1);
+    }
+    __syncthreads();
+    // ---- gradient of W1: dA1^T X
+    for (int64_t e = tid; e < (int64_t)H1 * L; e += kThreads) {
+      const int i = (int)(e / L), l = (int)(e - (int64_t)i * L);
+      float g = 0.0f;
+      for (int r = 0; r < R; ++r) g = fmaf(D1[r * H1 + i], X[r * L + l], g);
+      put(oW1 + e, g);
+    }
+    first = false;
     __syncthreads();
   }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int m = m0 + tm * 4 + i;
-    if (m >= g.M) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + tn * 4 + j;
-      if (n >= g.N) continue;
-      if constexpr (EPI == kEpiPartial)
-        g.part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j];
-      else
-        epilogue<EPI>(g, m, n, acc[i][j]);
+  // a workgroup without rows contributes zeros
+  if (kTrain && first)
+    for (int64_t e = tid; e <= a.total; e += kThreads) slab[e] = 0.0f;
+}
+
+struct ReduceArgs {
+  const float* slab;  // W slabs, `stride` floats apart
+  int W;
+  int64_t stride, total;
+  int B;          // rows behind the sums (loss = sum / B)
+  float* grads;   // gradient output (null: Adam)
+  float* loss;    // loss output (null: none; the slabs then have no loss entry)
+  float* params;  // Adam
+  float* WT;
+  float* m;
+  float* v;
+  int32_t* step;  // step counter, then an arrival counter (zero between launches)
+  float lr;
+  int L, H1, H2;
+};
+
+// Adds the slabs in order; writes the gradient, or applies one Adam step with
+// t = step + 1 and refreshes the transposed weights; the last workgroup
+// stores t.
+__global__ void reduce_kernel(ReduceArgs a, const DevState* halt) {
+  if (run_halted(halt)) return;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = a.grads ? 0 : *a.step + 1;
+  if (p < a.total || (p == a.total && a.loss)) {
+    float g = 0.0f;
+    for (int w = 0; w < a.W; ++w) g += a.slab[(int64_t)w * a.stride + p];
+    if (p == a.total) {
+      *a.loss = g / (float)a.B;
+    } else if (a.grads) {
+      a.grads[p] = g;
+    } else {
+      const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+      const float mi = b1 * a.m[p] + (1.0f - b1) * g;
+      const float vi = b2 * a.v[p] + (1.0f - b2) * g * g;
+      a.m[p] = mi;
+      a.v[p] = vi;
+      const float mhat = mi / (1.0f - powf(b1, (float)t));
+      const float vhat = vi / (1.0f - powf(b2, (float)t));
+      const float nv = a.params[p] - a.lr * mhat / (sqrtf(vhat) + eps);
+      a.params[p] = nv;
+      const int64_t n1 = (int64_t)a.H1 * a.L, o2 = n1 + a.H1, n2 = (int64_t)a.H2 * a.H1;
+      if (p < n1) {
+        const int64_t j = p / a.L, l = p - j * a.L;
+        a.WT[l * a.H1 + j] = nv;
+      } else if (p >= o2 && p < o2 + n2) {
+        const int64_t q = p - o2, j = q / a.H1, i = q - j * a.H1;
+        a.WT[n1 + i * a.H2 + j] = nv;
+      }
     }
+  }
+  if (a.grads) return;
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    s_last = atomicAdd(reinterpret_cast<uint32_t*>(a.step + 1), 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (s_last && threadIdx.x == 0) {
+    *a.step = t;
+    a.step[1] = 0;
   }
 }
 
-// Split K, second pass: add the S slices in order, then the epilogue.
-template <int EPI>
-__global__ void splitk_sum_kernel(GemmArgs g, const DevState* halt) {
-  if (run_halted(halt)) return;
+// Transposed copies of W1 and W2 from the parameters.
+__global__ void transpose_kernel(const float* __restrict__ P, float* __restrict__ WT, int L, int H1,
+                                 int H2) {
+  const int64_t n1 = (int64_t)H1 * L, n2 = (int64_t)H2 * H1;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t mn = (int64_t)g.M * g.N;
-  if (e >= mn) return;
-  float acc = 0.0f;
-  for (int z = 0; z < g.S; ++z) acc += g.part[z * mn + e];
-  epilogue<EPI>(g, (int)(e / g.N), (int)(e % g.N), acc);
-}
-
-constexpr int kFillWgs = 256;  // workgroups that fill the chip once
-
-template <int EPI>
-hipError_t gemm(GemmArgs g, const float* part, int64_t part_cap, const DevState* halt, hipStream_t s) {
-  if (g.M == 0 || g.N == 0) return hipSuccess;
-  const int tiles = ((g.N + kTile - 1) / kTile) * ((g.M + kTile - 1) / kTile);
-  int S = 1;
-  if (part && tiles < kFillWgs) {
-    S = (kFillWgs + tiles - 1) / tiles;
-    S = std::min(S, std::max(1, g.K / (4 * kKStep)));           // slices of >= 64 k
-    S = (int)std::min<int64_t>(S, part_cap / ((int64_t)g.M * g.N));
-    if (S < 1) S = 1;
+  if (e < n1) {
+    const int64_t j = e / L, l = e - j * L;
+    WT[l * H1 + j] = P[e];
+  } else if (e < n1 + n2) {
+    const int64_t q = e - n1, j = q / H1, i = q - j * H1;
+    WT[n1 + i * H2 + j] = P[n1 + H1 + q];
   }
-  g.S = S;
-  g.part = const_cast<float*>(part);
-  const dim3 grid((unsigned)((g.N + kTile - 1) / kTile), (unsigned)((g.M + kTile - 1) / kTile), (unsigned)S);
-  if (S == 1) {
-    hipLaunchKernelGGL(gemm_kernel<EPI>, grid, dim3(kGemmThreads), 0, s, g, halt);
-  } else {
-    hipLaunchKernelGGL(gemm_kernel<kEpiPartial>, grid, dim3(kGemmThreads), 0, s, g, halt);
-    const int64_t mn = (int64_t)g.M * g.N;
-    hipLaunchKernelGGL(splitk_sum_kernel<EPI>, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, g,
-                       halt);
-  }
-  return hipGetLastError();
-}
-
-// y[b] = h2[b, :] . w3 + b3 (one wave per row, lanes over the hidden units,
-// fixed shuffle tree)
-__global__ void head_kernel(const float* __restrict__ h2, int B, int H2, const float* __restrict__ w3,
-                            const float* __restrict__ b3, float* __restrict__ y, const DevState* halt) {
-  if (run_halted(halt)) return;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (row >= B) return;
-  float s = 0.0f;
-  for (int k = lane; k < H2; k += 64) s = fmaf(h2[(int64_t)row * H2 + k], w3[k], s);
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if (lane == 0) y[row] = s + b3[0];
-}
-
-// Loss and output gradient: r = y - target, dy = 2 r / B; loss = sum r^2 / B
-// (one workgroup, fixed order).
-__global__ void loss_kernel(const float* __restrict__ y, const float* __restrict__ target, int B,
-                            float* __restrict__ dy, float* __restrict__ loss, const DevState* halt) {
-  if (run_halted(halt)) return;
-  __shared__ float part[256];
-  float s = 0.0f;
-  for (int b = threadIdx.x; b < B; b += 256) {
-    const float r = y[b] - target[b];
-    dy[b] = 2.0f * r / (float)B;
-    s = fmaf(r, r, s);
-  }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float t = 0.0f;
-    for (int i = 0; i < 256; ++i) t += part[i];
-    if (loss) *loss = t / (float)B;
-  }
-}
-
-// dA2[b, n] = dy[b] * w3[n] * gelu'(A2[b, n])
-__global__ void head_back_kernel(const float* __restrict__ dy, const float* __restrict__ w3,
-                                 const float* __restrict__ a2, int B, int H2, float* __restrict__ da2,
-                                 const DevState* halt) {
-  if (run_halted(halt)) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)B * H2) return;
-  const int b = (int)(i / H2), n = (int)(i % H2);
-  da2[i] = dy[b] * w3[n] * gelu_grad(a2[i]);
-}
-
-// Column sums (bias gradients) and the head weight gradient: out[n] = sum_b
-// X[b, n] * (w ? w[b] : 1).  A workgroup takes 64 columns; its 16 row slices
-// (rows b = slice mod 16, in order) are added in slice order.
-__global__ __launch_bounds__(1024) void colsum_kernel(const float* __restrict__ X,
-                                                      const float* __restrict__ w, int B, int N,
-                                                      float* __restrict__ out, const DevState* halt) {
-  if (run_halted(halt)) return;
-  __shared__ float part[16][64];
-  const int c = threadIdx.x & 63, slice = threadIdx.x >> 6;
-  const int n = blockIdx.x * 64 + c;
-  float s = 0.0f;
-  if (n < N)
-    for (int b = slice; b < B; b += 16) s = fmaf(X[(int64_t)b * N + n], w ? w[b] : 1.0f, s);
-  part[slice][c] = s;
-  __syncthreads();
-  if (slice == 0 && n < N) {
-    float t = 0.0f;
-    for (int q = 0; q < 16; ++q) t += part[q][c];
-    out[n] = t;
-  }
-}
-
-// Adam over the flat parameter array; t is the step number after increment.
-__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                            float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
-                            const int32_t* __restrict__ step, const DevState* halt) {
-  if (run_halted(halt)) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int t = *step;
-  const float mi = b1 * m[i] + (1.0f - b1) * g[i];
-  const float vi = b2 * v[i] + (1.0f - b2) * g[i] * g[i];
-  m[i] = mi;
-  v[i] = vi;
-  const float mhat = mi / (1.0f - powf(b1, (float)t));
-  const float vhat = vi / (1.0f - powf(b2, (float)t));
-  p[i] -= lr * mhat / (sqrtf(vhat) + eps);
-}
-
-__global__ void step_inc_kernel(int32_t* step, const DevState* halt) {
-  if (run_halted(halt)) return;
-  *step += 1;
 }
 
 // He-uniform init: block (layer, row, col, MLP_INIT) word 0 -> u in (0, 1),
@@ -256,26 +344,87 @@ __global__ void init_kernel(float* __restrict__ p, float* __restrict__ m, float*
   if (i >= total) return;
   m[i] = 0.0f;
   v[i] = 0.0f;
-  int layer = 0, rows = 0, cols = 1;
+  int layer = 0, cols = 1;
   int64_t j = i;
   if (j < n1) {
-    layer = 1; cols = L;
+    layer = 1;
+    cols = L;
   } else if ((j -= n1) < H1) {
-    p[i] = 0.0f; return;
+    p[i] = 0.0f;
+    return;
   } else if ((j -= H1) < n2) {
-    layer = 2; cols = H1;
+    layer = 2;
+    cols = H1;
   } else if ((j -= n2) < H2) {
-    p[i] = 0.0f; return;
+    p[i] = 0.0f;
+    return;
   } else if ((j -= H2) < H2) {
-    layer = 3; cols = H2;
+    layer = 3;
+    cols = H2;
   } else {
-    p[i] = 0.0f; return;
+    p[i] = 0.0f;
+    return;
   }
-  (void)rows;
   const uint32_t r = (uint32_t)(j / cols), c = (uint32_t)(j % cols);
   const u32x4 b = philox((uint32_t)layer, r, c, kTagMlpInit, k0, k1);
   const double u = ((double)(b.x >> 8) + 0.5) * 0x1p-24;
   p[i] = (float)(sqrt(6.0 / (double)cols) * (2.0 * u - 1.0));
+}
+
+size_t rows_lds(const MlpDims& d, int R) {
+  return (size_t)R * ((size_t)d.L + 3 * (size_t)d.H1 + 3 * (size_t)d.H2) * sizeof(float);
+}
+
+hipError_t rows_prepare() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rows_kernel<true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowsLds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(rows_kernel<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowsLds);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+hipError_t launch_rows(bool train, const RowsArgs& a, const MlpDims& d, const DevState* halt,
+                       hipStream_t s) {
+  const hipError_t e = rows_prepare();
+  if (e != hipSuccess) return e;
+  const size_t lds = rows_lds(d, a.R);
+  if (train)
+    hipLaunchKernelGGL(rows_kernel<true>, dim3((unsigned)a.W), dim3(kThreads), lds, s, a, halt);
+  else
+    hipLaunchKernelGGL(rows_kernel<false>, dim3((unsigned)a.W), dim3(kThreads), lds, s, a, halt);
+  return hipGetLastError();
+}
+
+int64_t slab_stride(const MlpDims& d) { return mlp_layout(d.L, d.H1, d.H2).total + 1; }
+
+RowsArgs rows_args(const MlpDims& d, const float* params, const float* WT, int B) {
+  RowsArgs a{};
+  a.params = params;
+  a.WT = WT;
+  a.L = d.L;
+  a.H1 = d.H1;
+  a.H2 = d.H2;
+  a.B = B;
+  a.R = mlp_rows_per_pass(d);
+  a.total = mlp_layout(d.L, d.H1, d.H2).total;
+  return a;
+}
+
+// Workgroups of a training launch: one per R rows, as many slabs as fit.
+int train_wgs(const MlpDims& d, int B, int R, int64_t slab_cap) {
+  int64_t W = (B + R - 1) / R;
+  W = std::min<int64_t>(W, slab_cap / slab_stride(d));
+  return (int)std::max<int64_t>(W, 1);
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, const DevState* halt, hipStream_t s) {
+  const int64_t n = a.total + 1;
+  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, halt);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -292,72 +441,124 @@ MlpLayout mlp_layout(int L, int H1, int H2) {
   return o;
 }
 
-hipError_t mlp_init(const MlpDims& d, float* params, float* m, float* v, uint64_t seed,
+int mlp_rows_per_pass(const MlpDims& d) {
+  int R = kMaxR;
+  while (R > 1 && rows_lds(d, R) > kRowsLds) R /= 2;
+  return R;
+}
+
+bool mlp_fits(const MlpDims& d) { return rows_lds(d, 1) <= kRowsLds; }
+
+int64_t mlp_slab_floats(const MlpDims& d, int rows) {
+  const int64_t per = slab_stride(d);
+  const int R = mlp_rows_per_pass(d);
+  int64_t W = std::min<int64_t>((rows + R - 1) / R, kMlpSlabFloats / per);
+  return std::max<int64_t>(W, 1) * per;
+}
+
+hipError_t mlp_transpose(const MlpDims& d, const float* params, float* WT, hipStream_t s) {
+  const int64_t n = (int64_t)d.H1 * d.L + (int64_t)d.H2 * d.H1;
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params, WT,
+                     d.L, d.H1, d.H2);
+  return hipGetLastError();
+}
+
+hipError_t mlp_init(const MlpDims& d, float* params, float* m, float* v, float* WT, uint64_t seed,
                     hipStream_t s) {
   const int64_t n = mlp_layout(d.L, d.H1, d.H2).total;
   hipLaunchKernelGGL(init_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params, m, v,
                      d.L, d.H1, d.H2, (uint32_t)seed, (uint32_t)(seed >> 32));
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return mlp_transpose(d, params, WT, s);
 }
 
-// Forward for B rows of X (B x L, row stride L).  a1/a2 (pre-activations) may
-// be null when no backward pass follows.
-hipError_t mlp_forward(const MlpDims& d, const float* params, const float* X, int B, float* a1,
-                       float* h1, float* a2, float* h2, float* y, float* part, int64_t part_cap,
-                       const DevState* halt, hipStream_t s) {
-  const MlpLayout o = mlp_layout(d.L, d.H1, d.H2);
-  hipError_t e;
-  e = gemm<kEpiBiasGelu>({B, d.H1, d.L, X, d.L, 1, params + o.W1, 1, d.L, h1, d.H1, params + o.b1, a1},
-                         part, part_cap, halt, s);
-  if (e != hipSuccess) return e;
-  e = gemm<kEpiBiasGelu>({B, d.H2, d.H1, h1, d.H1, 1, params + o.W2, 1, d.H1, h2, d.H2, params + o.b2, a2},
-                         part, part_cap, halt, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(head_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, h2, B, d.H2,
-                     params + o.w3, params + o.b3, y, halt);
-  return hipGetLastError();
+hipError_t mlp_forward(const MlpDims& d, const float* params, const float* WT, const float* X, int B,
+                       float* y, const DevState* halt, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  RowsArgs a = rows_args(d, params, WT, B);
+  a.W = (B + a.R - 1) / a.R;
+  a.X = X;
+  a.y = y;
+  return launch_rows(false, a, d, halt, s);
 }
 
-// Gradients of the mean squared error for one batch (forward included).
-hipError_t mlp_grads(const MlpDims& d, const float* params, const float* X, const float* target,
-                     int B, const MlpScratch& w, float* grads, float* loss, const DevState* halt,
-                     hipStream_t s) {
-  const MlpLayout o = mlp_layout(d.L, d.H1, d.H2);
-  hipError_t e = mlp_forward(d, params, X, B, w.a1, w.h1, w.a2, w.h2, w.y, w.part, w.part_cap, halt, s);
+hipError_t mlp_grads(const MlpDims& d, const float* params, const float* WT, const float* X,
+                     const float* target, int B, float* slab, int64_t slab_cap, float* grads,
+                     float* loss, const DevState* halt, hipStream_t s) {
+  RowsArgs a = rows_args(d, params, WT, B);
+  a.W = train_wgs(d, B, a.R, slab_cap);
+  a.X = X;
+  a.target = target;
+  a.slab = slab;
+  hipError_t e = launch_rows(true, a, d, halt, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, s, w.y, target, B, w.dy, loss, halt);
-  // head: gw3 = h2^T dy, gb3 = sum dy
-  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((d.H2 + 63) / 64)), dim3(1024), 0, s, w.h2,
-                     w.dy, B, d.H2, grads + o.w3, halt);
-  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(1024), 0, s, w.dy, nullptr, B, 1, grads + o.b3, halt);
-  const int64_t n2 = (int64_t)B * d.H2;
-  hipLaunchKernelGGL(head_back_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, w.dy,
-                     params + o.w3, w.a2, B, d.H2, w.da2, halt);
-  // layer 2: gW2 = dA2^T h1, gb2 = colsum dA2, dA1 = (dA2 W2) * gelu'(A1)
-  e = gemm<kEpiStore>({d.H2, d.H1, B, w.da2, 1, d.H2, w.h1, d.H1, 1, grads + o.W2, d.H1, nullptr, nullptr},
-                      w.part, w.part_cap, halt, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((d.H2 + 63) / 64)), dim3(1024), 0, s, w.da2,
-                     nullptr, B, d.H2, grads + o.b2, halt);
-  e = gemm<kEpiGeluGrad>({B, d.H1, d.H2, w.da2, d.H2, 1, params + o.W2, d.H1, 1, w.da1, d.H1, nullptr, w.a1},
-                         w.part, w.part_cap, halt, s);
-  if (e != hipSuccess) return e;
-  // layer 1: gW1 = dA1^T X, gb1 = colsum dA1
-  e = gemm<kEpiStore>({d.H1, d.L, B, w.da1, 1, d.H1, X, d.L, 1, grads + o.W1, d.L, nullptr, nullptr},
-                      w.part, w.part_cap, halt, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((d.H1 + 63) / 64)), dim3(1024), 0, s, w.da1,
-                     nullptr, B, d.H1, grads + o.b1, halt);
-  return hipGetLastError();
+  ReduceArgs r{};
+  r.slab = slab;
+  r.W = a.W;
+  r.stride = a.total + 1;
+  r.total = a.total;
+  r.B = B;
+  r.grads = grads;
+  r.loss = loss;
+  return launch_reduce(r, halt, s);
 }
 
-hipError_t mlp_adam(const MlpDims& d, float* params, const float* grads, float* m, float* v,
+hipError_t mlp_train_step(const MlpDims& d, float* params, float* WT, float* m, float* v,
+                          int32_t* step, float lr, const float* buf, const float* bufy,
+                          const SurState* ss, uint64_t seed, int B, int n_recent, int cap,
+                          float* slab, int64_t slab_cap, float* loss, const DevState* halt,
+                          hipStream_t s) {
+  RowsArgs a = rows_args(d, params, WT, B);
+  a.W = train_wgs(d, B, a.R, slab_cap);
+  a.buf = buf;
+  a.bufy = bufy;
+  a.ss = ss;
+  a.step = step;
+  a.k0 = (uint32_t)seed;
+  a.k1 = (uint32_t)(seed >> 32);
+  a.n_recent = n_recent;
+  a.cap = cap;
+  a.slab = slab;
+  hipError_t e = launch_rows(true, a, d, halt, s);
+  if (e != hipSuccess) return e;
+  ReduceArgs r{};
+  r.slab = slab;
+  r.W = a.W;
+  r.stride = a.total + 1;
+  r.total = a.total;
+  r.B = B;
+  r.loss = loss;
+  r.params = params;
+  r.WT = WT;
+  r.m = m;
+  r.v = v;
+  r.step = step;
+  r.lr = lr;
+  r.L = d.L;
+  r.H1 = d.H1;
+  r.H2 = d.H2;
+  return launch_reduce(r, halt, s);
+}
+
+hipError_t mlp_adam(const MlpDims& d, float* params, float* WT, const float* grads, float* m, float* v,
                     int32_t* step, float lr, const DevState* halt, hipStream_t s) {
-  const int64_t n = mlp_layout(d.L, d.H1, d.H2).total;
-  hipLaunchKernelGGL(step_inc_kernel, dim3(1), dim3(1), 0, s, step, halt);
-  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params, grads,
-                     m, v, n, lr, 0.9f, 0.999f, 1e-8f, step, halt);
-  return hipGetLastError();
+  ReduceArgs r{};
+  r.slab = grads;  // one slab: the gradient itself (no loss entry)
+  r.W = 1;
+  r.total = mlp_layout(d.L, d.H1, d.H2).total;
+  r.stride = r.total;
+  r.B = 1;
+  r.params = params;
+  r.WT = WT;
+  r.m = m;
+  r.v = v;
+  r.step = step;
+  r.lr = lr;
+  r.L = d.L;
+  r.H1 = d.H1;
+  r.H2 = d.H2;
+  return launch_reduce(r, halt, s);
 }
 
 }  // namespace game

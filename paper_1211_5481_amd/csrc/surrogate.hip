@@ -244,30 +244,6 @@ __global__ __launch_bounds__(1024) void buffer_stats_kernel(const float* __restr
   }
 }
 
-// Minibatch of training step s, w = word 0 of block (s, i, 0, MINIBATCH):
-// rows i < B - n_recent take slot floor(w * count / 2^32) (the whole buffer),
-// the others slot head - 1 - floor(w * last / 2^32) mod cap (the latest
-// append); targets are standardised with the buffer statistics.
-__global__ void minibatch_kernel(const float* __restrict__ buf, const float* __restrict__ buf_y, int L,
-                                 int B, int n_recent, int cap, const SurState* ss,
-                                 const int32_t* step, uint32_t k0, uint32_t k1,
-                                 float* __restrict__ Xb, float* __restrict__ tb, const DevState* st) {
-  if (run_halted(st)) return;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)B * L) return;
-  const int i = (int)(e / L), l = (int)(e % L);
-  const uint32_t w = philox((uint32_t)*step, (uint32_t)i, 0u, kTagMinibatch, k0, k1).x;
-  int slot;
-  if (i < B - n_recent) {
-    slot = (int)__umulhi(w, (uint32_t)ss->count);
-  } else {
-    const int back = (int)__umulhi(w, (uint32_t)ss->last);
-    slot = (int)(((int64_t)ss->head - 1 - back + cap) % cap);
-  }
-  Xb[e] = buf[(int64_t)slot * L + l];
-  if (l == 0) tb[i] = (buf_y[slot] - ss->mu) / ss->sigma;
-}
-
 // ----------------------------------------------------------- population
 // Snapshot the current elites' exact values before the merge overwrites them.
 __global__ void snapshot_kernel(const int* __restrict__ elite, int E, const double* __restrict__ fit,
@@ -397,16 +373,6 @@ hipError_t sur_append(const float* genes, const double* mse, int n, int L, float
   hipLaunchKernelGGL(append_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, genes, mse, n,
                      L, buf, buf_y, cap, ss, st);
   hipLaunchKernelGGL(buffer_stats_kernel, dim3(1), dim3(1024), 0, s, buf_y, cap, n, ss, st);
-  return hipGetLastError();
-}
-
-hipError_t sur_minibatch(const float* buf, const float* buf_y, int L, int B, int n_recent, int cap,
-                         const SurState* ss, const int32_t* step, uint64_t seed, float* Xb, float* tb,
-                         const DevState* st, hipStream_t s) {
-  const int64_t t = (int64_t)B * L;
-  hipLaunchKernelGGL(minibatch_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, buf, buf_y,
-                     L, B, n_recent, cap, ss, step, (uint32_t)seed, (uint32_t)(seed >> 32), Xb, tb,
-                     st);
   return hipGetLastError();
 }
 
