@@ -306,6 +306,24 @@ game_status game_mlp_adam(game_ctx* ctx, const float* grads_dev);
 game_status game_get_population(game_ctx* ctx, float* genes_dev);
 game_status game_set_population(game_ctx* ctx, const float* genes_dev);
 
+/*
+ * Checkpoint and resume.  game_save writes everything a context carries from
+ * one generation to the next into a host buffer: the run state, both
+ * population buffers, the last fitness values, elites and best genes, and in
+ * the offspring form the surrogate's parameters, Adam moments and step, its
+ * replay ring and statistics and the log.  The random draws are counter
+ * based, so a context that loads the checkpoint continues bit for bit as the
+ * saving one would.  Blocking.
+ *   game_save: host_buf NULL -> *bytes = size needed; otherwise *bytes (in)
+ *              is the buffer size (GAME_E_INVALID if too small) and (out)
+ *              the size written.
+ *   game_load: into a context created with the same configuration (only
+ *              max_generations and mse_threshold may differ) and the same
+ *              patterns; GAME_E_INVALID for a foreign or mismatched buffer.
+ */
+game_status game_save(game_ctx* ctx, void* host_buf, size_t* bytes);
+game_status game_load(game_ctx* ctx, const void* host_buf, size_t bytes);
+
 /* Blocking snapshot of the run state; best genes optional (host, L floats). */
 game_status game_get_state(game_ctx* ctx, game_state* out, float* best_genes_host);
 

@@ -117,6 +117,8 @@ SIGNATURES = {
     "game_batch_run": (C.c_int, [_VP, _VP, _VP]),
     "game_batch_destroy": (None, [_VP]),
     "game_run_batched": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, C.c_size_t, _VP, _VP, _VP]),
+    "game_save": (C.c_int, [_VP, _VP, C.POINTER(C.c_size_t)]),
+    "game_load": (C.c_int, [_VP, _VP, C.c_size_t]),
     "game_get_population": (C.c_int, [_VP, _VP]),
     "game_set_population": (C.c_int, [_VP, _VP]),
     "game_get_state": (C.c_int, [_VP, C.POINTER(GameState), _VP]),

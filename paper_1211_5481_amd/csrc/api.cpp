@@ -952,6 +952,119 @@ game_status game_set_population(game_ctx* c, const float* genes) {
   return dev(c, launch_pop_copy(c->pop0, c->pop1, c->state, const_cast<float*>(genes), (int64_t)c->plan.P * c->plan.L, 1, c->stream), "population copy");
 }
 
+// Checkpoint sections: every device buffer that carries state from one
+// generation to the next (the basis, targets, gene tile and scratch are
+// rebuilt or rewritten).
+struct Section {
+  void* dev;
+  size_t bytes;
+};
+
+static std::vector<Section> checkpoint_sections(game_ctx* c) {
+  const Plan& p = c->plan;
+  std::vector<Section> v = {
+      {c->state, sizeof(DevState)},
+      {c->pop0, (size_t)p.P * p.L * 4},
+      {c->pop1, (size_t)p.P * p.L * 4},
+      {c->mse, (size_t)p.P_max * 8},
+      {c->miscls, (size_t)p.P_max * 8},
+      {c->fit, (size_t)p.P_max * 8},
+      {c->elite, (size_t)kMaxElite * 4},
+      {c->best, (size_t)p.L * 4},
+  };
+  if (p.offspring) {
+    v.push_back({c->sst, sizeof(SurState)});
+    v.push_back({c->log, (size_t)kLogCap * 4 * 4});
+    v.push_back({c->rho, 16});
+    v.push_back({c->loss, 16});
+    if (p.sur == GAME_SURROGATE_MLP) {
+      const size_t np = (size_t)mlp_layout(p.L, p.H, p.H).total * 4;
+      v.push_back({c->prm, np});
+      v.push_back({c->am, np});
+      v.push_back({c->av, np});
+      v.push_back({c->step, 16});
+      v.push_back({c->buf, (size_t)p.cap * p.L * 4});
+      v.push_back({c->bufy, (size_t)p.cap * 4});
+    }
+  }
+  return v;
+}
+
+struct CheckpointHeader {
+  char magic[8];
+  uint32_t version, config_bytes;
+  uint64_t total_bytes;
+  int32_t have_eval, sur_warm;
+  game_config cfg;
+};
+
+// The configuration a checkpoint must match: all but the run limits.
+static game_config comparable(game_config c) {
+  c.max_generations = 0;
+  c.mse_threshold = 0.0;
+  return c;
+}
+
+game_status game_save(game_ctx* c, void* host, size_t* bytes) {
+  GAME_TRY(check_ctx(c));
+  if (!bytes) return fail(GAME_E_INVALID, "bytes is NULL");
+  const std::vector<Section> secs = checkpoint_sections(c);
+  size_t need = sizeof(CheckpointHeader);
+  for (const Section& x : secs) need += x.bytes;
+  if (!host) {
+    *bytes = need;
+    return GAME_OK;
+  }
+  if (*bytes < need) return fail(GAME_E_INVALID, "buffer of %zu bytes, %zu needed", *bytes, need);
+  CheckpointHeader h{};
+  std::memcpy(h.magic, "GAMECKPT", 8);
+  h.version = 1;
+  h.config_bytes = sizeof(game_config);
+  h.total_bytes = need;
+  h.have_eval = c->have_eval;
+  h.sur_warm = c->sur_warm;
+  h.cfg = c->cfg;
+  unsigned char* out = static_cast<unsigned char*>(host);
+  std::memcpy(out, &h, sizeof(h));
+  size_t off = sizeof(h);
+  for (const Section& x : secs) {
+    GAME_TRY(dev(c, hipMemcpyAsync(out + off, x.dev, x.bytes, hipMemcpyDeviceToHost, c->stream), "save"));
+    off += x.bytes;
+  }
+  GAME_TRY(dev(c, hipStreamSynchronize(c->stream), "synchronize"));
+  *bytes = need;
+  return GAME_OK;
+}
+
+game_status game_load(game_ctx* c, const void* host, size_t bytes) {
+  GAME_TRY(check_ctx(c));
+  if (!host || bytes < sizeof(CheckpointHeader)) return fail(GAME_E_INVALID, "not a checkpoint");
+  CheckpointHeader h;
+  std::memcpy(&h, host, sizeof(h));
+  if (std::memcmp(h.magic, "GAMECKPT", 8) != 0 || h.version != 1 || h.config_bytes != sizeof(game_config))
+    return fail(GAME_E_INVALID, "not a checkpoint of this library version");
+  const game_config a = comparable(h.cfg), b = comparable(c->cfg);
+  if (std::memcmp(&a, &b, sizeof(a)) != 0)
+    return fail(GAME_E_INVALID, "the checkpoint was taken with another configuration");
+  const std::vector<Section> secs = checkpoint_sections(c);
+  size_t need = sizeof(CheckpointHeader);
+  for (const Section& x : secs) need += x.bytes;
+  if (h.total_bytes != need || bytes < need) return fail(GAME_E_INVALID, "checkpoint size mismatch");
+  const unsigned char* in = static_cast<const unsigned char*>(host);
+  size_t off = sizeof(h);
+  for (const Section& x : secs) {
+    GAME_TRY(dev(c, hipMemcpyAsync(x.dev, in + off, x.bytes, hipMemcpyHostToDevice, c->stream), "load"));
+    off += x.bytes;
+  }
+  if (c->plan.sur == GAME_SURROGATE_MLP)
+    GAME_TRY(dev(c, mlp_transpose(mlp_dims(c), c->prm, c->WT, c->stream), "load"));
+  GAME_TRY(dev(c, hipStreamSynchronize(c->stream), "synchronize"));
+  c->have_eval = h.have_eval != 0;
+  c->sur_warm = h.sur_warm != 0;
+  c->tile_fresh = false;
+  return GAME_OK;
+}
+
 game_status game_time_fitness(game_ctx* c, int32_t reps, float* ms) {
   GAME_TRY(check_ctx(c));
   if (reps < 1 || !ms) return fail(GAME_E_INVALID, "reps must be >= 1 and ms non-NULL");

@@ -297,15 +297,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       step(std::integral_constant<int, 0>{});
       if constexpr (Tr::kSteps > 1) step(std::integral_constant<int, 1>{});
     };
+    // loads unconditional (K-block index clamped), so only the needed one is waited for
+    auto kc = [&](int k) { return k < KB ? k : KB - 1; };
     load(a0, b0, 0);
-    int kb = 0;
-    for (; kb + 1 < KB; kb += 2) {
-      load(a1, b1, kb + 1);
+    for (int kb = 0; kb < KB; kb += 2) {
+      load(a1, b1, kc(kb + 1));
       mma_all(a0, b0);
-      if (kb + 2 < KB) load(a0, b0, kb + 2);
-      mma_all(a1, b1);
+      load(a0, b0, kc(kb + 2));
+      if (kb + 1 < KB) mma_all(a1, b1);
     }
-    if (kb < KB) mma_all(a0, b0);
 
     // epilogue: accumulator element r of block (i, j) is pattern
     // nw0 + 16 i + row_in_block(r) and chromosome pw0 + 16 j + lrow
@@ -374,15 +374,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   fitness_tail<TP>(tail, pt, n_pt, n_rg, part_ld, part_sse, part_miss);
 }
 
-// Persistent decomposition, used when the gene tile of 128 chromosomes fits
-// in LDS.  The grid holds as many workgroups as can be resident; workgroup
-// (row range wr, chromosome tile pt) stages its gene tile in LDS once (row
-// stride padded so the 16 rows a quarter-wave reads sit in distinct banks)
-// and walks its contiguous range of 128-pattern row tiles.  The four waves are
-// stacked over rows, each computing 32 patterns x 128 chromosomes (2 x 8
-// blocks of 16 x 16), so every Phi row is read by exactly one wave.  The next
-// row tile's targets and first Phi K-block are fetched before the current
-// epilogue.  One partial row per workgroup: part[wr][p].
+// Persistent decomposition, used when the gene tile fits in LDS.  The grid
+// holds as many workgroups as can be resident; workgroup (row range wr,
+// chromosome tile pt) stages its gene tile in LDS once (row stride padded so
+// the 16 rows a quarter-wave reads sit in distinct banks) and walks its
+// contiguous range of 128-pattern row tiles.  The four waves are stacked over
+// rows, each computing 32 patterns x TP chromosomes (2 x WN blocks of
+// 16 x 16), so every Phi row is read by exactly one wave.  The next row
+// tile's targets and first Phi K-blocks are fetched before the current
+// epilogue.
+//
 // One work item of the LDS-staged kernels: chromosome tile pt (TP = 16 WN
 // chromosomes, staged in LDS) against row range wr of n_ranges (consecutive
 // 128-pattern row tiles, 32 rows per wave); writes the range's partial sums
@@ -466,7 +467,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
   if (rt_begin < rt_end) {
     load_t(rt_begin);
     loadA(a0, rt_begin, 0);
-    if (kDepth == 2 && KB > 1) loadA(a1, rt_begin, 1);
+    if (kDepth == 2) loadA(a1, rt_begin, KB > 1 ? 1 : 0);
   }
   __syncthreads();
 
@@ -489,80 +490,60 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
       step(std::integral_constant<int, 0>{});
       if constexpr (Tr::kSteps > 1) step(std::integral_constant<int, 1>{});
     };
-    // 16-bit operands: the gene fragments are 16 bytes per lane, so only Phi is
-    // double-buffered (LDS reads are issued right before their MFMAs)
+    // Loads are issued unconditionally (block indices clamped to the last
+    // K-block; a clamped load is simply not used), so the compiler can count
+    // the loads in flight and wait only for the one an MFMA needs: a load
+    // under a branch makes it wait for all of them.  16-bit operands: the
+    // gene fragments are 16 bytes per lane, so only Phi is double-buffered
+    // (LDS reads are issued right before their MFMAs).
     constexpr bool kDoubleB = sizeof(Ld) == 8;
-    int kb = 0;
+    auto kc = [&](int k) { return k < KB ? k : KB - 1; };
     if constexpr (kDepth == 2) {
-    // Phi fragments two K-blocks ahead: a0..a3 hold blocks kb..kb+3
-    Ld a2[WM], a3[WM];
-    if constexpr (kDoubleB) loadB(b0, 0);
-    for (; kb < KB; kb += 4) {
-      if (kb + 2 < KB) loadA(a2, rt, kb + 2);
-      if constexpr (kDoubleB) {
-        if (kb + 1 < KB) loadB(b1, kb + 1);
-      } else {
-        loadB(b0, kb);
-      }
-      mma_all(a0, b0);
-      if (kb + 3 < KB) loadA(a3, rt, kb + 3);
-      if (kb + 1 < KB) {
+      // Phi fragments two K-blocks ahead: a0..a3 hold blocks kb..kb+3
+      Ld a2[WM], a3[WM];
+      if constexpr (kDoubleB) loadB(b0, 0);
+      for (int kb = 0; kb < KB; kb += 4) {
+        loadA(a2, rt, kc(kb + 2));
+        if constexpr (kDoubleB) loadB(b1, kc(kb + 1));
+        else loadB(b0, kb);
+        mma_all(a0, b0);
+        loadA(a3, rt, kc(kb + 3));
         if constexpr (kDoubleB) {
-          if (kb + 2 < KB) loadB(b0, kb + 2);
-          mma_all(a1, b1);
+          loadB(b0, kc(kb + 2));
+          if (kb + 1 < KB) mma_all(a1, b1);
         } else {
-          loadB(b0, kb + 1);
-          mma_all(a1, b0);
+          loadB(b0, kc(kb + 1));
+          if (kb + 1 < KB) mma_all(a1, b0);
+        }
+        loadA(a0, rt, kc(kb + 4));
+        if constexpr (kDoubleB) loadB(b1, kc(kb + 3));
+        else loadB(b0, kc(kb + 2));
+        if (kb + 2 < KB) mma_all(a2, b0);
+        loadA(a1, rt, kc(kb + 5));
+        if constexpr (kDoubleB) {
+          loadB(b0, kc(kb + 4));
+          if (kb + 3 < KB) mma_all(a3, b1);
+        } else {
+          loadB(b0, kc(kb + 3));
+          if (kb + 3 < KB) mma_all(a3, b0);
         }
       }
-      if (kb + 4 < KB) loadA(a0, rt, kb + 4);
-      if (kb + 2 < KB) {
-        if constexpr (kDoubleB) {
-          if (kb + 3 < KB) loadB(b1, kb + 3);
-        } else {
-          loadB(b0, kb + 2);
-        }
-        mma_all(a2, b0);
-      }
-      if (kb + 5 < KB) loadA(a1, rt, kb + 5);
-      if (kb + 3 < KB) {
-        if constexpr (kDoubleB) {
-          if (kb + 4 < KB) loadB(b0, kb + 4);
-          mma_all(a3, b1);
-        } else {
-          loadB(b0, kb + 3);
-          mma_all(a3, b0);
-        }
-      }
-    }
     } else {
-    if constexpr (kDoubleB) {
-      loadB(b0, 0);
-      for (; kb + 1 < KB; kb += 2) {
-        loadA(a1, rt, kb + 1);
-        loadB(b1, kb + 1);
+      if constexpr (kDoubleB) loadB(b0, 0);
+      for (int kb = 0; kb < KB; kb += 2) {
+        loadA(a1, rt, kc(kb + 1));
+        if constexpr (kDoubleB) loadB(b1, kc(kb + 1));
+        else loadB(b0, kb);
         mma_all(a0, b0);
-        if (kb + 2 < KB) {
-          loadA(a0, rt, kb + 2);
-          loadB(b0, kb + 2);
+        loadA(a0, rt, kc(kb + 2));
+        if constexpr (kDoubleB) {
+          loadB(b0, kc(kb + 2));
+          if (kb + 1 < KB) mma_all(a1, b1);
+        } else {
+          loadB(b0, kc(kb + 1));
+          if (kb + 1 < KB) mma_all(a1, b0);
         }
-        mma_all(a1, b1);
       }
-      if (kb < KB) mma_all(a0, b0);
-    } else {
-      for (; kb + 1 < KB; kb += 2) {
-        loadA(a1, rt, kb + 1);
-        loadB(b0, kb);
-        mma_all(a0, b0);
-        if (kb + 2 < KB) loadA(a0, rt, kb + 2);
-        loadB(b0, kb + 1);
-        mma_all(a1, b0);
-      }
-      if (kb < KB) {
-        loadB(b0, kb);
-        mma_all(a0, b0);
-      }
-    }
     }
     (void)b1;
 
@@ -580,10 +561,11 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
         tcur[i][r] = kCls ? (lab ? Acc(kLog2e) : Acc(-kLog2e)) : tv[i][r];
         cmask[i][r] = valid ? (lab ? kMissIfLabel1 : kMissIfLabel0) : 0;
       }
-    if (rt + 1 < rt_end) {
-      load_t(rt + 1);
-      loadA(a0, rt + 1, 0);
-      if (kDepth == 2 && KB > 1) loadA(a1, rt + 1, 1);
+    {  // next row tile (the last tile reloads itself, unused)
+      const int64_t rn = rt + 1 < rt_end ? rt + 1 : rt;
+      load_t(rn);
+      loadA(a0, rn, 0);
+      if (kDepth == 2) loadA(a1, rn, kc(1));
     }
 
     // epilogue: element r of block (i, j) is pattern nw0 + 16 i + row_in_block(r),

@@ -308,6 +308,19 @@ class Game:
             d["best_genes"] = np.frombuffer(genes, dtype=np.float32).copy()
         return d
 
+    def save(self) -> bytes:
+        """Checkpoint (game_save) as bytes."""
+        n = C.c_size_t()
+        L.check(L.lib().game_save(self._ctx, None, C.byref(n)), "game_save")
+        buf = (C.c_ubyte * n.value)()
+        L.check(L.lib().game_save(self._ctx, buf, C.byref(n)), "game_save")
+        return bytes(buf)
+
+    def load(self, blob: bytes):
+        """Resume from a checkpoint taken with the same configuration (game_load)."""
+        buf = (C.c_ubyte * len(blob)).from_buffer_copy(blob)
+        L.check(L.lib().game_load(self._ctx, buf, len(blob)), "game_load")
+
     def time_fitness(self, reps: int = 20) -> float:
         """Mean duration (ms) of one fitness-kernel launch over the population."""
         ms = C.c_float()

@@ -164,3 +164,9 @@ def test_batch_validation_without_launching():
 def _query_ws(cfg):
     need = C.c_size_t()
     return L.lib().game_workspace_size(C.byref(cfg.to_c()), C.byref(need)), need.value
+
+
+def test_checkpoint_arguments_without_a_context():
+    n = C.c_size_t()
+    assert L.lib().game_save(None, None, C.byref(n)) == L.GAME_E_INVALID
+    assert L.lib().game_load(None, None, 0) == L.GAME_E_INVALID
