@@ -74,11 +74,15 @@ def measured_traffic(per_launch_bytes_hint=None):
     return float(m_b.group(1))
 
 
-def cpu_baseline(meta, X, t, dtype, seconds: float):
+def cpu_baseline(meta, X, t, dtype, seconds: float, threads_limit=None):
     """The float64 oracle timed on the host cores over whole generations
-    (evaluate every chromosome on every pattern, then one GA step)."""
+    (evaluate every chromosome on every pattern, then one GA step); with
+    threads_limit, BLAS limited to that many threads."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
+    if threads_limit is not None:
+        with threadpool_limits(limits=threads_limit):
+            return cpu_baseline(meta, X, t, dtype, seconds)
     from oracle import ga, model
     Xo = X.astype(np.float32).astype(np.float64)
     Phi = model.design_matrix(Xo, meta["basis"], meta["D"])   # once, like the device
@@ -168,33 +172,52 @@ def surrogate_compare(args):
         g.close()
         return r, el, log
 
-    r, el, _ = timed_run(Config(**base, max_generations=args.generations))
-    target = r["best_mse"]
-    G = r["generations"]
-    exact = n_off * G
-    out["plain"] = {"generations": G, "seconds": el, "best_mse": target,
-                    "generations_per_s": G / el, "exact_evals": exact,
-                    "evals_per_s": float(exact) * meta["N"] / el}
-    print(f"[bench] plain: {out['plain']}", file=sys.stderr, flush=True)
-    for mode in ("mlp", "random"):
-        cfg = Config(**base, surrogate=mode, prescreen_frac=0.25, audit=256, surrogate_hidden=256,
-                     surrogate_buffer=50000, surrogate_batch=1024, mse_threshold=target,
-                     max_generations=4 * args.generations)
-        r, el, log = timed_run(cfg)
+    def one_seed(seed):
+        res = {"ga_seed": seed}
+        b = {**base, "seed": seed}
+        r, el, _ = timed_run(Config(**b, max_generations=args.generations))
+        target = r["best_mse"]
         G = r["generations"]
-        per_gen = 2048 + (256 if mode == "mlp" else 0)
-        rec = {"generations": G, "seconds": el, "reached": r["stop_reason"] == "threshold",
-               "best_mse": r["best_mse"], "generations_per_s": G / el,
-               "exact_evals": per_gen * G, "screened_per_s": n_off * G / el,
-               "evals_per_s": float(per_gen * G) * meta["N"] / el,
-               "speedup_vs_plain": out["plain"]["seconds"] / el}
-        if log is not None and len(log):
-            rec["spearman_audit_mean"] = float(np.mean(log[:, 0]))
-            rec["spearman_audit_last10"] = float(np.mean(log[-10:, 0]))
-            rec["spearman_selected_mean"] = float(np.mean(log[:, 1]))
-            rec["train_loss_last"] = float(log[-1, 2])
-        out[mode] = rec
-        print(f"[bench] {mode}: {rec}", file=sys.stderr, flush=True)
+        exact = n_off * G
+        res["plain"] = {"generations": G, "seconds": el, "best_mse": target,
+                        "generations_per_s": G / el, "exact_evals": exact,
+                        "evals_per_s": float(exact) * meta["N"] / el}
+        print(f"[bench] seed {seed} plain: {res['plain']}", file=sys.stderr, flush=True)
+        for mode in ("mlp", "random"):
+            cfg = Config(**b, surrogate=mode, prescreen_frac=0.25, audit=256, surrogate_hidden=256,
+                         surrogate_buffer=50000, surrogate_batch=1024, mse_threshold=target,
+                         max_generations=4 * args.generations)
+            r, el, log = timed_run(cfg)
+            G = r["generations"]
+            per_gen = 2048 + (256 if mode == "mlp" else 0)
+            rec = {"generations": G, "seconds": el, "reached": r["stop_reason"] == "threshold",
+                   "best_mse": r["best_mse"], "generations_per_s": G / el,
+                   "exact_evals": per_gen * G, "screened_per_s": n_off * G / el,
+                   "evals_per_s": float(per_gen * G) * meta["N"] / el,
+                   "speedup_vs_plain": res["plain"]["seconds"] / el}
+            if log is not None and len(log):
+                rec["spearman_audit_mean"] = float(np.mean(log[:, 0]))
+                rec["spearman_audit_last10"] = float(np.mean(log[-10:, 0]))
+                rec["spearman_selected_mean"] = float(np.mean(log[:, 1]))
+                rec["train_loss_last"] = float(log[-1, 2])
+            res[mode] = rec
+            print(f"[bench] seed {seed} {mode}: {rec}", file=sys.stderr, flush=True)
+        return res
+
+    out["runs"] = [one_seed(meta["ga_seed"] + k) for k in range(args.seeds)]
+    summ = {}
+    for mode in ("mlp", "random"):
+        rr = [x[mode] for x in out["runs"]]
+        summ[mode] = {
+            "reached": sum(1 for x in rr if x["reached"]),
+            "seconds_mean": float(np.mean([x["seconds"] for x in rr])),
+            "generations_mean": float(np.mean([x["generations"] for x in rr])),
+            "speedup_vs_plain_geomean": float(np.exp(np.mean([np.log(x["speedup_vs_plain"])
+                                                              for x in rr])))}
+    summ["plain_seconds_mean"] = float(np.mean([x["plain"]["seconds"] for x in out["runs"]]))
+    summ["mlp_vs_random_time_geomean"] = float(np.exp(np.mean(
+        [np.log(x["random"]["seconds"] / x["mlp"]["seconds"]) for x in out["runs"]])))
+    out["summary"] = summ
     return out
 
 
@@ -290,6 +313,7 @@ def main():
                     help="surrogate form: MLP and random 25 %% prescreens vs exact evaluation of "
                          "all 8192 offspring, generations and time to the plain run's final MSE")
     ap.add_argument("--generations", type=int, default=100)
+    ap.add_argument("--seeds", type=int, default=1, help="surrogate form: GA seeds to compare over")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -390,6 +414,9 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(meta, X, t, args.dtype, args.cpu_seconds)
+        # the same oracle on one core (the paper's serial CPU comparison point)
+        out["cpu_baseline_one_core"] = cpu_baseline(meta, X, t, args.dtype, args.cpu_seconds / 3,
+                                                    threads_limit=1)
     g.close()
     print(json.dumps(out), flush=True)
 

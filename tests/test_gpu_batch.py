@@ -131,3 +131,45 @@ def test_batch_fixed_tiles_and_bf16():
     compare_with_alone(b, runs, results)
     assert b.time_fitness(reps=3) > 0.0
     b.close()
+
+
+def test_full_batched_workload_sampled():
+    """The 64-run batched workload at full size, one generation: for sampled
+    runs the tracked best chromosome's MSE matches the float64 oracle, and no
+    sampled chromosome of that population beats it."""
+    torch = require_gpu()
+    from oracle import model
+    from paper_1211_5481_amd import Batch, Config
+    specs = synth.batched_workload(64, synth.data_seed(4))
+    runs, data = [], []
+    for sp in specs:
+        if sp["task"] == "classification":
+            X, t = synth.classification_dataset(sp["n"], sp["f"], seed=sp["data_seed"])
+        else:
+            X, t, _ = synth.regression_dataset(sp["n"], sp["f"], 3, 0.05, seed=sp["data_seed"])
+        cfg = Config(n_patterns=sp["n"], n_features=sp["f"], degree=sp["degree"], basis=sp["basis"],
+                     task=sp["task"], dtype="f32", pop_size=sp["pop"], max_generations=1,
+                     seed=synth.ga_seed(4) + sp["run"])
+        runs.append((cfg, dev(X, torch.float32), dev(t, torch.float32)))
+        data.append((X, t))
+    announce("full batched workload, one generation")
+    b = Batch(runs)
+    results = b.run()
+    cost = [sp["n"] * sp["f"] * sp["degree"] for sp in specs]
+    order = np.argsort(cost)
+    sample = [int(order[0]), int(order[1]), int(order[len(order) // 2]), int(order[-1])]
+    rng = np.random.default_rng(0)
+    for i in sample:
+        sp, (X, t) = specs[i], data[i]
+        Xo = X.astype(np.float32).astype(np.float64)
+        to = t.astype(np.float32).astype(np.float64)
+        Phi = model.design_matrix(Xo, sp["basis"], sp["degree"])
+        best = results[i]["best_genes"].astype(np.float64)[None, :]
+        ref = model.evaluate(Xo, to, best, sp["basis"], sp["degree"], sp["task"], Phi=Phi)["mse"][0]
+        assert abs(results[i]["best_mse"] - ref) <= 1e-5 * ref, f"run {i}"
+        pop = host(b.context(i).population)
+        rows = rng.choice(pop.shape[0], 16, replace=False)
+        mse = model.evaluate(Xo, to, pop[rows].astype(np.float64), sp["basis"], sp["degree"],
+                             sp["task"], Phi=Phi)["mse"]
+        assert mse.min() >= ref * (1 - 2e-5), f"run {i}"
+    b.close()

@@ -306,3 +306,18 @@ def test_learned_prescreen_beats_random():
     assert ra["best_mse"] < rb["best_mse"]
     a.close()
     b.close()
+
+
+def test_advance_equals_steps_in_offspring_form():
+    announce("offspring advance (graph) vs eager steps")
+    kw = dict(P=32, n_off=160, frac=0.5, steps=1, audit=8, batch=32, H=16, seed=99)
+    a, _ = make("mlp", **kw)
+    b, _ = make("mlp", **kw)
+    a.advance(11)          # one chunk of 8 and three single generations
+    for _ in range(11):
+        b.step()
+    assert np.array_equal(bits(host(a.population)), bits(host(b.population)))
+    assert np.array_equal(bits(host(a.mlp_params())), bits(host(b.mlp_params())))
+    assert a.state() == b.state()
+    a.close()
+    b.close()
