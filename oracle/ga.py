@@ -1,11 +1,16 @@
 """Genetic operators of GAME -- oracle side, test infrastructure only.
 
 The paper lists the operators (Sec. 3: crossover, mutation, roulette/ranking
-selection, elitism; genes drawn at random in [-1, +1] and kept there) and the
-settings of its experiment (Sec. 5: crossover rate 0.9, 2 elite chromosomes per
-generation).  The operator variants used here are tournament selection,
-one-point crossover producing two complementary children and per-gene
-Gaussian mutation with clamping to [-1, 1].
+selection, elitism; genes drawn at random in [-1, +1] and kept there), says
+that randomly generated chromosomes replace older individuals during the
+evolution (Sec. 4), and gives the settings of its experiment (Sec. 5:
+ranking and roulette selection, crossover rate 0.9, mutation rate 0.2, 2
+elite chromosomes per generation, MSE threshold 0.001).  The operator
+variants used here: selection by tournament, by fitness-proportionate
+roulette, or by rank-based roulette (linear ranking weights); one-point
+crossover producing two complementary children; per-gene Gaussian mutation
+with clamping to [-1, 1]; optionally the last n_imm children of a generation
+replaced by random immigrants.
 
 Every random decision is a pure function of a Philox4x32-10 block
 (``oracle.philox``) addressed by a counter (a, b, generation, tag) under the
@@ -19,6 +24,8 @@ reproduces each decision bit for bit.  Counter addressing:
   mutation  child c, gene l:        (c, l, g, MUT) word 0 (decision); Gaussian
             from (c,l,g,MUT) words 1..3, (c,l,g,MUT1) words 0..3,
             (c,l,g,MUT2) words 0..3, (c,l,g,MUT3) word 0
+  roulette  pair j, parent s:       (j, s, g, ROULETTE) words 0, 1 -> a 64-bit draw
+  immigrant child c, gene l:        (c, l, g, IMMIGRANT) word 0, as at init
 
 Arithmetic is exact integer arithmetic except the mutation update, which is
 done in IEEE float32 one operation at a time (numpy float32 scalars), exactly
@@ -38,6 +45,10 @@ TAG_MUT = 3
 TAG_MUT1 = 4
 TAG_MUT2 = 5
 TAG_MUT3 = 6
+TAG_ROULETTE = 11
+TAG_IMMIGRANT = 12
+
+SEL_TOURNAMENT, SEL_ROULETTE, SEL_RANKING = 0, 1, 2
 
 TWO32 = 1 << 32
 
@@ -92,6 +103,84 @@ def tournament(fit, j: int, s: int, g: int, k: int, seed: int) -> int:
         if winner is None or better(fit, cand, winner):
             winner = cand
     return winner
+
+
+def roulette_weights(fit) -> list:
+    """Integer weights of fitness-proportionate selection, shifted so the worst
+    chromosome weighs 0: w_i = floor((f_i - f_min) / (f_max - f_min) * 2^32)
+    (float64 arithmetic); NaN fitness weighs 0; when every finite fitness is
+    equal each finite one weighs 1 (all NaN: every chromosome weighs 1)."""
+    f = [float(x) for x in fit]
+    fin = [x for x in f if not math.isnan(x)]
+    if not fin:
+        return [1] * len(f)
+    lo, hi = min(fin), max(fin)
+    if not hi > lo:
+        return [0 if math.isnan(x) else 1 for x in f]
+    span = hi - lo
+    return [0 if math.isnan(x) else int(math.floor((x - lo) / span * 4294967296.0)) for x in f]
+
+
+def cumulative(weights) -> list:
+    out, acc = [], 0
+    for w in weights:
+        acc += int(w)
+        out.append(acc)
+    return out
+
+
+def wide_draw(j: int, s: int, g: int, seed: int) -> int:
+    """64-bit uniform draw of parent s of pair j: words 0 (low) and 1 (high)."""
+    blk = philox4x32_10(j, s, g, TAG_ROULETTE, seed)
+    return (int(blk[1]) << 32) | int(blk[0])
+
+
+def pick_cumulative(cdf, r: int) -> int:
+    """Smallest k with cdf[k] > t, t = floor(r * total / 2^64)."""
+    t = (r * int(cdf[-1])) >> 64
+    lo, hi = 0, len(cdf) - 1
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if cdf[mid] > t:
+            hi = mid
+        else:
+            lo = mid + 1
+    return lo
+
+
+def rank_cdf(q: int, P: int) -> int:
+    """Cumulative linear-ranking weight of ranks 0..q (rank 0 = best weighs P)."""
+    return (q + 1) * P - q * (q + 1) // 2
+
+
+def roulette(cdf, j: int, s: int, g: int, seed: int) -> int:
+    return pick_cumulative(cdf, wide_draw(j, s, g, seed))
+
+
+def pick_rank(P: int, r: int) -> int:
+    """Rank q (0 = best) of a linear-ranking draw: smallest q with
+    rank_cdf(q) > floor(r * P(P+1)/2 / 2^64)."""
+    t = (r * (P * (P + 1) // 2)) >> 64
+    lo, hi = 0, P - 1
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if rank_cdf(mid, P) > t:
+            hi = mid
+        else:
+            lo = mid + 1
+    return lo
+
+
+def ranking(order, j: int, s: int, g: int, seed: int) -> int:
+    """Rank-based roulette: rank q (0 = best) is drawn with weight P - q."""
+    return order[pick_rank(len(order), wide_draw(j, s, g, seed))]
+
+
+def immigrant(c: int, L: int, g: int, seed: int) -> np.ndarray:
+    """Random chromosome for child c of generation g, drawn like the initial genes."""
+    l = np.arange(L, dtype=np.uint64)
+    w0, _, _, _ = philox4x32_10(c, l, g, TAG_IMMIGRANT, seed)
+    return ((w0 >> np.uint32(8)).astype(np.float64) * 2.0 ** -23 - 1.0).astype(np.float32)
 
 
 def gaussian_ih12(words) -> np.float32:
@@ -157,8 +246,10 @@ def mutate(children: np.ndarray, g: int, seed: int, p_mutation: float,
 
 def make_offspring(pop, fit, g: int, n_children: int, seed: int, k: int = 3,
                    p_crossover: float = 0.9, p_mutation: float = 0.05,
-                   sigma: float = 0.1) -> np.ndarray:
-    """n_children children from tournament pairs, crossover, then mutation.
+                   sigma: float = 0.1, selection: int = SEL_TOURNAMENT,
+                   n_immigrants: int = 0) -> np.ndarray:
+    """n_children children from selected pairs, crossover, then mutation; the
+    last n_immigrants children are random immigrants instead.
 
     Pair j yields child ordinals 2j and 2j+1; an odd count drops the last one.
     """
@@ -166,11 +257,23 @@ def make_offspring(pop, fit, g: int, n_children: int, seed: int, k: int = 3,
     P, L = pop.shape
     if not 1 <= k <= 16:
         raise ValueError("tournament size must be in [1, 16]")
+    if not 0 <= n_immigrants <= n_children:
+        raise ValueError("n_immigrants out of range")
     thr_c = prob_threshold(p_crossover)
+    if selection == SEL_ROULETTE:
+        cdf = cumulative(roulette_weights(fit))
+        pick = lambda j, s: roulette(cdf, j, s, g, seed)
+    elif selection == SEL_RANKING:
+        order = rank_order(fit)
+        pick = lambda j, s: ranking(order, j, s, g, seed)
+    elif selection == SEL_TOURNAMENT:
+        pick = lambda j, s: tournament(fit, j, s, g, k, seed)
+    else:
+        raise ValueError("unknown selection")
     out = np.empty((n_children, L), dtype=np.float32)
     for j in range((n_children + 1) // 2):
-        a = tournament(fit, j, 0, g, k, seed)
-        b = tournament(fit, j, 1, g, k, seed)
+        a = pick(j, 0)
+        b = pick(j, 1)
         blk = philox4x32_10(j, 8, g, TAG_SEL, seed)
         ca, cb = pop[a].copy(), pop[b].copy()
         if int(blk[0]) < thr_c and L >= 2:
@@ -180,7 +283,10 @@ def make_offspring(pop, fit, g: int, n_children: int, seed: int, k: int = 3,
         out[2 * j] = ca
         if 2 * j + 1 < n_children:
             out[2 * j + 1] = cb
-    return mutate(out, g, seed, p_mutation, sigma)
+    out = mutate(out, g, seed, p_mutation, sigma)
+    for c in range(n_children - n_immigrants, n_children):
+        out[c] = immigrant(c, L, g, seed)
+    return out
 
 
 def ga_step(pop, fit, g: int, seed: int, elitism: int = 2, **kw) -> np.ndarray:

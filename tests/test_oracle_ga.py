@@ -1,5 +1,6 @@
 """Pins of the oracle's genetic operators: closed-form distributions, exact
 enumeration and invariants that any correct implementation must satisfy."""
+import collections
 import math
 
 import numpy as np
@@ -162,3 +163,95 @@ def test_best_fitness_never_decreases_with_elitism():
         assert fit.max() >= best
         best = fit.max()
         pop = ga.ga_step(pop, fit, g, seed=5, elitism=2)
+
+
+# ---------------------------------------------------------------- roulette / ranking / immigrants
+def test_roulette_weights_definition_and_edge_cases():
+    f = [0.5, 0.2, float("nan"), 0.9]
+    w = ga.roulette_weights(f)
+    assert w[1] == 0 and w[2] == 0 and w[3] == 2 ** 32
+    assert w[0] == int(np.floor((0.5 - 0.2) / (0.9 - 0.2) * 2.0 ** 32))
+    assert ga.roulette_weights([0.3, 0.3, float("nan")]) == [1, 1, 0]
+    assert ga.roulette_weights([float("nan")] * 3) == [1, 1, 1]
+
+
+def test_pick_cumulative_against_linear_scan():
+    rng = np.random.default_rng(0)
+    cdf = ga.cumulative([3, 0, 5, 1, 0, 7])
+    for _ in range(2000):
+        r = int(rng.integers(0, 2 ** 63)) * 2 + int(rng.integers(0, 2))
+        t = (r * cdf[-1]) >> 64
+        want = next(k for k, c in enumerate(cdf) if c > t)
+        assert ga.pick_cumulative(cdf, r) == want
+    # every target value of a small wheel: zero-weight slots are never chosen
+    for t in range(cdf[-1]):
+        r = -(-(t << 64) // cdf[-1])  # smallest r with floor(r * T / 2^64) == t
+        k = ga.pick_cumulative(cdf, r)
+        assert cdf[k] > t and (k == 0 or cdf[k - 1] <= t)
+        assert [3, 0, 5, 1, 0, 7][k] > 0
+
+
+def test_rank_cdf_closed_form_and_inversion():
+    for P in (1, 2, 5, 17):
+        w = [P - q for q in range(P)]
+        cum = np.cumsum(w)
+        assert [ga.rank_cdf(q, P) for q in range(P)] == cum.tolist()
+    # exhaustive inversion at P = 5: every target value, through pick_rank
+    P = 5
+    T = P * (P + 1) // 2
+    seen = collections.Counter()
+    for t in range(T):
+        r = -(-(t << 64) // T)  # smallest 64-bit draw whose target is t
+        q = ga.pick_rank(P, r)
+        assert q == next(q for q in range(P) if sum(P - x for x in range(q + 1)) > t)
+        seen[q] += 1
+    assert [seen[q] for q in range(P)] == [5, 4, 3, 2, 1]
+
+
+def test_roulette_and_ranking_frequencies_chi2():
+    P, g, seed, n = 12, 3, 777, 6000
+    fit = np.linspace(0.1, 0.9, P)[::-1].copy()  # chromosome 0 best
+    fit[7] = np.nan
+    w = np.array(ga.roulette_weights(fit), dtype=np.float64)
+    cdf = ga.cumulative(w)
+    counts = np.zeros(P)
+    for j in range(n // 2):
+        for s in (0, 1):
+            counts[ga.roulette(cdf, j, s, g, seed)] += 1
+    assert counts[7] == 0 and counts[int(np.nanargmin(fit))] == 0
+    exp = w / w.sum() * n
+    m = exp > 0
+    assert stats.chisquare(counts[m], exp[m]).pvalue > 1e-3
+    order = ga.rank_order(fit)
+    rc = np.zeros(P)
+    for j in range(n // 2):
+        for s in (0, 1):
+            rc[order.index(ga.ranking(order, j, s, g, seed))] += 1
+    expr = np.array([P - q for q in range(P)], dtype=np.float64)
+    expr = expr / expr.sum() * n
+    assert stats.chisquare(rc, expr).pvalue > 1e-3
+
+
+def test_immigrants_replace_the_last_children():
+    pop = synth.random_population(20, 9, seed=4)
+    fit = synth.random_fitness(20, seed=5)
+    for sel in (ga.SEL_TOURNAMENT, ga.SEL_ROULETTE, ga.SEL_RANKING):
+        base = ga.make_offspring(pop, fit, 6, 11, 99, selection=sel)
+        imm = ga.make_offspring(pop, fit, 6, 11, 99, selection=sel, n_immigrants=3)
+        np.testing.assert_array_equal(base[:8], imm[:8])
+        for c in range(8, 11):
+            np.testing.assert_array_equal(imm[c], ga.immigrant(c, 9, 6, 99))
+        assert np.all(imm >= -1.0) and np.all(imm < 1.0)
+        grid = (imm[8:].astype(np.float64) + 1.0) * 2.0 ** 23
+        assert np.all(grid == np.floor(grid))
+
+
+def test_paper_selection_modes_keep_population_invariants():
+    pop = synth.random_population(30, 12, seed=6)
+    fit = synth.random_fitness(30, seed=7, n_ties=5, n_nan=2)
+    for sel in (ga.SEL_ROULETTE, ga.SEL_RANKING):
+        new = ga.ga_step(pop, fit, 2, 5, elitism=2, selection=sel, p_mutation=0.2, n_immigrants=4)
+        assert new.shape == pop.shape
+        e = ga.elites(fit, 2)
+        np.testing.assert_array_equal(new[:2], pop[e])
+        assert np.all(np.abs(new) <= 1.0)
