@@ -72,7 +72,16 @@ typedef enum { GAME_REGRESSION = 0, GAME_CLASSIFICATION = 1 } game_task;
  * Phi and genes rounded (nearest even) to 16 bits, FP32 accumulation. */
 typedef enum { GAME_F64 = 0, GAME_F32 = 1, GAME_BF16 = 2, GAME_F16 = 3 } game_dtype;
 
-typedef enum { GAME_SEL_TOURNAMENT = 0 } game_selection;
+/*
+ * Parent selection (Sec. 3 lists roulette and ranking; the experiments of
+ * Sec. 5 use them):
+ *   TOURNAMENT: best of tournament_k uniform draws (with replacement);
+ *   ROULETTE:   fitness-proportionate wheel with weights
+ *               floor((f - f_min) / (f_max - f_min) * 2^32) (NaN weighs 0);
+ *   RANKING:    rank-based wheel, rank q (0 = best) weighs P - q (P <= 8192).
+ * Wheel draws are 64-bit Philox draws scaled to the wheel's integer total.
+ */
+typedef enum { GAME_SEL_TOURNAMENT = 0, GAME_SEL_ROULETTE = 1, GAME_SEL_RANKING = 2 } game_selection;
 
 /* Prescreen of the offspring form.  NONE: every child is evaluated exactly.
  * MLP: a 2-hidden-layer GELU perceptron trained online (Adam) on the
@@ -105,6 +114,10 @@ typedef struct {
   int32_t  elitism;         /* E in [0, min(P, 64)] (the paper's runs use 2)      */
   int32_t  selection;       /* game_selection                                     */
   int32_t  tournament_k;    /* k in [1, 16]                                       */
+  int32_t  n_immigrants;    /* the last n_immigrants children of each generation  */
+                            /* are random chromosomes instead (the paper's random */
+                            /* chromosomes that replace older individuals, Sec. 4)*/
+  int32_t  reserved;        /* must be 0                                          */
   int32_t  max_generations; /* >= 1, used by game_run                             */
   int32_t  rescore_top;     /* 0..8: every generation re-scores the top-k ranked   */
                             /* chromosomes in float32 and tracks the best and     */

@@ -16,6 +16,7 @@ TASK = {"regression": 0, "classification": 1}
 DTYPE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 STOP = {0: "none", 1: "threshold", 2: "max_generations"}
 SURROGATE = {"none": 0, "mlp": 1, "random": 2}
+SELECTION = {"tournament": 0, "roulette": 1, "ranking": 2}
 
 
 class GameConfig(C.Structure):
@@ -33,6 +34,8 @@ class GameConfig(C.Structure):
         ("elitism", C.c_int32),
         ("selection", C.c_int32),
         ("tournament_k", C.c_int32),
+        ("n_immigrants", C.c_int32),
+        ("reserved", C.c_int32),
         ("max_generations", C.c_int32),
         ("rescore_top", C.c_int32),
         ("tile_p", C.c_int32),

@@ -52,6 +52,7 @@ struct game_ctx {
   float* xf;      // float32 patterns (16-bit and float32 forms)
   double* rpart;  // re-score partials
   int* elite;
+  uint64_t* wheel;  // selection wheel or ranking of the current population
   DevState* state;
   uint64_t thr_c, thr_m;
   bool poisoned = false;
@@ -86,7 +87,8 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   if (c->n_patterns > (int64_t(1) << 40)) return bad("n_patterns too large");
   if (c->n_features < 1 || c->degree < 1) return bad("n_features and degree must be >= 1");
   if (c->bias != 0 && c->bias != 1) return bad("bias must be 0 or 1");
-  if (c->selection != GAME_SEL_TOURNAMENT) return bad("only tournament selection is available");
+  if (c->selection < GAME_SEL_TOURNAMENT || c->selection > GAME_SEL_RANKING) return bad("unknown selection");
+  if (c->reserved != 0) return bad("reserved must be 0");
   if (c->tournament_k < 1 || c->tournament_k > kMaxTournament) return bad("tournament_k must be in [1, 16]");
   auto prob_ok = [](double v) { return std::isfinite(v) && v >= 0.0 && v <= 1.0; };
   if (!prob_ok(c->p_crossover) || !prob_ok(c->p_mutation)) return bad("probabilities must be in [0, 1]");
@@ -109,6 +111,8 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
     return GAME_E_UNSUPPORTED;
   }
   if (c->rescore_top > P) return bad("rescore_top must not exceed the population size");
+  if (c->selection == GAME_SEL_RANKING && P > 8192) return bad("ranking selection needs pop_size <= 8192");
+  if (c->n_immigrants < 0 || c->n_immigrants > n_off) return bad("n_immigrants must be in [0, n_offspring]");
   if (c->surrogate < GAME_SURROGATE_NONE || c->surrogate > GAME_SURROGATE_RANDOM) return bad("unknown surrogate mode");
   const bool offspring = c->surrogate != GAME_SURROGATE_NONE || n_off != P - c->elitism;
   p->offspring = offspring;
@@ -219,6 +223,7 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   const bool f32x = c->dtype != GAME_F64;
   p->off_x = take(f32x ? (size_t)p->N * c->n_features * 4 : 0);
   p->off_rpart = take(f32x ? (size_t)rescore_grid() * 2 * kMaxRescore * 8 : 0);
+  p->off_wheel = take((size_t)P * 8);
   if (offspring) {
     const size_t Lz = (size_t)L;
     const int evrows = std::max<int>((int)P, p->P_eval);
@@ -380,6 +385,22 @@ game_status enqueue_eval_population(game_ctx* c, double* mse, double* miscls, do
   return GAME_OK;
 }
 
+// Parent selection and immigrants of a breed (the wheel buffer holds the
+// cumulative roulette weights or the ranking, written by launch_select_prep).
+void set_selection(game_ctx* c, BreedArgs& a) {
+  a.sel = c->cfg.selection;
+  a.wheel = c->wheel;
+  a.order = reinterpret_cast<const int*>(c->wheel);
+  a.n_imm = c->cfg.n_immigrants;
+}
+
+game_status enqueue_select_prep(game_ctx* c, const double* fit, hipStream_t s) {
+  return dev(c,
+             launch_select_prep(c->cfg.selection, fit, c->plan.P, c->wheel,
+                                reinterpret_cast<int*>(c->wheel), c->state, s),
+             "selection");
+}
+
 // Breed arguments of the generational form: E elites and P - E children
 // written to the next population buffer and the gene tile.
 BreedArgs evolve_args(game_ctx* c, const double* fit) {
@@ -405,11 +426,13 @@ BreedArgs evolve_args(game_ctx* c, const double* fit) {
   a.M_pad = p.M_pad;
   a.bias = c->cfg.bias;
   a.counter = c->counters + p.n_pt_cap + 1;
+  set_selection(c, a);
   return a;
 }
 
 game_status enqueue_evolve(game_ctx* c, const double* fit, hipStream_t s) {
   const BreedArgs a = evolve_args(c, fit);
+  GAME_TRY(enqueue_select_prep(c, fit, s));
   GAME_TRY(dev(c, launch_breed(c->cfg.dtype, a, c->state, s), "breed"));
   c->tile_fresh = true;  // breed writes the new population into the tile
   return GAME_OK;
@@ -472,6 +495,8 @@ game_status enqueue_offspring_generation(game_ctx* c, hipStream_t s) {
   a.M_pad = p.M_pad;
   a.bias = c->cfg.bias;
   a.out = c->O;
+  set_selection(c, a);
+  GAME_TRY(enqueue_select_prep(c, c->fit, s));
   GAME_TRY(dev(c, launch_breed(c->cfg.dtype, a, st, s), "breed offspring"));
   // prescreen: which children are evaluated exactly
   const int* sel = nullptr;
@@ -540,8 +565,14 @@ game_status build_graph(game_ctx* c, int n_gen, hipGraph_t* graph, hipGraphExec_
   if (!c->cap) GAME_TRY(dev(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking), "stream create"));
   GAME_TRY(dev(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "begin capture"));
   game_status st = GAME_OK;
-  if (!c->plan.offspring) c->tile_fresh = true;  // callers pack the population before replay
+  // The captured generations never pack (the breed writes the next tile);
+  // callers pack the population before the first replay when the tile is
+  // stale, so the flag is restored after the capture.
+  // (The offspring form leaves the tile holding the evaluated children.)
+  const bool fresh = c->tile_fresh;
+  if (!c->plan.offspring) c->tile_fresh = true;
   for (int i = 0; i < n_gen && st == GAME_OK; ++i) st = enqueue_generation(c, c->cap);
+  c->tile_fresh = c->plan.offspring ? false : fresh;
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->cap, &g);
   if (st != GAME_OK) {
@@ -664,6 +695,7 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
   c->counters = reinterpret_cast<uint32_t*>(c->ws + p.off_cnt);
   c->xf = reinterpret_cast<float*>(c->ws + p.off_x);
   c->rpart = reinterpret_cast<double*>(c->ws + p.off_rpart);
+  c->wheel = reinterpret_cast<uint64_t*>(c->ws + p.off_wheel);
   if (p.offspring) {
     auto F = [&](size_t o) { return reinterpret_cast<float*>(c->ws + o); };
     auto D = [&](size_t o) { return reinterpret_cast<double*>(c->ws + o); };
@@ -717,6 +749,7 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
   if (r == GAME_OK) {  // prime per-kernel attributes outside any graph capture
     (void)fitness_geometry(p, cfg->task, cfg->dtype, p.P_max);
     if (p.offspring) r = dev(c, sur_prepare(), "prepare");
+    if (r == GAME_OK) r = dev(c, select_prepare(cfg->selection), "prepare");
   }
   if (r == GAME_OK && p.offspring) {
     r = dev(c, hipMemsetAsync(c->sst, 0, sizeof(SurState), st), "surrogate state");
@@ -1166,6 +1199,8 @@ game_status batch_layout(const game_config* cfgs, int n, BatchLayout* L, int* dt
     if (p.offspring || cfgs[i].rescore_top > 0)
       return fail(GAME_E_UNSUPPORTED, "run %d: the batched form runs the generational GA only", i);
     if (!p.lds) return fail(GAME_E_UNSUPPORTED, "run %d: too many genes for the LDS-staged kernel", i);
+    if (cfgs[i].selection != GAME_SEL_TOURNAMENT)
+      return fail(GAME_E_UNSUPPORTED, "run %d: the batched form selects by tournament", i);
     L->ws_off[i] = off;
     off = align256(off + p.total);
     G = std::max(G, cfgs[i].max_generations);

@@ -570,8 +570,9 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
 
     // epilogue: element r of block (i, j) is pattern nw0 + 16 i + row_in_block(r),
     // chromosome p0 + 16 j + lrow
-    auto epilogue = [&](auto full_tag) {
+    auto epilogue = [&](auto full_tag, auto bias_tag) {
       constexpr bool kFull = decltype(full_tag)::value;
+      constexpr bool kBias = decltype(bias_tag)::value;
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
         Acc loc = Acc(0);
@@ -580,7 +581,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
         for (int i = 0; i < WM; ++i)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const Acc z = acc[i][j][r] + bias_j[j];
+            const Acc z = kBias ? acc[i][j][r] + bias_j[j] : acc[i][j][r];
             Acc q;
             if constexpr (kCls) {
               q = sig_pos(tcur[i][r] * z);
@@ -595,10 +596,16 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
         miss[j] += ms;
       }
     };
-    if (full)
-      epilogue(std::integral_constant<bool, true>{});
-    else
-      epilogue(std::integral_constant<bool, false>{});
+    // without a bias gene the add is skipped (z is the accumulator itself)
+    using T_ = std::integral_constant<bool, true>;
+    using F_ = std::integral_constant<bool, false>;
+    if (biasv) {
+      if (full) epilogue(T_{}, T_{});
+      else epilogue(F_{}, T_{});
+    } else {
+      if (full) epilogue(T_{}, F_{});
+      else epilogue(F_{}, F_{});
+    }
   }
 
 #pragma unroll

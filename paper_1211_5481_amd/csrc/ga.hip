@@ -88,6 +88,41 @@ __device__ __forceinline__ int tournament(const BreedArgs& a, uint32_t j, uint32
   return win.idx;
 }
 
+// Parent s of pair j: a tournament, or a 64-bit draw r from block
+// (j, s, g, ROULETTE) (word 1 high, word 0 low) scaled to the wheel's integer
+// total, t = floor(r T / 2^64), and the first slot whose cumulative weight
+// exceeds t.  Rank wheel: rank q (0 = best) weighs P - q, so its cumulative
+// weight is (q + 1) P - q (q + 1) / 2 and T = P (P + 1) / 2.
+__device__ __forceinline__ int select_parent(const BreedArgs& a, uint32_t j, uint32_t s, uint32_t g) {
+  if (a.sel == GAME_SEL_TOURNAMENT) return tournament(a, j, s, g);
+  const u32x4 b = philox(j, s, g, kTagRoulette, a.k0, a.k1);
+  const uint64_t r = ((uint64_t)b.y << 32) | (uint64_t)b.x;
+  int lo = 0, hi = a.P - 1;
+  if (a.sel == GAME_SEL_ROULETTE) {
+    const uint64_t t = __umul64hi(r, a.wheel[a.P - 1]);
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (a.wheel[mid] > t) hi = mid;
+      else lo = mid + 1;
+    }
+    return lo;
+  }
+  const uint64_t P = (uint64_t)a.P;
+  const uint64_t t = __umul64hi(r, P * (P + 1) / 2);
+  while (lo < hi) {
+    const uint64_t mid = (uint64_t)((lo + hi) >> 1);
+    if ((mid + 1) * P - mid * (mid + 1) / 2 > t) hi = (int)mid;
+    else lo = (int)mid + 1;
+  }
+  return a.order[lo];
+}
+
+// Random immigrant gene: as at init, from block (c, l, g, IMMIGRANT) word 0.
+__device__ __forceinline__ float immigrant_gene(uint32_t c, uint32_t l, uint32_t g, const BreedArgs& a) {
+  const uint32_t w = philox(c, l, g, kTagImmigrant, a.k0, a.k1).x;
+  return (float)(w >> 8) * 0x1p-23f - 1.0f;
+}
+
 __device__ __forceinline__ float mutate_gene(float gene, uint32_t c, uint32_t l, uint32_t g,
                                              const BreedArgs& a) {
   const u32x4 b0 = philox(c, l, g, kTagMut, a.k0, a.k1);
@@ -134,8 +169,8 @@ __device__ __forceinline__ void breed_block(const BreedArgs& a, DevState* st, in
     for (int l = lane; l < a.L; l += 64) put_gene<O, B>(a, dst, wave, l, row[l]);
   } else if (2 * (wave - a.E) < a.n_children) {
     const int j = wave - a.E;
-    const int pa = tournament(a, (uint32_t)j, 0u, g);
-    const int pb = tournament(a, (uint32_t)j, 1u, g);
+    const int pa = select_parent(a, (uint32_t)j, 0u, g);
+    const int pb = select_parent(a, (uint32_t)j, 1u, g);
     const u32x4 xb = philox((uint32_t)j, 8u, g, kTagSel, a.k0, a.k1);
     int cut = a.L;  // no crossover: child0 = a, child1 = b
     if ((uint64_t)xb.x < a.thr_c && a.L >= 2) cut = 1 + (int)__umulhi(xb.y, (uint32_t)(a.L - 1));
@@ -143,12 +178,18 @@ __device__ __forceinline__ void breed_block(const BreedArgs& a, DevState* st, in
     const float* rb = src + (int64_t)pb * a.L;
     const uint32_t c0 = 2u * (uint32_t)j, c1 = c0 + 1u;
     const bool has1 = (int)c1 < a.n_children;
+    const int first_imm = a.n_children - a.n_imm;  // children from here on are immigrants
+    const bool imm0 = (int)c0 >= first_imm, imm1 = (int)c1 >= first_imm;
     for (int l = lane; l < a.L; l += 64) {
       const float ga = ra[l], gb = rb[l];
       const float x0 = l < cut ? ga : gb;
       const float x1 = l < cut ? gb : ga;
-      put_gene<O, B>(a, dst, a.E + (int)c0, l, mutate_gene(x0, c0, (uint32_t)l, g, a));
-      if (has1) put_gene<O, B>(a, dst, a.E + (int)c1, l, mutate_gene(x1, c1, (uint32_t)l, g, a));
+      const uint32_t ul = (uint32_t)l;
+      put_gene<O, B>(a, dst, a.E + (int)c0, l,
+                     imm0 ? immigrant_gene(c0, ul, g, a) : mutate_gene(x0, c0, ul, g, a));
+      if (has1)
+        put_gene<O, B>(a, dst, a.E + (int)c1, l,
+                       imm1 ? immigrant_gene(c1, ul, g, a) : mutate_gene(x1, c1, ul, g, a));
     }
   }
   // The last workgroup to arrive advances the generation.  The barrier waits
@@ -283,7 +324,111 @@ __global__ void run_arm_kernel(DevState* st, int max_generations, double thresho
 
 __global__ void run_disarm_kernel(DevState* st) { st->run_active = 0; }
 
+// Roulette wheel of fit[0..P): integer weights (see select_parent) and their
+// inclusive prefix sums, one workgroup.  Integer sums are exact, so the wheel
+// does not depend on the order of the additions.
+__global__ __launch_bounds__(1024) void wheel_kernel(const double* __restrict__ fit, int P,
+                                                     uint64_t* __restrict__ wheel, const DevState* st) {
+  if (run_halted(st)) return;
+  __shared__ double s_lo[16], s_hi[16];
+  __shared__ uint64_t s_scan[1024];
+  __shared__ uint64_t s_carry;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double mn = INFINITY, mx = -INFINITY;
+  for (int i = tid; i < P; i += 1024) {
+    const double f = fit[i];
+    if (!isnan(f)) {
+      mn = fmin(mn, f);
+      mx = fmax(mx, f);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, off));
+    mx = fmax(mx, __shfl_xor(mx, off));
+  }
+  if (lane == 0) {
+    s_lo[wave] = mn;
+    s_hi[wave] = mx;
+  }
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  double lo = s_lo[0], hi = s_hi[0];
+  for (int w = 1; w < 16; ++w) {
+    lo = fmin(lo, s_lo[w]);
+    hi = fmax(hi, s_hi[w]);
+  }
+  const bool any = lo <= hi;  // some finite fitness
+  const double span = hi - lo;
+  for (int base = 0; base < P; base += 1024) {
+    const int i = base + tid;
+    uint64_t w = 0;
+    if (i < P) {
+      const double f = fit[i];
+      if (!any) w = 1;
+      else if (isnan(f)) w = 0;
+      else if (!(hi > lo)) w = 1;
+      else w = (uint64_t)floor((f - lo) / span * 4294967296.0);
+    }
+    s_scan[tid] = w;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan (Hillis-Steele)
+      const uint64_t add = tid >= off ? s_scan[tid - off] : 0;
+      __syncthreads();
+      s_scan[tid] += add;
+      __syncthreads();
+    }
+    if (i < P) wheel[i] = s_carry + s_scan[tid];
+    __syncthreads();
+    if (tid == 0) s_carry += s_scan[1023];
+    __syncthreads();
+  }
+}
+
+// Full ranking of fit[0..P) (fitness descending, index ascending, NaN last)
+// by a bitonic sort in LDS, one workgroup; order[q] = chromosome of rank q.
+__global__ __launch_bounds__(1024) void rank_all_kernel(const double* __restrict__ fit, int P, int n_pow2,
+                                                        int* __restrict__ order, const DevState* st) {
+  if (run_halted(st)) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* sk = reinterpret_cast<uint64_t*>(smem);
+  int* si = reinterpret_cast<int*>(smem + (size_t)n_pow2 * 8);
+  for (int i = threadIdx.x; i < n_pow2; i += 1024) {
+    sk[i] = i < P ? ord_desc_f64(fit[i]) : ~0ull;
+    si[i] = i < P ? i : 0x7fffffff;
+  }
+  __syncthreads();
+  block_sort_pairs<1024>(sk, si, n_pow2);
+  for (int q = threadIdx.x; q < P; q += 1024) order[q] = si[q];
+}
+
 }  // namespace
+
+hipError_t select_prepare(int sel) {
+  static bool prepared = false;
+  if (sel != GAME_SEL_RANKING || prepared) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rank_all_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 98304);
+  if (e == hipSuccess) prepared = true;
+  return e;
+}
+
+hipError_t launch_select_prep(int sel, const double* fit, int P, uint64_t* wheel, int* order,
+                              const DevState* st, hipStream_t s) {
+  if (sel == GAME_SEL_ROULETTE) {
+    hipLaunchKernelGGL(wheel_kernel, dim3(1), dim3(1024), 0, s, fit, P, wheel, st);
+    return hipGetLastError();
+  }
+  if (sel == GAME_SEL_RANKING) {
+    const hipError_t e = select_prepare(sel);
+    if (e != hipSuccess) return e;
+    int n = 1;
+    while (n < P) n <<= 1;
+    if ((size_t)n * 12 > 98304) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(rank_all_kernel, dim3(1), dim3(1024), (size_t)n * 12, s, fit, P, n, order, st);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
 
 hipError_t launch_init_population(float* pop, int P, int L, uint64_t seed, hipStream_t s) {
   const int64_t n = (int64_t)P * L;

@@ -27,6 +27,8 @@ enum : uint32_t {
   kTagMinibatch = 8,
   kTagAudit = 9,
   kTagPrescreen = 10,
+  kTagRoulette = 11,
+  kTagImmigrant = 12,
 };
 
 // ------------------------------------------------- Philox4x32-10 (device)
@@ -121,6 +123,7 @@ struct Plan {
   size_t off_phi, off_t, off_tile, off_bias, off_pop0, off_pop1, off_psse, off_pmiss;
   size_t off_mse, off_miscls, off_fit, off_elite, off_state, off_best, off_cnt;
   size_t off_x, off_rpart;          // float32 patterns and re-score partials (16-bit forms)
+  size_t off_wheel;                 // selection wheel / ranking (P_max x 8 bytes)
   // offspring form (n_offspring != P - E, or a prescreen)
   bool offspring;
   int k_sel, audit, P_eval, sur, H, cap, steps, batch, n_recent, rows_max;
@@ -189,7 +192,17 @@ struct BreedArgs {
   int M, M_pad, bias;
   uint32_t* counter;  // zero between launches
   float* out;         // offspring form: children go here (no tile, no advance)
+  int sel;            // game_selection
+  const uint64_t* wheel;  // ROULETTE: cumulative integer weights (P)
+  const int* order;       // RANKING: chromosome of each rank (P)
+  int n_imm;          // the last n_imm children are random immigrants
 };
+// Per-generation input of the wheel selections: the cumulative roulette
+// weights (ROULETTE) or the full ranking (RANKING) of fit[0..P); no-op for
+// tournaments.
+hipError_t launch_select_prep(int sel, const double* fit, int P, uint64_t* wheel, int* order,
+                              const DevState* st, hipStream_t s);
+hipError_t select_prepare(int sel);  // once per selection kind, outside graph capture
 hipError_t launch_breed(int dtype, const BreedArgs& a, DevState* st, hipStream_t s);
 
 // Population copies in and out of pop[g & 1] (dir 0: out to dst, 1: in from src).

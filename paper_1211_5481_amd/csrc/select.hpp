@@ -22,6 +22,45 @@ __device__ __forceinline__ bool better(const Ranked& a, const Ranked& b) {
 }
 __device__ __forceinline__ double rank_key(double f) { return isnan(f) ? -INFINITY : f; }
 
+// Order-preserving maps to unsigned integers: ascending float; descending
+// double with NaN ranked like -inf (the order above).
+__device__ __forceinline__ uint64_t ord_f32(float f) {
+  if (isnan(f)) return 0xFFFFFFFFull;
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? (uint64_t)(~u) : (uint64_t)(u | 0x80000000u);
+}
+__device__ __forceinline__ uint64_t ord_desc_f64(double f) {
+  if (isnan(f)) f = -INFINITY;
+  const uint64_t u = (uint64_t)__double_as_longlong(f);
+  const uint64_t asc = (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+  return ~asc;
+}
+
+// Bitonic sort of n_pow2 (key, index) pairs in LDS by one workgroup of
+// kThreads threads (all of which call this), ascending by key then index.
+template <int kThreads>
+__device__ void block_sort_pairs(uint64_t* sk, int* si, int n_pow2) {
+  for (int size = 2; size <= n_pow2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < n_pow2 / 2; t += kThreads) {
+        const int lo = 2 * t - (t & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t ka = sk[lo], kb = sk[hi];
+        const int ia = si[lo], ib = si[hi];
+        const bool a_gt_b = ka > kb || (ka == kb && ia > ib);
+        if (a_gt_b == up) {
+          sk[lo] = kb;
+          sk[hi] = ka;
+          si[lo] = ib;
+          si[hi] = ia;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Loads and stores of values another workgroup of the same launch produces or
 // consumes: agent-scope atomics, which go through to the device-coherent
 // level instead of an XCD's L2 (no cache invalidation needed).

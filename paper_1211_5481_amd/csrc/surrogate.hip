@@ -25,20 +25,6 @@ namespace {
 
 constexpr int kSortThreads = 1024;
 
-// order-preserving maps to unsigned integers
-__device__ __forceinline__ uint64_t ord_f32(float f) {
-  if (isnan(f)) return 0xFFFFFFFFull;
-  const uint32_t u = __float_as_uint(f);
-  return (u & 0x80000000u) ? (uint64_t)(~u) : (uint64_t)(u | 0x80000000u);
-}
-// descending by value, NaN ranked like -inf (the GA's order)
-__device__ __forceinline__ uint64_t ord_desc_f64(double f) {
-  if (isnan(f)) f = -INFINITY;
-  const uint64_t u = (uint64_t)__double_as_longlong(f);
-  const uint64_t asc = (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
-  return ~asc;
-}
-
 // keys for the selections: 0 = float ascending (scores), 1 = random u32 word
 // of block (i, 0, g, tag), 2 = double descending (fitness)
 __global__ void keys_kernel(int mode, const float* __restrict__ fsrc, const double* __restrict__ dsrc,
@@ -69,25 +55,7 @@ __global__ __launch_bounds__(kSortThreads) void select_kernel(const uint64_t* __
     si[i] = i < n ? i : 0x7fffffff;
   }
   __syncthreads();
-  for (int size = 2; size <= n_pow2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int t = threadIdx.x; t < n_pow2 / 2; t += kSortThreads) {
-        const int lo = 2 * t - (t & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const uint64_t ka = sk[lo], kb = sk[hi];
-        const int ia = si[lo], ib = si[hi];
-        const bool a_gt_b = ka > kb || (ka == kb && ia > ib);
-        if (a_gt_b == up) {
-          sk[lo] = kb;
-          sk[hi] = ka;
-          si[lo] = ib;
-          si[hi] = ia;
-        }
-      }
-      __syncthreads();
-    }
-  }
+  block_sort_pairs<kSortThreads>(sk, si, n_pow2);
   for (int i = threadIdx.x; i < k; i += kSortThreads) out[i] = si[i];
 }
 
@@ -117,25 +85,7 @@ __global__ __launch_bounds__(kSortThreads) void spearman_kernel(const float* __r
       }
     }
     __syncthreads();
-    for (int size = 2; size <= n_pow2; size <<= 1) {
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        for (int t = threadIdx.x; t < n_pow2 / 2; t += kSortThreads) {
-          const int lo = 2 * t - (t & (stride - 1));
-          const int hi = lo + stride;
-          const bool up = (lo & size) == 0;
-          const uint64_t ka = sk[lo], kb = sk[hi];
-          const int ia = si[lo], ib = si[hi];
-          const bool a_gt_b = ka > kb || (ka == kb && ia > ib);
-          if (a_gt_b == up) {
-            sk[lo] = kb;
-            sk[hi] = ka;
-            si[lo] = ib;
-            si[hi] = ia;
-          }
-        }
-        __syncthreads();
-      }
-    }
+    block_sort_pairs<kSortThreads>(sk, si, n_pow2);
     float* r = side == 0 ? rx : ry;
     for (int q = threadIdx.x; q < n; q += kSortThreads) {
       int a = q, b = q;

@@ -29,6 +29,8 @@ class Config:
     n_offspring: int = 0
     elitism: int = 2
     tournament_k: int = 3
+    selection: str = "tournament"     # tournament | roulette | ranking
+    n_immigrants: int = 0
     max_generations: int = 100
     rescore_top: int = 0              # per-generation float32 re-score of the top-k
     tile_p: int = 0                   # fitness tile width: 0 (library's choice) | 32 | 64 | 128
@@ -61,7 +63,8 @@ class Config:
         c.pop_size = int(self.pop_size)
         c.n_offspring = int(self.n_offspring)
         c.elitism = int(self.elitism)
-        c.selection = 0
+        c.selection = L.SELECTION[self.selection]
+        c.n_immigrants = int(self.n_immigrants)
         c.tournament_k = int(self.tournament_k)
         c.max_generations = int(self.max_generations)
         c.rescore_top = int(self.rescore_top)

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_function():
 
 def test_struct_layouts_match_the_header():
     # sizes computed by the C compiler for the declared structs
-    assert C.sizeof(L.GameConfig) == 160
+    assert C.sizeof(L.GameConfig) == 168
     assert C.sizeof(L.GameDims) == 40
     assert C.sizeof(L.GameResult) == 40
     assert C.sizeof(L.GameState) == 40
@@ -170,3 +170,17 @@ def test_checkpoint_arguments_without_a_context():
     n = C.c_size_t()
     assert L.lib().game_save(None, None, C.byref(n)) == L.GAME_E_INVALID
     assert L.lib().game_load(None, None, 0) == L.GAME_E_INVALID
+
+
+def test_selection_and_immigrant_validation():
+    st, _ = _query(selection="ranking", pop_size=9000, dtype="f32")
+    assert st == L.GAME_E_INVALID
+    assert _query(selection="roulette", n_immigrants=18)[0] == L.GAME_OK
+    assert _query(n_immigrants=19)[0] == L.GAME_E_INVALID        # more than P - E children
+    assert _query(n_immigrants=-1)[0] == L.GAME_E_INVALID
+    c = Config(n_patterns=100, n_features=2).to_c()
+    c.selection = 3
+    assert L.lib().game_query(C.byref(c), C.byref(L.GameDims())) == L.GAME_E_INVALID
+    c.selection = 0
+    c.reserved = 1
+    assert L.lib().game_query(C.byref(c), C.byref(L.GameDims())) == L.GAME_E_INVALID

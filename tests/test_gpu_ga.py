@@ -15,13 +15,14 @@ def bits(a):
     return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
 
 
-def make_game(P, L_genes, E=2, k=3, pc=0.9, pm=0.05, sigma=0.1, seed=99):
+def make_game(P, L_genes, E=2, k=3, pc=0.9, pm=0.05, sigma=0.1, seed=99, selection="tournament",
+              n_imm=0):
     torch = require_gpu()
     from paper_1211_5481_amd import Config, Game
     # L genes = F * D with the power basis and D = 1 (bias adds one)
     cfg = Config(n_patterns=64, n_features=L_genes, degree=1, basis="power", dtype="f32",
                  pop_size=P, elitism=E, tournament_k=k, p_crossover=pc, p_mutation=pm,
-                 mutation_sigma=sigma, seed=seed)
+                 mutation_sigma=sigma, seed=seed, selection=selection, n_immigrants=n_imm)
     X = np.random.default_rng(0).uniform(-1, 1, (64, L_genes))
     t = np.zeros(64)
     return Game(cfg, dev(X, torch.float32), dev(t, torch.float32)), cfg
@@ -103,4 +104,47 @@ def test_set_population_then_evolve_from_odd_generation():
     mse, _, _ = g.eval_fitness()
     ref, _, _ = g.eval_fitness(dev(want, torch.float32))
     assert np.array_equal(host(mse), host(ref))
+    g.close()
+
+
+SEL = {"tournament": ga.SEL_TOURNAMENT, "roulette": ga.SEL_ROULETTE, "ranking": ga.SEL_RANKING}
+WHEEL_CASES = [
+    # selection, P, L, E, n_immigrants, p_mutation, fitness kind
+    ("roulette", 20, 32, 2, 0, 0.05, "ties+nan"),
+    ("roulette", 1000, 120, 2, 0, 0.2, "ties+nan"),
+    ("roulette", 33, 9, 2, 5, 0.2, "all-equal"),
+    ("roulette", 17, 5, 1, 0, 0.05, "all-nan"),
+    ("ranking", 20, 32, 2, 0, 0.05, "ties+nan"),
+    ("ranking", 2048, 128, 2, 0, 0.2, "ties+nan"),
+    ("ranking", 8192, 7, 2, 30, 0.2, "ties+nan"),   # largest ranked population
+    ("tournament", 64, 16, 2, 7, 0.05, "ties+nan"),
+    ("ranking", 21, 7, 0, 21, 0.2, "ties+nan"),     # every child an immigrant
+]
+
+
+def wheel_fitness(kind, P, seed):
+    if kind == "all-equal":
+        return np.full(P, 0.25)
+    if kind == "all-nan":
+        return np.full(P, np.nan)
+    return synth.random_fitness(P, seed=seed, n_ties=P // 4, n_nan=2 if P > 4 else 0)
+
+
+@pytest.mark.parametrize("case", WHEEL_CASES, ids=lambda c: "-".join(map(str, c)))
+def test_wheel_selection_and_immigrants_bit_exact(case):
+    torch = require_gpu()
+    sel, P, L, E, n_imm, pm, kind = case
+    seed = 5150 + P
+    g, cfg = make_game(P, L, E, pm=pm, seed=seed, selection=sel, n_imm=n_imm)
+    pop = host(g.population)
+    for gen in range(3):
+        fit = wheel_fitness(kind, P, gen + P)
+        announce(f"wheel step {case} generation {gen}")
+        g.step(dev(fit, torch.float64))
+        got = host(g.population)
+        want = ga.ga_step(pop, fit, gen, seed, elitism=E, k=3, p_crossover=0.9, p_mutation=pm,
+                          sigma=0.1, selection=SEL[sel], n_immigrants=n_imm)
+        bad = np.argwhere(bits(got) != bits(want))
+        assert bad.size == 0, f"generation {gen}: first mismatches {bad[:5].tolist()}"
+        pop = want
     g.close()

@@ -83,3 +83,50 @@ def test_best_fitness_never_decreases_and_runs_repeat():
     assert np.array_equal(host(g.population).view(np.uint32), host(h.population).view(np.uint32))
     g.close()
     h.close()
+
+
+def test_set_population_then_first_run_uses_the_new_population():
+    """A context whose first graph is built after set_population evaluates the
+    population it was given (the stale gene tile is repacked)."""
+    torch = require_gpu()
+    from paper_1211_5481_amd import Config, Game
+    X, t = synth.classification_dataset(4000, 5, seed=8)
+    cfg = Config(n_patterns=4000, n_features=5, degree=3, basis="trig", task="classification",
+                 dtype="f32", pop_size=64, max_generations=1, seed=5)
+    a = Game(cfg, dev(X, torch.float32), dev(t, torch.float32))
+    announce("set_population then run")
+    mse_a = host(a.eval_fitness()[0])
+    b = Game(Config(**{**cfg.__dict__, "seed": 6}), dev(X, torch.float32), dev(t, torch.float32))
+    b.population = a.population.clone()
+    r = b.run()
+    assert r["generations"] == 1 and r["best_mse"] == mse_a.min()
+    a.close()
+    b.close()
+
+
+def test_paper_settings_run():
+    """The settings of the paper's experiment (Sec. 5): polytrigo expansion,
+    rank-based roulette selection, crossover 0.9, mutation 0.2, two elites,
+    MSE threshold 0.001, on a 2100-pattern, 7-feature two-class set (the
+    paper's data size); population B*F + 1 (eq. 4).  The best fitness never
+    decreases and the run ends by one of its two stop rules."""
+    torch = require_gpu()
+    from paper_1211_5481_amd import Config, Game
+    X, t = synth.classification_dataset(2100, 7, seed=21)
+    for D in (1, 2, 4, 8):
+        cfg = Config(n_patterns=2100, n_features=7, degree=D, basis="trig", task="classification",
+                     dtype="f32", pop_size=0, elitism=2, selection="ranking", p_crossover=0.9,
+                     p_mutation=0.2, mse_threshold=0.001, max_generations=300, seed=D)
+        g = Game(cfg, dev(X, torch.float32), dev(t, torch.float32))
+        assert g.P == 2 * 7 + 1
+        announce(f"paper settings D={D}")
+        best = []
+        for _ in range(40):
+            g.advance(1)
+            g.eval_fitness()
+            best.append(g.state()["best_fitness"])
+        assert all(b1 >= b0 for b0, b1 in zip(best, best[1:]))
+        r = g.run()
+        assert r["stop_reason"] in ("threshold", "max_generations")
+        assert 0.0 <= r["best_miscls"] <= 1.0 and r["best_mse"] <= 1.0 - best[0] + 1e-12
+        g.close()
