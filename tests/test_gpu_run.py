@@ -123,8 +123,7 @@ def test_paper_settings_run():
         best = []
         for _ in range(40):
             g.advance(1)
-            g.eval_fitness()
-            best.append(g.state()["best_fitness"])
+            best.append(float(np.nanmax(host(g.eval_fitness()[2]))))  # this generation's best
         assert all(b1 >= b0 for b0, b1 in zip(best, best[1:]))
         r = g.run()
         assert r["stop_reason"] in ("threshold", "max_generations")
