@@ -31,9 +31,9 @@
 namespace game {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 1024;
 constexpr int kMaxR = 8;            // rows per workgroup pass (registers)
-constexpr size_t kRowsLds = 65536;  // LDS budget of the rows kernel
+constexpr size_t kRowsLds = 98304;  // LDS budget of the rows kernel
 
 __device__ __forceinline__ float gelu(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float a) {
@@ -60,23 +60,43 @@ struct RowsArgs {
   int64_t total;  // parameters
 };
 
-// Block-wide sums of kMaxR per-thread values in a fixed order (each wave by
-// shuffles, then the four waves in order); the sums land in out[0..kMaxR).
-__device__ __forceinline__ void block_sum_rows(const float (&v)[kMaxR], float* red, float* out) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// Thread layout of the rows kernel: 1024 threads = 4 groups (ks) of 256
+// column lanes (c).  A product over K is split into 4 contiguous K quarters,
+// one per group; the quarters' partial sums are added in group order.
+constexpr int kLanes = 256, kGroups = kThreads / kLanes;
+
+// Partial dot products of column j (lane stride kLanes) over K quarter ks:
+// acc[r] = sum_{k in quarter} W[k * ldw + j] * V[r * ldv + k], r < R.
+__device__ __forceinline__ void quarter_dot(const float* __restrict__ W, int64_t ldw, int j,
+                                            const float* V, int ldv, int K, int ks, int R,
+                                            float (&acc)[kMaxR]) {
 #pragma unroll
-  for (int r = 0; r < kMaxR; ++r) {
-    float x = v[r];
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-    if (lane == 0) red[wave * kMaxR + r] = x;
+  for (int r = 0; r < kMaxR; ++r) acc[r] = 0.0f;
+  const int q = (K + kGroups - 1) / kGroups;
+  const int k0 = ks * q, k1 = min(K, k0 + q);
+  int k = k0;
+  if (((k0 | q | ldv) & 3) == 0 && (reinterpret_cast<uintptr_t>(V) & 15) == 0) {
+    for (; k + 4 <= k1; k += 4) {
+      float w[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) w[u] = W[(int64_t)(k + u) * ldw + j];
+#pragma unroll
+      for (int r = 0; r < kMaxR; ++r)
+        if (r < R) {
+          const float4 v = *reinterpret_cast<const float4*>(&V[r * ldv + k]);
+          acc[r] = fmaf(w[0], v.x, acc[r]);
+          acc[r] = fmaf(w[1], v.y, acc[r]);
+          acc[r] = fmaf(w[2], v.z, acc[r]);
+          acc[r] = fmaf(w[3], v.w, acc[r]);
+        }
+    }
   }
-  __syncthreads();
-  if (threadIdx.x < kMaxR) {
-    float t = 0.0f;
-    for (int w = 0; w < kThreads / 64; ++w) t += red[w * kMaxR + threadIdx.x];
-    out[threadIdx.x] = t;
+  for (; k < k1; ++k) {
+    const float w = W[(int64_t)k * ldw + j];
+#pragma unroll
+    for (int r = 0; r < kMaxR; ++r)
+      if (r < R) acc[r] = fmaf(w, V[r * ldv + k], acc[r]);
   }
-  __syncthreads();
 }
 
 template <bool kTrain>
@@ -84,6 +104,7 @@ __global__ __launch_bounds__(kThreads) void rows_kernel(RowsArgs a, const DevSta
   if (run_halted(halt)) return;
   extern __shared__ __align__(16) float sm[];
   const int L = a.L, H1 = a.H1, H2 = a.H2, R = a.R;
+  const int Hm = H1 > H2 ? H1 : H2;
   float* X = sm;              // R x L
   float* A1 = X + R * L;      // R x H1 pre-activations
   float* Hd1 = A1 + R * H1;   // R x H1 activations
@@ -91,9 +112,11 @@ __global__ __launch_bounds__(kThreads) void rows_kernel(RowsArgs a, const DevSta
   float* A2 = D1 + R * H1;    // R x H2
   float* Hd2 = A2 + R * H2;   // R x H2
   float* D2 = Hd2 + R * H2;   // R x H2: dLoss/dA2
-  __shared__ float s_t[kMaxR], s_y[kMaxR], s_dy[kMaxR], s_red[(kThreads / 64) * kMaxR];
+  float* red = D2 + R * H2;   // kGroups x R x Hm quarter sums
+  __shared__ float s_t[kMaxR], s_y[kMaxR], s_dy[kMaxR];
   __shared__ int s_slot[kMaxR];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, c = tid % kLanes, ks = tid / kLanes;
+  const int lane = tid & 63, wave = tid >> 6;
   const int64_t oW1 = 0, ob1 = (int64_t)H1 * L, oW2 = ob1 + H1, ob2 = oW2 + (int64_t)H2 * H1,
                 ow3 = ob2 + H2, ob3 = ow3 + H2;
   const float* P = a.params;
@@ -102,6 +125,17 @@ __global__ __launch_bounds__(kThreads) void rows_kernel(RowsArgs a, const DevSta
   float* slab = kTrain ? a.slab + (int64_t)blockIdx.x * (a.total + 1) : nullptr;
   bool first = true;
   auto put = [&](int64_t o, float v) { slab[o] = first ? v : slab[o] + v; };
+  // quarter sums of the columns this thread owns -> red[ks][r][j]
+  auto to_red = [&](int j, const float (&acc)[kMaxR]) {
+#pragma unroll
+    for (int r = 0; r < kMaxR; ++r)
+      if (r < R) red[(ks * R + r) * Hm + j] = acc[r];
+  };
+  auto quarters = [&](int r, int j) {
+    float t = 0.0f;
+    for (int g = 0; g < kGroups; ++g) t += red[(g * R + r) * Hm + j];
+    return t;
+  };
 
   for (int r0 = blockIdx.x * R; r0 < a.B; r0 += a.W * R) {
     const int nr = min(R, a.B - r0);
@@ -124,68 +158,57 @@ __global__ __launch_bounds__(kThreads) void rows_kernel(RowsArgs a, const DevSta
       }
     }
     __syncthreads();
-    for (int e = tid; e < R * L; e += kThreads) {
-      const int r = e / L, l = e - r * L;
-      float v = 0.0f;
-      if (r < nr) v = a.X ? a.X[(int64_t)(r0 + r) * L + l] : a.buf[(int64_t)s_slot[r] * L + l];
-      X[e] = v;
-    }
+    for (int r = 0; r < R; ++r)
+      for (int l = tid; l < L; l += kThreads) {
+        float v = 0.0f;
+        if (r < nr) v = a.X ? a.X[(int64_t)(r0 + r) * L + l] : a.buf[(int64_t)s_slot[r] * L + l];
+        X[r * L + l] = v;
+      }
     __syncthreads();
     // ---- layer 1: A1 = X W1^T + b1
-    for (int j = tid; j < H1; j += kThreads) {
+    for (int j = c; j < H1; j += kLanes) {
       float acc[kMaxR];
-      const float b = P[ob1 + j];
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r) acc[r] = b;
-      for (int l = 0; l < L; ++l) {
-        const float w = W1T[(int64_t)l * H1 + j];
-#pragma unroll
-        for (int r = 0; r < kMaxR; ++r)
-          if (r < R) acc[r] = fmaf(w, X[r * L + l], acc[r]);
-      }
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r)
-        if (r < R) {
-          A1[r * H1 + j] = acc[r];
-          Hd1[r * H1 + j] = gelu(acc[r]);
-        }
+      quarter_dot(W1T, H1, j, X, L, L, ks, R, acc);
+      to_red(j, acc);
     }
     __syncthreads();
-    // ---- layer 2: A2 = H1 W2^T + b2, and the head's per-thread terms
-    float yp[kMaxR];
-#pragma unroll
-    for (int r = 0; r < kMaxR; ++r) yp[r] = 0.0f;
-    for (int j = tid; j < H2; j += kThreads) {
-      float acc[kMaxR];
-      const float b = P[ob2 + j];
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r) acc[r] = b;
-      for (int i = 0; i < H1; ++i) {
-        const float w = W2T[(int64_t)i * H2 + j];
-#pragma unroll
-        for (int r = 0; r < kMaxR; ++r)
-          if (r < R) acc[r] = fmaf(w, Hd1[r * H1 + i], acc[r]);
-      }
-      const float w3 = P[ow3 + j];
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r)
-        if (r < R) {
-          A2[r * H2 + j] = acc[r];
-          const float h = gelu(acc[r]);
-          Hd2[r * H2 + j] = h;
-          yp[r] = fmaf(h, w3, yp[r]);
-        }
+    for (int e = tid; e < R * H1; e += kThreads) {
+      const int r = e / H1, j = e - r * H1;
+      const float pre = P[ob1 + j] + quarters(r, j);
+      A1[e] = pre;
+      Hd1[e] = gelu(pre);
     }
-    // ---- head: y = H2 w3 + b3
-    block_sum_rows(yp, s_red, s_y);
+    __syncthreads();
+    // ---- layer 2: A2 = H1 W2^T + b2
+    for (int j = c; j < H2; j += kLanes) {
+      float acc[kMaxR];
+      quarter_dot(W2T, H2, j, Hd1, H1, H1, ks, R, acc);
+      to_red(j, acc);
+    }
+    __syncthreads();
+    for (int e = tid; e < R * H2; e += kThreads) {
+      const int r = e / H2, j = e - r * H2;
+      const float pre = P[ob2 + j] + quarters(r, j);
+      A2[e] = pre;
+      Hd2[e] = gelu(pre);
+    }
+    __syncthreads();
+    // ---- head: y = H2 w3 + b3, wave r sums row r (fixed order)
+    if (wave < R) {
+      float y = 0.0f;
+      for (int j = lane; j < H2; j += 64) y = fmaf(Hd2[wave * H2 + j], P[ow3 + j], y);
+      for (int off = 32; off > 0; off >>= 1) y += __shfl_xor(y, off);
+      if (lane == 0) s_y[wave] = y + P[ob3];
+    }
+    __syncthreads();
     if (!kTrain) {
-      if (tid < nr) a.y[r0 + tid] = s_y[tid] + P[ob3];
+      if (tid < nr) a.y[r0 + tid] = s_y[tid];
       __syncthreads();
       continue;
     }
     // ---- loss and output gradient: residual = y - t, dy = 2 residual / B
     if (tid < kMaxR) {
-      const float res = tid < nr ? (s_y[tid] + P[ob3]) - s_t[tid] : 0.0f;
+      const float res = tid < nr ? s_y[tid] - s_t[tid] : 0.0f;
       s_dy[tid] = 2.0f * res / (float)a.B;
       s_y[tid] = res * res;
     }
@@ -199,57 +222,53 @@ __global__ __launch_bounds__(kThreads) void rows_kernel(RowsArgs a, const DevSta
       put(ob3, dsum);
       put(a.total, lsum);
     }
-    // ---- dA2 = dy w3 gelu'(A2); gradients of w3 and b2
+    // ---- dA2 = dy w3 gelu'(A2)
+    for (int e = tid; e < R * H2; e += kThreads) {
+      const int r = e / H2, j = e - r * H2;
+      D2[e] = s_dy[r] * P[ow3 + j] * gelu_grad(A2[e]);  // zero for rows past the batch
+    }
+    __syncthreads();
+    // ---- gradients of w3 and b2
     for (int j = tid; j < H2; j += kThreads) {
-      const float w3 = P[ow3 + j];
       float gw3 = 0.0f, gb2 = 0.0f;
       for (int r = 0; r < R; ++r) {
-        const float dy = s_dy[r];  // zero for rows past the batch
-        gw3 = fmaf(Hd2[r * H2 + j], dy, gw3);
-        const float d = dy * w3 * gelu_grad(A2[r * H2 + j]);
-        D2[r * H2 + j] = d;
-        gb2 += d;
+        gw3 = fmaf(Hd2[r * H2 + j], s_dy[r], gw3);
+        gb2 += D2[r * H2 + j];
       }
       put(ow3 + j, gw3);
       put(ob2 + j, gb2);
     }
-    __syncthreads();
-    // ---- gradient of W2: dA2^T H1
-    for (int64_t e = tid; e < (int64_t)H2 * H1; e += kThreads) {
-      const int j = (int)(e / H1), i = (int)(e - (int64_t)j * H1);
-      float g = 0.0f;
-      for (int r = 0; r < R; ++r) g = fmaf(D2[r * H2 + j], Hd1[r * H1 + i], g);
-      put(oW2 + e, g);
-    }
-    // ---- dA1 = (dA2 W2) gelu'(A1); gradient of b1
-    for (int i = tid; i < H1; i += kThreads) {
-      float acc[kMaxR];
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r) acc[r] = 0.0f;
-      for (int j = 0; j < H2; ++j) {
-        const float w = P[oW2 + (int64_t)j * H1 + i];
-#pragma unroll
-        for (int r = 0; r < kMaxR; ++r)
-          if (r < R) acc[r] = fmaf(D2[r * H2 + j], w, acc[r]);
+    // ---- gradient of W2: dA2^T H1 (rows j by group, columns i by lane)
+    for (int j = ks; j < H2; j += kGroups)
+      for (int i = c; i < H1; i += kLanes) {
+        float g = 0.0f;
+        for (int r = 0; r < R; ++r) g = fmaf(D2[r * H2 + j], Hd1[r * H1 + i], g);
+        put(oW2 + (int64_t)j * H1 + i, g);
       }
+    // ---- dA1 = (dA2 W2) gelu'(A1): quarter sums over j
+    for (int i = c; i < H1; i += kLanes) {
+      float acc[kMaxR];
+      quarter_dot(P + oW2, H1, i, D2, H2, H2, ks, R, acc);
+      to_red(i, acc);
+    }
+    __syncthreads();
+    for (int e = tid; e < R * H1; e += kThreads) {
+      const int r = e / H1, i = e - r * H1;
+      D1[e] = quarters(r, i) * gelu_grad(A1[e]);
+    }
+    __syncthreads();
+    // ---- gradient of b1, and of W1: dA1^T X
+    for (int i = tid; i < H1; i += kThreads) {
       float gb1 = 0.0f;
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r)
-        if (r < R) {
-          const float d = acc[r] * gelu_grad(A1[r * H1 + i]);
-          D1[r * H1 + i] = d;
-          gb1 += d;
-        }
+      for (int r = 0; r < R; ++r) gb1 += D1[r * H1 + i];
       put(ob1 + i, gb1);
     }
-    __syncthreads();
-    // ---- gradient of W1: dA1^T X
-    for (int64_t e = tid; e < (int64_t)H1 * L; e += kThreads) {
-      const int i = (int)(e / L), l = (int)(e - (int64_t)i * L);
-      float g = 0.0f;
-      for (int r = 0; r < R; ++r) g = fmaf(D1[r * H1 + i], X[r * L + l], g);
-      put(oW1 + e, g);
-    }
+    for (int i = ks; i < H1; i += kGroups)
+      for (int l = c; l < L; l += kLanes) {
+        float g = 0.0f;
+        for (int r = 0; r < R; ++r) g = fmaf(D1[r * H1 + i], X[r * L + l], g);
+        put(oW1 + (int64_t)i * L + l, g);
+      }
     first = false;
     __syncthreads();
   }
@@ -372,7 +391,8 @@ __global__ void init_kernel(float* __restrict__ p, float* __restrict__ m, float*
 }
 
 size_t rows_lds(const MlpDims& d, int R) {
-  return (size_t)R * ((size_t)d.L + 3 * (size_t)d.H1 + 3 * (size_t)d.H2) * sizeof(float);
+  const size_t Hm = (size_t)std::max(d.H1, d.H2);
+  return (size_t)R * ((size_t)d.L + 3 * (size_t)d.H1 + 3 * (size_t)d.H2 + 4 * Hm) * sizeof(float);
 }
 
 hipError_t rows_prepare() {
