@@ -159,6 +159,41 @@ def evaluate(X, t, G, basis: str, degree: int, task: str = "regression",
     return dict(mse=mse, miscls=miscls, fitness=1.0 - mse, z=z)
 
 
+def predict(X, genes, basis: str, degree: int, task: str = "regression", bias: int = 0,
+            Phi=None) -> np.ndarray:
+    """Model output of one chromosome on new patterns (the paper's test and
+    validation use, Sec. 4): z for regression, sigmoid(z) for classification."""
+    z = pattern_output(X, np.asarray(genes, dtype=np.float64)[None, :], basis, degree, bias,
+                       Phi)[:, 0]
+    return sigmoid(z) if task == "classification" else z
+
+
+def metrics(X, t, genes, basis: str, degree: int, task: str = "regression", bias: int = 0,
+            Phi=None) -> dict:
+    """Quality of one chromosome on a pattern set: MSE (eq. 3) and its root;
+    for classification the confusion counts with class 1 as the positive class
+    (predicted 1 iff z >= 0, label l = [t >= 0.5]) and the rates the paper
+    reports (Sec. 5): accuracy = (TP + TN) / N, completeness = TP / (TP + FN),
+    contamination = FP / (TP + FP) (NaN when a denominator is 0)."""
+    g = np.asarray(genes, dtype=np.float64)[None, :]
+    r = evaluate(X, t, g, basis, degree, task, bias, Phi)
+    mse = float(r["mse"][0])
+    out = dict(mse=mse, rmse=math.sqrt(mse), tp=0, fp=0, tn=0, fn=0, accuracy=math.nan,
+               completeness=math.nan, contamination=math.nan)
+    if task == "classification":
+        pred = r["z"][:, 0] >= 0.0
+        lab = np.asarray(t, dtype=np.float64) >= 0.5
+        tp = int(np.sum(pred & lab))
+        fp = int(np.sum(pred & ~lab))
+        tn = int(np.sum(~pred & ~lab))
+        fn = int(np.sum(~pred & lab))
+        n = tp + fp + tn + fn
+        out.update(tp=tp, fp=fp, tn=tn, fn=fn, accuracy=(tp + tn) / n,
+                   completeness=tp / (tp + fn) if tp + fn else math.nan,
+                   contamination=fp / (tp + fp) if tp + fp else math.nan)
+    return out
+
+
 def quantize(a, kind: str) -> np.ndarray:
     """Round to a storage type and back to float64 (round to nearest even).
 

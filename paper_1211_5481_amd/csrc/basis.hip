@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "expand.hpp"
 #include "game_internal.hpp"
 
 namespace game {
@@ -46,49 +47,6 @@ __device__ __forceinline__ bf16_bits to_storage<bf16_bits>(double v) {
   return bf16_bits{(uint16_t)(r >> 16)};
 }
 
-// All K basis values of one feature value x, written through `put(k, value)`.
-template <typename Put>
-__device__ __forceinline__ void expand(int basis, int D, double x, Put put) {
-  if (basis == GAME_BASIS_POWER) {
-    double p = x;
-    for (int k = 0; k < D; ++k) {
-      put(k, p);
-      p *= x;
-    }
-  } else if (basis == GAME_BASIS_CHEBYSHEV) {
-    double prev = 1.0, cur = x;
-    for (int k = 0; k < D; ++k) {
-      put(k, cur);
-      const double nxt = 2.0 * x * cur - prev;
-      prev = cur;
-      cur = nxt;
-    }
-  } else if (basis == GAME_BASIS_LEGENDRE) {
-    double prev = 1.0, cur = x;
-    for (int k = 0; k < D; ++k) {
-      put(k, cur);
-      const double j = (double)(k + 1);
-      const double nxt = ((2.0 * j + 1.0) * x * cur - j * prev) / (j + 1.0);
-      prev = cur;
-      cur = nxt;
-    }
-  } else {  // trig: cos(1x)..cos(Dx), sin(1x)..sin(Dx)
-    double s1, c1;
-    sincos(x, &s1, &c1);
-    double cp = 1.0, cc = c1, sp = 0.0, sc = s1;
-    for (int k = 0; k < D; ++k) {
-      put(k, cc);
-      put(D + k, sc);
-      const double cn = 2.0 * c1 * cc - cp;
-      const double sn = 2.0 * c1 * sc - sp;
-      cp = cc;
-      cc = cn;
-      sp = sc;
-      sc = sn;
-    }
-  }
-}
-
 template <typename XT, typename O>
 __global__ __launch_bounds__(kBasisThreads) void basis_kernel(const XT* __restrict__ X,
                                                               int64_t rows_in, int64_t rows_out,
@@ -109,7 +67,7 @@ __global__ __launch_bounds__(kBasisThreads) void basis_kernel(const XT* __restri
     O* dst = lds + (int64_t)r * ld + (int64_t)i * K;
     if (n < rows_in) {
       const double x = (double)X[n * F + i];
-      expand(basis, D, x, [&](int k, double v) { dst[k] = to_storage<O>(v); });
+      expand_feature(basis, D, x, [&](int k, double v) { dst[k] = to_storage<O>(v); });
     } else {
       for (int k = 0; k < K; ++k) dst[k] = to_storage<O>(0.0);
     }

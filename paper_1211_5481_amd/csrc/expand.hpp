@@ -1,0 +1,57 @@
+// Basis values of one feature value (eq. 1; eq. 6 for trig), shared by the
+// basis, re-score and prediction kernels.  Evaluated in double by the
+// three-term recurrences (Chebyshev, Legendre, the cos/sin multiple-angle
+// recurrence seeded by one sincos); power by repeated products.  The K values
+// are handed to put(k, value) in column order: phi_1..phi_D, or for trig
+// cos(1x)..cos(Dx) then sin(1x)..sin(Dx).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "game.h"
+
+namespace game {
+
+template <typename Put>
+__device__ __forceinline__ void expand_feature(int basis, int D, double x, Put put) {
+  if (basis == GAME_BASIS_POWER) {
+    double p = x;
+    for (int k = 0; k < D; ++k) {
+      put(k, p);
+      p *= x;
+    }
+  } else if (basis == GAME_BASIS_CHEBYSHEV) {
+    double prev = 1.0, cur = x;
+    for (int k = 0; k < D; ++k) {
+      put(k, cur);
+      const double nxt = 2.0 * x * cur - prev;
+      prev = cur;
+      cur = nxt;
+    }
+  } else if (basis == GAME_BASIS_LEGENDRE) {
+    double prev = 1.0, cur = x;
+    for (int k = 0; k < D; ++k) {
+      put(k, cur);
+      const double j = (double)(k + 1);
+      const double nxt = ((2.0 * j + 1.0) * x * cur - j * prev) / (j + 1.0);
+      prev = cur;
+      cur = nxt;
+    }
+  } else {
+    double s1, c1;
+    sincos(x, &s1, &c1);
+    double cp = 1.0, cc = c1, sp = 0.0, sc = s1;
+    for (int k = 0; k < D; ++k) {
+      put(k, cc);
+      put(D + k, sc);
+      const double cn = 2.0 * c1 * cc - cp;
+      const double sn = 2.0 * c1 * sc - sp;
+      cp = cc;
+      cc = cn;
+      sp = sc;
+      sc = sn;
+    }
+  }
+}
+
+}  // namespace game

@@ -14,6 +14,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "expand.hpp"
 #include "game_internal.hpp"
 #include "select.hpp"
 
@@ -40,50 +41,6 @@ struct RescoreArgs {
   DevState* st;          // tracking mode: best tracking + stop test; else null
   float* best;           // best genes (tracking mode)
 };
-
-// One feature value -> its K basis values (double recurrence), each handed to
-// put(k, value) as soon as it is formed.
-template <typename Put>
-__device__ __forceinline__ void basis_row(int basis, int D, double x, Put put) {
-  if (basis == GAME_BASIS_POWER) {
-    double p = x;
-    for (int k = 0; k < D; ++k) {
-      put(k, p);
-      p *= x;
-    }
-  } else if (basis == GAME_BASIS_CHEBYSHEV) {
-    double prev = 1.0, cur = x;
-    for (int k = 0; k < D; ++k) {
-      put(k, cur);
-      const double nxt = 2.0 * x * cur - prev;
-      prev = cur;
-      cur = nxt;
-    }
-  } else if (basis == GAME_BASIS_LEGENDRE) {
-    double prev = 1.0, cur = x;
-    for (int k = 0; k < D; ++k) {
-      put(k, cur);
-      const double j = (double)(k + 1);
-      const double nxt = ((2.0 * j + 1.0) * x * cur - j * prev) / (j + 1.0);
-      prev = cur;
-      cur = nxt;
-    }
-  } else {
-    double s1, c1;
-    sincos(x, &s1, &c1);
-    double cp = 1.0, cc = c1, sp = 0.0, sc = s1;
-    for (int k = 0; k < D; ++k) {
-      put(k, cc);
-      put(D + k, sc);
-      const double cn = 2.0 * c1 * cc - cp;
-      const double sn = 2.0 * c1 * sc - sp;
-      cp = cc;
-      cc = cn;
-      sp = sc;
-      sc = sn;
-    }
-  }
-}
 
 __global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
   if (run_halted(a.st)) return;
@@ -116,7 +73,7 @@ __global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
     for (int e = 0; e < kMaxRescore; ++e) z[e] = 0.0f;
     for (int i = 0; i < a.F; ++i) {
       const float* gi = g_lds + i * a.K;
-      basis_row(a.basis, a.D, (double)a.X[nrow * a.F + i], [&](int k, double val) {
+      expand_feature(a.basis, a.D, (double)a.X[nrow * a.F + i], [&](int k, double val) {
         const float vf = (float)val;
 #pragma unroll
         for (int e = 0; e < kMaxRescore; ++e)

@@ -216,3 +216,34 @@ def test_classification_compares_with_class_labels():
     b = model.evaluate(X, t_lab, G, "legendre", 2, "classification")
     np.testing.assert_array_equal(a["mse"], b["mse"])
     np.testing.assert_array_equal(a["miscls"], b["miscls"])
+
+
+def test_metrics_against_sklearn_and_a_hand_example():
+    from sklearn import metrics as skm
+    # hand example: four patterns, power basis D = 1, one feature, gene 1 -> z = x
+    X = np.array([[0.5], [-0.2], [0.0], [-0.7]])
+    t = np.array([1.0, 1.0, 0.0, 0.0])
+    m = model.metrics(X, t, [1.0], "power", 1, "classification")
+    # predictions z >= 0: [1, 0, 1, 0] -> TP 1, FN 1, FP 1, TN 1
+    assert (m["tp"], m["fn"], m["fp"], m["tn"]) == (1, 1, 1, 1)
+    assert m["accuracy"] == 0.5 and m["completeness"] == 0.5 and m["contamination"] == 0.5
+    s = 1.0 / (1.0 + np.exp(-X[:, 0]))
+    assert abs(m["mse"] - np.mean((t - s) ** 2)) < 1e-15
+    # random set against scikit-learn's confusion matrix, recall and precision
+    X, t = synth.classification_dataset(3000, 4, seed=13)
+    g = synth.random_population(1, 4 * 2 * 3, seed=2)[0]
+    m = model.metrics(X, t, g, "trig", 3, "classification")
+    pred = model.predict(X, g, "trig", 3, "classification") >= 0.5
+    lab = t >= 0.5
+    tn, fp, fn, tp = skm.confusion_matrix(lab, pred).ravel()
+    assert (m["tp"], m["fp"], m["tn"], m["fn"]) == (tp, fp, tn, fn)
+    assert abs(m["accuracy"] - skm.accuracy_score(lab, pred)) < 1e-15
+    assert abs(m["completeness"] - skm.recall_score(lab, pred)) < 1e-15
+    assert abs(m["contamination"] - (1.0 - skm.precision_score(lab, pred))) < 1e-15
+    # regression: RMSE from scikit-learn, no confusion counts
+    X, t, _ = synth.regression_dataset(500, 3, 2, 0.05, seed=3)
+    g = synth.random_population(1, 3 * 4, seed=4)[0]
+    m = model.metrics(X, t, g, "legendre", 4, "regression")
+    y = model.predict(X, g, "legendre", 4, "regression")
+    assert abs(m["rmse"] - np.sqrt(skm.mean_squared_error(t, y))) < 1e-12
+    assert m["tp"] == m["fp"] == m["tn"] == m["fn"] == 0 and math.isnan(m["accuracy"])
