@@ -320,6 +320,31 @@ game_status game_get_population(game_ctx* ctx, float* genes_dev);
 game_status game_set_population(game_ctx* ctx, const float* genes_dev);
 
 /*
+ * Test and validation use (Sec. 4: the trained model applied to patterns).
+ * genes_dev: one chromosome (L floats, device), or NULL for the best so far
+ * (GAME_E_STATE before any population evaluation).  X_dev: n x F patterns,
+ * t_dev: n targets (double for F64 contexts, else float; the basis is that of
+ * the context).  Every pattern is computed in double.
+ *   game_predict: out_dev[i] = z_i (regression) or sigmoid(z_i)
+ *     (classification), n values of the input type; async.
+ *   game_evaluate: blocking; fills *out: MSE (eq. 3) and RMSE over the n
+ *     patterns and, for classification, the confusion counts with class 1
+ *     positive (predicted 1 iff z >= 0, label t >= 0.5) and the rates the
+ *     paper reports (Sec. 5): accuracy = (TP + TN) / n, completeness =
+ *     TP / (TP + FN), contamination = FP / (TP + FP); rates are NaN when
+ *     undefined (regression, or a zero denominator).
+ */
+typedef struct {
+  int64_t n;
+  double  mse, rmse, accuracy, completeness, contamination;
+  int64_t tp, fp, tn, fn;
+} game_metrics;
+game_status game_predict(game_ctx* ctx, const float* genes_dev, const void* X_dev, int64_t n,
+                         void* out_dev);
+game_status game_evaluate(game_ctx* ctx, const float* genes_dev, const void* X_dev,
+                          const void* t_dev, int64_t n, game_metrics* out_host);
+
+/*
  * Checkpoint and resume.  game_save writes everything a context carries from
  * one generation to the next into a host buffer: the run state, both
  * population buffers, the last fitness values, elites and best genes, and in

@@ -19,6 +19,13 @@ SURROGATE = {"none": 0, "mlp": 1, "random": 2}
 SELECTION = {"tournament": 0, "roulette": 1, "ranking": 2}
 
 
+class GameMetrics(C.Structure):
+    _fields_ = [("n", C.c_int64), ("mse", C.c_double), ("rmse", C.c_double),
+                ("accuracy", C.c_double), ("completeness", C.c_double),
+                ("contamination", C.c_double), ("tp", C.c_int64), ("fp", C.c_int64),
+                ("tn", C.c_int64), ("fn", C.c_int64)]
+
+
 class GameConfig(C.Structure):
     _fields_ = [
         ("struct_size", C.c_uint32),
@@ -120,6 +127,8 @@ SIGNATURES = {
     "game_batch_run": (C.c_int, [_VP, _VP, _VP]),
     "game_batch_destroy": (None, [_VP]),
     "game_run_batched": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, C.c_size_t, _VP, _VP, _VP]),
+    "game_predict": (C.c_int, [_VP, _VP, _VP, C.c_int64, _VP]),
+    "game_evaluate": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int64, C.POINTER(GameMetrics)]),
     "game_save": (C.c_int, [_VP, _VP, C.POINTER(C.c_size_t)]),
     "game_load": (C.c_int, [_VP, _VP, C.c_size_t]),
     "game_get_population": (C.c_int, [_VP, _VP]),

@@ -53,6 +53,8 @@ struct game_ctx {
   double* rpart;  // re-score partials
   int* elite;
   uint64_t* wheel;  // selection wheel or ranking of the current population
+  double* mpart;    // metric partials, then the 5 result values
+  bool evaluated = false;  // a population evaluation has been enqueued (best genes exist)
   DevState* state;
   uint64_t thr_c, thr_m;
   bool poisoned = false;
@@ -224,6 +226,7 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   p->off_x = take(f32x ? (size_t)p->N * c->n_features * 4 : 0);
   p->off_rpart = take(f32x ? (size_t)rescore_grid() * 2 * kMaxRescore * 8 : 0);
   p->off_wheel = take((size_t)P * 8);
+  p->off_mpart = take((size_t)(kPredictParts + 1) * 5 * 8);
   if (offspring) {
     const size_t Lz = (size_t)L;
     const int evrows = std::max<int>((int)P, p->P_eval);
@@ -379,6 +382,7 @@ game_status enqueue_rescore(game_ctx* c, const float* genes, int n, double* mse,
 game_status enqueue_eval_population(game_ctx* c, double* mse, double* miscls, double* fit,
                                     hipStream_t s) {
   if (!c->tile_fresh) GAME_TRY(enqueue_pack_population(c, s));
+  c->evaluated = true;
   GAME_TRY(enqueue_fitness(c, c->plan.P, make_tail(c, c->plan.P, true, mse, miscls, fit), s));
   if (c->cfg.rescore_top > 0)
     GAME_TRY(enqueue_rescore(c, nullptr, c->cfg.rescore_top, nullptr, nullptr, true, s));
@@ -696,6 +700,7 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
   c->xf = reinterpret_cast<float*>(c->ws + p.off_x);
   c->rpart = reinterpret_cast<double*>(c->ws + p.off_rpart);
   c->wheel = reinterpret_cast<uint64_t*>(c->ws + p.off_wheel);
+  c->mpart = reinterpret_cast<double*>(c->ws + p.off_mpart);
   if (p.offspring) {
     auto F = [&](size_t o) { return reinterpret_cast<float*>(c->ws + o); };
     auto D = [&](size_t o) { return reinterpret_cast<double*>(c->ws + o); };
@@ -985,6 +990,60 @@ game_status game_set_population(game_ctx* c, const float* genes) {
   return dev(c, launch_pop_copy(c->pop0, c->pop1, c->state, const_cast<float*>(genes), (int64_t)c->plan.P * c->plan.L, 1, c->stream), "population copy");
 }
 
+static PredictArgs predict_args(game_ctx* c, const float* genes, const void* X, const void* t,
+                                int64_t n) {
+  PredictArgs a{};
+  a.X = X;
+  a.t = t;
+  a.n = n;
+  a.F = c->cfg.n_features;
+  a.D = c->cfg.degree;
+  a.K = c->plan.K;
+  a.basis = c->cfg.basis;
+  a.M = c->plan.M;
+  a.L = c->plan.L;
+  a.bias = c->cfg.bias;
+  a.task = c->cfg.task;
+  a.genes = genes ? genes : c->best;
+  a.part = c->mpart;
+  return a;
+}
+
+game_status game_predict(game_ctx* c, const float* genes, const void* X, int64_t n, void* out) {
+  GAME_TRY(check_ctx(c));
+  if (!X || !out || n < 1) return fail(GAME_E_INVALID, "X, out and n >= 1 are required");
+  if (!genes && !c->evaluated) return fail(GAME_E_STATE, "no best chromosome yet: evaluate or pass genes");
+  PredictArgs a = predict_args(c, genes, X, nullptr, n);
+  a.out = out;
+  return dev(c, launch_predict(c->cfg.dtype == GAME_F64, a, c->stream), "predict");
+}
+
+game_status game_evaluate(game_ctx* c, const float* genes, const void* X, const void* t, int64_t n,
+                          game_metrics* out) {
+  GAME_TRY(check_ctx(c));
+  if (!X || !t || !out || n < 1) return fail(GAME_E_INVALID, "X, t, out and n >= 1 are required");
+  if (!genes && !c->evaluated) return fail(GAME_E_STATE, "no best chromosome yet: evaluate or pass genes");
+  const PredictArgs a = predict_args(c, genes, X, t, n);
+  double* res = c->mpart + (size_t)kPredictParts * 5;
+  double h[5];
+  GAME_TRY(dev(c, launch_metrics(c->cfg.dtype == GAME_F64, a, res, c->stream), "metrics"));
+  GAME_TRY(dev(c, hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, c->stream), "metrics"));
+  GAME_TRY(dev(c, hipStreamSynchronize(c->stream), "synchronize"));
+  out->n = n;
+  out->mse = h[0] / (double)n;
+  out->rmse = std::sqrt(out->mse);
+  out->tp = (int64_t)h[1];
+  out->fp = (int64_t)h[2];
+  out->tn = (int64_t)h[3];
+  out->fn = (int64_t)h[4];
+  const bool cls = c->cfg.task == GAME_CLASSIFICATION;
+  const double nan = std::nan("");
+  out->accuracy = cls ? (double)(out->tp + out->tn) / (double)n : nan;
+  out->completeness = cls && out->tp + out->fn ? (double)out->tp / (double)(out->tp + out->fn) : nan;
+  out->contamination = cls && out->tp + out->fp ? (double)out->fp / (double)(out->tp + out->fp) : nan;
+  return GAME_OK;
+}
+
 // Checkpoint sections: every device buffer that carries state from one
 // generation to the next (the basis, targets, gene tile and scratch are
 // rebuilt or rewritten).
@@ -1094,6 +1153,7 @@ game_status game_load(game_ctx* c, const void* host, size_t bytes) {
   GAME_TRY(dev(c, hipStreamSynchronize(c->stream), "synchronize"));
   c->have_eval = h.have_eval != 0;
   c->sur_warm = h.sur_warm != 0;
+  c->evaluated = true;
   c->tile_fresh = false;
   return GAME_OK;
 }
@@ -1571,6 +1631,7 @@ game_status game_batch_run(game_batch* b, game_result* results, double* latency_
     results[i].stop_reason = s.stop_reason;
     c->have_eval = true;
     c->tile_fresh = true;
+    c->evaluated = true;
     if (latency_us) {
       // generation g of context i: from the start of the batched fitness
       // launch to the end of its breed (bred generations only)

@@ -124,6 +124,7 @@ struct Plan {
   size_t off_mse, off_miscls, off_fit, off_elite, off_state, off_best, off_cnt;
   size_t off_x, off_rpart;          // float32 patterns and re-score partials (16-bit forms)
   size_t off_wheel;                 // selection wheel / ranking (P_max x 8 bytes)
+  size_t off_mpart;                 // metric partials and result
   // offspring form (n_offspring != P - E, or a prescreen)
   bool offspring;
   int k_sel, audit, P_eval, sur, H, cap, steps, batch, n_recent, rows_max;
@@ -277,6 +278,21 @@ hipError_t mlp_train_step(const MlpDims& d, float* params, float* WT, float* m, 
                           hipStream_t s);
 hipError_t mlp_adam(const MlpDims& d, float* params, float* WT, const float* grads, float* m, float* v,
                     int32_t* step, float lr, const DevState* halt, hipStream_t s);
+
+// ------------------------------------------------------ test / validation use
+struct PredictArgs {
+  const void* X;       // n x F patterns (double for F64, else float)
+  const void* t;       // n targets (metrics)
+  int64_t n;
+  int F, D, K, basis, M, L, bias, task;
+  const float* genes;  // one chromosome, L floats
+  void* out;           // n outputs (prediction), same type as X
+  double* part;        // kPredictParts x 5 metric partials
+};
+constexpr int kPredictParts = 1024;
+hipError_t launch_predict(bool f64, const PredictArgs& a, hipStream_t s);
+// result (device): {sum of squared errors, TP, FP, TN, FN}
+hipError_t launch_metrics(bool f64, const PredictArgs& a, double* result, hipStream_t s);
 
 // ------------------------------------------------------ batched form
 // One context's share of a batched fitness launch (device table entry).

@@ -311,6 +311,39 @@ class Game:
             d["best_genes"] = np.frombuffer(genes, dtype=np.float32).copy()
         return d
 
+    def _patterns(self, X, name="X"):
+        X = X.contiguous()
+        if X.dtype != self.cfg.io_dtype or not X.is_cuda:
+            raise ValueError(f"{name} must be a {self.cfg.io_dtype} CUDA tensor")
+        return X
+
+    def predict(self, X, genes=None):
+        """Model output on patterns X (n x F): z, or sigmoid(z) for classification."""
+        torch = _torch()
+        X = self._patterns(X)
+        if X.dim() != 2 or X.shape[1] != self.cfg.n_features:
+            raise ValueError("X must be n x F")
+        if genes is not None:
+            genes = genes.contiguous().to(torch.float32)
+        out = torch.empty(X.shape[0], dtype=self.cfg.io_dtype, device=self.device)
+        L.check(L.lib().game_predict(self._ctx, _ptr(genes), _ptr(X), X.shape[0], _ptr(out)),
+                "game_predict")
+        self._keep = (X, genes)
+        return out
+
+    def evaluate(self, X, t, genes=None) -> dict:
+        """MSE, RMSE and (classification) confusion counts and rates on (X, t)."""
+        torch = _torch()
+        X, t = self._patterns(X), self._patterns(t, "t")
+        if X.dim() != 2 or X.shape[1] != self.cfg.n_features or t.shape != (X.shape[0],):
+            raise ValueError("X must be n x F and t must have n entries")
+        if genes is not None:
+            genes = genes.contiguous().to(torch.float32)
+        m = L.GameMetrics()
+        L.check(L.lib().game_evaluate(self._ctx, _ptr(genes), _ptr(X), _ptr(t), X.shape[0],
+                                      C.byref(m)), "game_evaluate")
+        return {k: getattr(m, k) for k, _ in L.GameMetrics._fields_}
+
     def save(self) -> bytes:
         """Checkpoint (game_save) as bytes."""
         n = C.c_size_t()
