@@ -60,5 +60,6 @@ def test_predict_and_metrics_match_oracle(dtype, basis, task, bias):
     m2 = g.evaluate(dev(Xv, io), dev(tv, io), genes=dev(G, torch.float32))
     ref2 = model.metrics(Xo, to, G.astype(np.float64), basis, D, task, bias)
     assert abs(m2["mse"] - ref2["mse"]) <= 1e-10 * ref2["mse"]
-    assert g.evaluate(dev(Xv, io), dev(tv, io), genes=dev(G, torch.float32)) == m2
+    m3 = g.evaluate(dev(Xv, io), dev(tv, io), genes=dev(G, torch.float32))
+    assert all(m3[k] == m2[k] or (math.isnan(m3[k]) and math.isnan(m2[k])) for k in m2)
     g.close()
