@@ -111,13 +111,29 @@ def design_matrix(X: np.ndarray, basis: str, degree: int) -> np.ndarray:
     return Phi
 
 
-def pattern_output(X, G, basis: str, degree: int, bias: int = 0, Phi=None):
-    """z[n, p] = bias_p + sum_i sum_k G[p, i*K+k] phi_{k+1}(X[n, i])   (eq. 2)."""
+def design_matrix_shared(X: np.ndarray, basis: str, degree: int) -> np.ndarray:
+    """The paper's literal form (eq. 2, eq. 7 and the serial code of Sec. 4):
+    one coefficient per basis function, shared by all features, so the
+    pattern's basis value is summed over its features,
+    Phi_s[n, k] = sum_i phi_{k+1}(X[n, i])  (features added in order)."""
+    X = np.asarray(X, dtype=np.float64)
+    n, f = X.shape
+    K = basis_width(basis, degree)
+    Phi = np.zeros((n, K))
+    for k in range(K):
+        for i in range(f):
+            Phi[:, k] += basis_column(basis, degree, k, X[:, i])
+    return Phi
+
+
+def pattern_output(X, G, basis: str, degree: int, bias: int = 0, Phi=None, shared: bool = False):
+    """z[n, p] = bias_p + sum_i sum_k G[p, i*K+k] phi_{k+1}(X[n, i])   (eq. 2);
+    shared: z[n, p] = bias_p + sum_k G[p, k] sum_i phi_{k+1}(X[n, i])."""
     G = np.asarray(G, dtype=np.float64)
     if G.ndim == 1:
         G = G[None, :]
     if Phi is None:
-        Phi = design_matrix(X, basis, degree)
+        Phi = design_matrix_shared(X, basis, degree) if shared else design_matrix(X, basis, degree)
     M = Phi.shape[1]
     if G.shape[1] != M + (1 if bias else 0):
         raise ValueError(f"chromosome length {G.shape[1]} != {M} + bias {bias}")
@@ -133,7 +149,7 @@ def sigmoid(z):
 
 
 def evaluate(X, t, G, basis: str, degree: int, task: str = "regression",
-             bias: int = 0, Phi=None):
+             bias: int = 0, Phi=None, shared: bool = False):
     """Fitness of every chromosome (row of G) over all patterns.
 
     Returns dict(mse, miscls, fitness, z):
@@ -146,7 +162,7 @@ def evaluate(X, t, G, basis: str, degree: int, task: str = "regression",
     if task not in TASKS:
         raise ValueError(f"unknown task {task!r}")
     t = np.asarray(t, dtype=np.float64)
-    z = pattern_output(X, G, basis, degree, bias, Phi)
+    z = pattern_output(X, G, basis, degree, bias, Phi, shared)
     if task == "classification":
         err = ((t >= 0.5).astype(np.float64)[:, None] - sigmoid(z)) ** 2
     else:
@@ -160,23 +176,23 @@ def evaluate(X, t, G, basis: str, degree: int, task: str = "regression",
 
 
 def predict(X, genes, basis: str, degree: int, task: str = "regression", bias: int = 0,
-            Phi=None) -> np.ndarray:
+            Phi=None, shared: bool = False) -> np.ndarray:
     """Model output of one chromosome on new patterns (the paper's test and
     validation use, Sec. 4): z for regression, sigmoid(z) for classification."""
     z = pattern_output(X, np.asarray(genes, dtype=np.float64)[None, :], basis, degree, bias,
-                       Phi)[:, 0]
+                       Phi, shared)[:, 0]
     return sigmoid(z) if task == "classification" else z
 
 
 def metrics(X, t, genes, basis: str, degree: int, task: str = "regression", bias: int = 0,
-            Phi=None) -> dict:
+            Phi=None, shared: bool = False) -> dict:
     """Quality of one chromosome on a pattern set: MSE (eq. 3) and its root;
     for classification the confusion counts with class 1 as the positive class
     (predicted 1 iff z >= 0, label l = [t >= 0.5]) and the rates the paper
     reports (Sec. 5): accuracy = (TP + TN) / N, completeness = TP / (TP + FN),
     contamination = FP / (TP + FP) (NaN when a denominator is 0)."""
     g = np.asarray(genes, dtype=np.float64)[None, :]
-    r = evaluate(X, t, g, basis, degree, task, bias, Phi)
+    r = evaluate(X, t, g, basis, degree, task, bias, Phi, shared)
     mse = float(r["mse"][0])
     out = dict(mse=mse, rmse=math.sqrt(mse), tp=0, fp=0, tn=0, fn=0, accuracy=math.nan,
                completeness=math.nan, contamination=math.nan)

@@ -247,3 +247,28 @@ def test_metrics_against_sklearn_and_a_hand_example():
     y = model.predict(X, g, "legendre", 4, "regression")
     assert abs(m["rmse"] - np.sqrt(skm.mean_squared_error(t, y))) < 1e-12
     assert m["tp"] == m["fp"] == m["tn"] == m["fn"] == 0 and math.isnan(m["accuracy"])
+
+
+def test_shared_coefficient_form_is_the_literal_polytrigo():
+    # eq. (7): out = a0 + sum_i sum_j [a_j cos(j x_i) + b_j sin(j x_i)], genes
+    # stored [a1..ad, b1..bd, a0]; written out directly as a double sum
+    rng = np.random.default_rng(11)
+    d, f = 3, 11
+    a0, a, b = rng.uniform(-1, 1), rng.uniform(-1, 1, d), rng.uniform(-1, 1, d)
+    X = rng.uniform(-1, 1, (200, f))
+    expect = np.array([a0 + sum(a[j - 1] * math.cos(j * xi) + b[j - 1] * math.sin(j * xi)
+                                for xi in row for j in range(1, d + 1)) for row in X])
+    g = np.concatenate([a, b, [a0]])
+    z = model.pattern_output(X, g, "trig", d, bias=1, shared=True)[:, 0]
+    np.testing.assert_allclose(z, expect, rtol=1e-13, atol=1e-13)
+    # it is the per-feature model with coefficients tied across features
+    G = np.concatenate([np.tile(g[:-1], f), [a0]])
+    np.testing.assert_allclose(model.pattern_output(X, G, "trig", d, bias=1)[:, 0], z,
+                               rtol=1e-13, atol=1e-13)
+    # eq. (5): B * d + 1 genes
+    assert g.size == model.paper_gene_count(d, 2) == 7
+    # the other bases sum Chebyshev / Legendre / power columns the same way
+    for basis in ("chebyshev", "legendre", "power"):
+        Ps = model.design_matrix_shared(X[:5, :4], basis, 4)
+        Pf = model.design_matrix(X[:5, :4], basis, 4)
+        np.testing.assert_allclose(Ps, Pf.reshape(5, 4, 4).sum(axis=1), rtol=1e-14, atol=1e-14)
