@@ -117,7 +117,11 @@ typedef struct {
   int32_t  n_immigrants;    /* the last n_immigrants children of each generation  */
                             /* are random chromosomes instead (the paper's random */
                             /* chromosomes that replace older individuals, Sec. 4)*/
-  int32_t  reserved;        /* must be 0                                          */
+  int32_t  shared;          /* 0: one coefficient per feature and basis function  */
+                            /* (M = F*B*D genes); 1: the paper's literal model,   */
+                            /* one coefficient per basis function shared by all   */
+                            /* features (eq. 2 and eq. 7; M = B*D genes, eq. 5),  */
+                            /* so Phi[n, k] = sum_i phi_{k+1}(x[n, i])            */
   int32_t  max_generations; /* >= 1, used by game_run                             */
   int32_t  rescore_top;     /* 0..8: every generation re-scores the top-k ranked   */
                             /* chromosomes in float32 and tracks the best and     */

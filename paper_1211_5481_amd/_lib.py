@@ -42,7 +42,7 @@ class GameConfig(C.Structure):
         ("selection", C.c_int32),
         ("tournament_k", C.c_int32),
         ("n_immigrants", C.c_int32),
-        ("reserved", C.c_int32),
+        ("shared", C.c_int32),
         ("max_generations", C.c_int32),
         ("rescore_top", C.c_int32),
         ("tile_p", C.c_int32),

@@ -90,7 +90,7 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   if (c->n_features < 1 || c->degree < 1) return bad("n_features and degree must be >= 1");
   if (c->bias != 0 && c->bias != 1) return bad("bias must be 0 or 1");
   if (c->selection < GAME_SEL_TOURNAMENT || c->selection > GAME_SEL_RANKING) return bad("unknown selection");
-  if (c->reserved != 0) return bad("reserved must be 0");
+  if (c->shared != 0 && c->shared != 1) return bad("shared must be 0 or 1");
   if (c->tournament_k < 1 || c->tournament_k > kMaxTournament) return bad("tournament_k must be in [1, 16]");
   auto prob_ok = [](double v) { return std::isfinite(v) && v >= 0.0 && v <= 1.0; };
   if (!prob_ok(c->p_crossover) || !prob_ok(c->p_mutation)) return bad("probabilities must be in [0, 1]");
@@ -100,9 +100,9 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
   if (c->rescore_top < 0 || c->rescore_top > kMaxRescore) return bad("rescore_top must be in [0, 8]");
   const int64_t B = c->basis == GAME_BASIS_TRIG ? 2 : 1;
   const int64_t K = B * c->degree;
-  const int64_t M = (int64_t)c->n_features * K;
+  const int64_t M = c->shared ? K : (int64_t)c->n_features * K;
   const int64_t L = M + c->bias;
-  if (L > kMaxGenes) return bad("too many genes (F * B * D + bias must be <= 4096)");
+  if (L > kMaxGenes) return bad("too many genes (M + bias must be <= 4096)");
   int64_t P = c->pop_size;
   if (P == 0) P = B * c->n_features + 1;  // eq. (4)
   if (P < 1 || P > (1 << 24)) return bad("pop_size out of range");

@@ -1,4 +1,7 @@
 // Basis expansion Phi[n, i*K + k] = phi_{k+1}(x[n, i])  (eq. 1; eq. 6 for trig).
+// In the shared-coefficient model (one coefficient per basis function for all
+// features, eq. 2 and eq. 7) the row holds K values instead,
+// Phi[n, k] = sum_i phi_{k+1}(x[n, i]), summed in double in feature order.
 //
 // The values are computed once per dataset, as the paper does with its sin/cos
 // tables (Sec. 4): inputs never change during training, so only the genes are
@@ -47,12 +50,17 @@ __device__ __forceinline__ bf16_bits to_storage<bf16_bits>(double v) {
   return bf16_bits{(uint16_t)(r >> 16)};
 }
 
+// byte offset of the shared model's accumulators: after the block, 16-aligned
+__host__ __device__ inline size_t acc_offset(int rows, int64_t ld, size_t elem) {
+  return ((size_t)rows * (size_t)ld * elem + 15) & ~(size_t)15;
+}
+
 template <typename XT, typename O>
 __global__ __launch_bounds__(kBasisThreads) void basis_kernel(const XT* __restrict__ X,
                                                               int64_t rows_in, int64_t rows_out,
                                                               int F, int D, int K, int basis,
                                                               int M, int64_t ld, int rows_per_wg,
-                                                              O* __restrict__ phi) {
+                                                              int shared, O* __restrict__ phi) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   O* lds = reinterpret_cast<O*>(lds_raw);
   const int64_t row0 = (int64_t)blockIdx.x * rows_per_wg;
@@ -60,8 +68,23 @@ __global__ __launch_bounds__(kBasisThreads) void basis_kernel(const XT* __restri
   const int rows = (int)min((int64_t)rows_per_wg, rows_out - row0);
   const int tid = threadIdx.x;
 
-  // 1) every (row, feature) pair expands into its K columns in LDS
-  for (int idx = tid; idx < rows * F; idx += kBasisThreads) {
+  // 1) every (row, feature) pair expands into its K columns in LDS; in the
+  //    shared model a thread owns a row and adds its features' expansions
+  //    into double accumulators placed after the block
+  if (shared) {
+    double* acc = reinterpret_cast<double*>(lds_raw + acc_offset(rows_per_wg, ld, sizeof(O)));
+    for (int r = tid; r < rows; r += kBasisThreads) {
+      const int64_t n = row0 + r;
+      double* a = acc + (int64_t)r * K;
+      for (int k = 0; k < K; ++k) a[k] = 0.0;
+      if (n < rows_in)
+        for (int i = 0; i < F; ++i)
+          expand_feature(basis, D, (double)X[n * F + i], [&](int k, double v) { a[k] += v; });
+      O* dst = lds + (int64_t)r * ld;
+      for (int k = 0; k < K; ++k) dst[k] = to_storage<O>(a[k]);
+    }
+  }
+  for (int idx = tid; !shared && idx < rows * F; idx += kBasisThreads) {
     const int r = idx / F, i = idx - r * F;
     const int64_t n = row0 + r;
     O* dst = lds + (int64_t)r * ld + (int64_t)i * K;
@@ -99,18 +122,22 @@ hipError_t launch_typed(const game_config* cfg, const void* X, int64_t rows_in, 
                         void* phi, int64_t ld, hipStream_t s) {
   const int F = cfg->n_features, D = cfg->degree;
   const int K = (cfg->basis == GAME_BASIS_TRIG ? 2 : 1) * D;
-  const int M = F * K;
+  const int shared = cfg->shared;
+  const int M = shared ? K : F * K;
   const int64_t row_bytes = ld * (int64_t)sizeof(O);
-  int rows_per_wg = (int)(kBasisLdsBytes / row_bytes);
+  // the shared model keeps K double accumulators per row (one thread per row)
+  const int64_t acc_bytes = shared ? (int64_t)K * 8 : 0;
+  int rows_per_wg = (int)(kBasisLdsBytes / (row_bytes + acc_bytes));
   if (rows_per_wg < 1) rows_per_wg = 1;
-  if (rows_per_wg > 64) rows_per_wg = 64;
-  const size_t lds = (size_t)rows_per_wg * (size_t)row_bytes;
+  if (rows_per_wg > (shared ? kBasisThreads : 64)) rows_per_wg = shared ? kBasisThreads : 64;
+  const size_t lds = shared ? acc_offset(rows_per_wg, ld, sizeof(O)) + (size_t)rows_per_wg * acc_bytes
+                            : (size_t)rows_per_wg * (size_t)row_bytes;
   const int64_t grid = (rows_out + rows_per_wg - 1) / rows_per_wg;
   if (grid == 0) return hipSuccess;
   if (lds > 65536) return hipErrorInvalidValue;  // a single row larger than LDS allows
   hipLaunchKernelGGL((basis_kernel<XT, O>), dim3((unsigned)grid), dim3(kBasisThreads), lds, s,
                      static_cast<const XT*>(X), rows_in, rows_out, F, D, K, cfg->basis, M, ld,
-                     rows_per_wg, static_cast<O*>(phi));
+                     rows_per_wg, shared, static_cast<O*>(phi));
   return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 // Test and validation use (Sec. 4): one chromosome applied to a pattern set.
 //
 //   prediction: z = sum_i sum_k g[i*K+k] phi_k(x_i) (+ bias gene), output z
-//               (regression) or sigmoid(z) (classification);
+//               (regression) or sigmoid(z) (classification); in the
+//               shared-coefficient model (M == K) feature i uses g[k];
 //   metrics:    squared error summed over the patterns, and for
 //               classification the confusion counts (class 1 positive,
 //               predicted 1 iff z >= 0, label [t >= 0.5]).
@@ -27,7 +28,7 @@ template <typename T>
 __device__ __forceinline__ double pattern_z(const T* __restrict__ X, int64_t n, const PredictArgs& a) {
   double z = a.bias ? (double)a.genes[a.M] : 0.0;
   for (int i = 0; i < a.F; ++i) {
-    const float* g = a.genes + (int64_t)i * a.K;
+    const float* g = a.genes + (a.M == a.K ? 0 : (int64_t)i * a.K);
     expand_feature(a.basis, a.D, (double)X[n * a.F + i],
                    [&](int k, double v) { z = fma(v, (double)g[k], z); });
   }

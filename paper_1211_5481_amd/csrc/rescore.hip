@@ -6,7 +6,10 @@
 // thread walks patterns, recomputes the pattern's basis row from x (double
 // recurrence rounded to float32, as the FP32 path stores Phi), forms
 // z = sum_m phi_m g_m in float32 for every chromosome, and adds the error
-// (eq. 3; classification against the class label) in double.  Block sums
+// (eq. 3; classification against the class label) in double.  In the
+// shared-coefficient model (M == K) a pattern's basis value k is the sum over
+// its features in double, rounded to float32 once, as the FP32 path stores
+// it; the sums are formed eight columns at a time in registers.  Block sums
 // are combined in a fixed order by the last workgroup to arrive, so results
 // are bit-reproducible.  For a population evaluation the same workgroup then
 // tracks the best chromosome by the float32 MSE and applies the stop test.
@@ -66,12 +69,33 @@ __global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
     sse[e] = 0.0;
     mis[e] = 0.0;
   }
+  // shared-coefficient model; with one feature both forms are the same
+  const bool shared = a.M == a.K && a.F > 1;
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   for (int64_t nrow = (int64_t)blockIdx.x * kThreads + tid; nrow < a.N; nrow += stride) {
     float z[kMaxRescore];
 #pragma unroll
     for (int e = 0; e < kMaxRescore; ++e) z[e] = 0.0f;
-    for (int i = 0; i < a.F; ++i) {
+    for (int k0 = 0; shared && k0 < a.K; k0 += 8) {
+      double acc[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+      for (int i = 0; i < a.F; ++i)
+        expand_feature(a.basis, a.D, (double)a.X[nrow * a.F + i], [&](int k, double val) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (k - k0 == q) acc[q] += val;
+        });
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (k0 + q >= a.K) break;
+        const float vf = (float)acc[q];
+#pragma unroll
+        for (int e = 0; e < kMaxRescore; ++e)
+          if (e < a.n) z[e] = fmaf(vf, g_lds[e * a.L + k0 + q], z[e]);
+      }
+    }
+    for (int i = 0; !shared && i < a.F; ++i) {
       const float* gi = g_lds + i * a.K;
       expand_feature(a.basis, a.D, (double)a.X[nrow * a.F + i], [&](int k, double val) {
         const float vf = (float)val;

@@ -25,6 +25,7 @@ class Config:
     task: str = "regression"          # regression | classification
     dtype: str = "f32"                # f64 | f32 | bf16 | f16
     bias: int = 0
+    shared: int = 0                   # 1: one coefficient per basis function for all features
     pop_size: int = 0                 # 0 -> B*F + 1 (eq. 4)
     n_offspring: int = 0
     elitism: int = 2
@@ -60,6 +61,7 @@ class Config:
         c.task = L.TASK[self.task]
         c.dtype = L.DTYPE[self.dtype]
         c.bias = int(self.bias)
+        c.shared = int(self.shared)
         c.pop_size = int(self.pop_size)
         c.n_offspring = int(self.n_offspring)
         c.elitism = int(self.elitism)

@@ -55,6 +55,9 @@ def test_query_derived_sizes():
     st, d = _query(n_features=10, degree=6, basis="trig", dtype="bf16", bias=1, pop_size=0)
     assert (d.M, d.L, d.M_pad, d.P) == (120, 121, 128, 21)     # P = B*F + 1 (eq. 4)
     assert d.workspace_bytes % 256 == 0 and d.workspace_bytes > 0
+    # shared-coefficient model: B*d genes plus a_0 (eq. 5), P = B*F + 1 (eq. 4)
+    st, d = _query(n_features=7, degree=4, basis="trig", dtype="f32", bias=1, shared=1, pop_size=0)
+    assert st == L.GAME_OK and (d.K, d.M, d.L, d.P) == (8, 8, 9, 15)
 
 
 @pytest.mark.parametrize("kw,status", [
@@ -182,5 +185,5 @@ def test_selection_and_immigrant_validation():
     c.selection = 3
     assert L.lib().game_query(C.byref(c), C.byref(L.GameDims())) == L.GAME_E_INVALID
     c.selection = 0
-    c.reserved = 1
+    c.shared = 2
     assert L.lib().game_query(C.byref(c), C.byref(L.GameDims())) == L.GAME_E_INVALID
