@@ -68,7 +68,7 @@ struct game_ctx {
   double *emse = nullptr, *emis = nullptr, *efit = nullptr, *snap = nullptr;
   float *prm = nullptr, *am = nullptr, *av = nullptr;
   int32_t* step = nullptr;
-  float *WT = nullptr, *slab = nullptr;
+  float *WT = nullptr, *mscr = nullptr;
   float *buf = nullptr, *bufy = nullptr, *log = nullptr;
   SurState* sst = nullptr;
 };
@@ -142,8 +142,6 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
     p->P_eval = p->k_sel + p->audit;
     if (c->surrogate == GAME_SURROGATE_MLP) {
       if (c->surrogate_hidden < 16 || c->surrogate_hidden > 1024) return bad("surrogate_hidden must be in [16, 1024]");
-      if (!mlp_fits(MlpDims{(int)L, c->surrogate_hidden, c->surrogate_hidden}))
-        return bad("surrogate_hidden too large for this gene count");
       if (c->surrogate_batch < 1 || c->surrogate_batch > 8192) return bad("surrogate_batch must be in [1, 8192]");
       if (c->surrogate_buffer < c->surrogate_batch) return bad("surrogate_buffer must be >= surrogate_batch");
       if (c->surrogate_buffer > (1 << 24)) return bad("surrogate_buffer too large");
@@ -253,9 +251,9 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
       p->off_am = take(np * 4);
       p->off_av = take(np * 4);
       p->off_step = take(16);
-      p->off_WT = take(((size_t)L * p->H + (size_t)p->H * p->H) * 4);
-      p->slab_cap = mlp_slab_floats(md, p->batch);
-      p->off_slab = take((size_t)p->slab_cap * 4);
+      p->off_WT = take((size_t)p->H * p->H * 4);
+      p->mlp_scratch = mlp_scratch_floats(md, p->batch, p->rows_max);
+      p->off_mscr = take((size_t)p->mlp_scratch * 4);
       p->off_buf = take((size_t)p->cap * Lz * 4);
       p->off_bufy = take((size_t)p->cap * 4);
     }
@@ -452,7 +450,7 @@ game_status enqueue_train(game_ctx* c, hipStream_t s) {
     GAME_TRY(dev(c,
                  mlp_train_step(d, c->prm, c->WT, c->am, c->av, c->step, (float)c->cfg.surrogate_lr,
                                 c->buf, c->bufy, c->sst, c->cfg.seed, p.batch, p.n_recent, p.cap,
-                                c->slab, p.slab_cap, c->loss, c->state, s),
+                                c->mscr, c->loss, c->state, s),
                  "mlp train"));
   return GAME_OK;
 }
@@ -506,7 +504,7 @@ game_status enqueue_offspring_generation(game_ctx* c, hipStream_t s) {
   const int* sel = nullptr;
   if (p.sur == GAME_SURROGATE_MLP) {
     GAME_TRY(dev(c,
-                 mlp_forward(mlp_dims(c), c->prm, c->WT, c->O, p.n_off, c->yhat, st, s),
+                 mlp_forward(mlp_dims(c), c->prm, c->WT, c->O, p.n_off, c->yhat, c->mscr, st, s),
                  "mlp forward"));
     GAME_TRY(dev(c, sur_keys(0, c->yhat, nullptr, p.n_off, 0, st, c->cfg.seed, c->keys, s), "keys"));
     GAME_TRY(dev(c, sur_select(c->keys, p.n_off, k, c->sel, st, s), "prescreen"));
@@ -726,7 +724,7 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
       c->av = F(p.off_av);
       c->step = reinterpret_cast<int32_t*>(c->ws + p.off_step);
       c->WT = F(p.off_WT);
-      c->slab = F(p.off_slab);
+      c->mscr = F(p.off_mscr);
       c->buf = F(p.off_buf);
       c->bufy = F(p.off_bufy);
     }
@@ -952,7 +950,8 @@ game_status game_mlp_params(game_ctx* c, float* params, int32_t dir) {
 game_status game_mlp_forward(game_ctx* c, const float* X, int32_t n, float* y) {
   GAME_TRY(need_mlp(c));
   if (!X || !y || n < 1 || n > c->plan.rows_max) return fail(GAME_E_INVALID, "n must be in [1, %d]", c->plan.rows_max);
-  return dev(c, mlp_forward(mlp_dims(c), c->prm, c->WT, X, n, y, nullptr, c->stream), "mlp forward");
+  return dev(c, mlp_forward(mlp_dims(c), c->prm, c->WT, X, n, y, c->mscr, nullptr, c->stream),
+             "mlp forward");
 }
 
 game_status game_mlp_grads(game_ctx* c, const float* X, const float* target, int32_t n, float* grads,
@@ -961,8 +960,8 @@ game_status game_mlp_grads(game_ctx* c, const float* X, const float* target, int
   if (!X || !target || !grads || n < 1 || n > c->plan.batch)
     return fail(GAME_E_INVALID, "n must be in [1, %d]", c->plan.batch);
   return dev(c,
-             mlp_grads(mlp_dims(c), c->prm, c->WT, X, target, n, c->slab, c->plan.slab_cap, grads, loss,
-                       nullptr, c->stream),
+             mlp_grads(mlp_dims(c), c->prm, c->WT, X, target, n, c->mscr, grads, loss, nullptr,
+                       c->stream),
              "mlp grads");
 }
 

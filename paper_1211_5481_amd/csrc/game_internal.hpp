@@ -128,10 +128,10 @@ struct Plan {
   // offspring form (n_offspring != P - E, or a prescreen)
   bool offspring;
   int k_sel, audit, P_eval, sur, H, cap, steps, batch, n_recent, rows_max;
-  int64_t slab_cap;            // floats of MLP partial-gradient slabs
+  int64_t mlp_scratch;         // floats of MLP activation scratch
   size_t off_O, off_keys, off_sel, off_aud, off_surv, off_evg, off_emse, off_emis, off_efit;
   size_t off_snap, off_yhat, off_rho, off_loss, off_prm, off_am, off_av, off_step;
-  size_t off_WT, off_slab, off_buf, off_bufy, off_sst, off_log;
+  size_t off_WT, off_mscr, off_buf, off_bufy, off_sst, off_log;
   size_t total;
 };
 constexpr int kLogCap = 4096;  // generations of surrogate statistics kept
@@ -254,29 +254,27 @@ struct MlpDims {
 struct MlpLayout {  // offsets into the flat parameter array
   int64_t W1, b1, W2, b2, w3, b3, total;
 };
-constexpr int64_t kMlpSlabFloats = int64_t(1) << 24;  // partial-gradient slabs, at most
 MlpLayout mlp_layout(int L, int H1, int H2);
-int mlp_rows_per_pass(const MlpDims& d);      // rows a workgroup takes per pass
-bool mlp_fits(const MlpDims& d);              // one row's activations fit in LDS
-int64_t mlp_slab_floats(const MlpDims& d, int rows);  // slab space a batch of rows uses
-// WT: transposed copies of W1 (L x H1) and W2 (H1 x H2), kept in step with the parameters
-hipError_t mlp_transpose(const MlpDims& d, const float* params, float* WT, hipStream_t s);
-hipError_t mlp_init(const MlpDims& d, float* params, float* m, float* v, float* WT, uint64_t seed,
+// activation scratch (floats) for training steps of `batch` rows and forward
+// passes of up to `rows_max` rows
+int64_t mlp_scratch_floats(const MlpDims& d, int batch, int rows_max);
+// W2T: transposed copy of W2 (H1 x H2), kept in step with the parameters
+hipError_t mlp_transpose(const MlpDims& d, const float* params, float* W2T, hipStream_t s);
+hipError_t mlp_init(const MlpDims& d, float* params, float* m, float* v, float* W2T, uint64_t seed,
                     hipStream_t s);
 // halt: kernels return at once once a run has stopped (may be null)
-hipError_t mlp_forward(const MlpDims& d, const float* params, const float* WT, const float* X, int B,
-                       float* y, const DevState* halt, hipStream_t s);
-hipError_t mlp_grads(const MlpDims& d, const float* params, const float* WT, const float* X,
-                     const float* target, int B, float* slab, int64_t slab_cap, float* grads,
-                     float* loss, const DevState* halt, hipStream_t s);
+hipError_t mlp_forward(const MlpDims& d, const float* params, const float* W2T, const float* X, int B,
+                       float* y, float* scratch, const DevState* halt, hipStream_t s);
+hipError_t mlp_grads(const MlpDims& d, const float* params, const float* W2T, const float* X,
+                     const float* target, int B, float* scratch, float* grads, float* loss,
+                     const DevState* halt, hipStream_t s);
 // one Adam step on a minibatch drawn from the replay ring (step[0]: steps
 // taken, step[1]: arrival counter, zero between launches)
-hipError_t mlp_train_step(const MlpDims& d, float* params, float* WT, float* m, float* v,
+hipError_t mlp_train_step(const MlpDims& d, float* params, float* W2T, float* m, float* v,
                           int32_t* step, float lr, const float* buf, const float* bufy,
                           const SurState* ss, uint64_t seed, int B, int n_recent, int cap,
-                          float* slab, int64_t slab_cap, float* loss, const DevState* halt,
-                          hipStream_t s);
-hipError_t mlp_adam(const MlpDims& d, float* params, float* WT, const float* grads, float* m, float* v,
+                          float* scratch, float* loss, const DevState* halt, hipStream_t s);
+hipError_t mlp_adam(const MlpDims& d, float* params, float* W2T, const float* grads, float* m, float* v,
                     int32_t* step, float lr, const DevState* halt, hipStream_t s);
 
 // ------------------------------------------------------ test / validation use

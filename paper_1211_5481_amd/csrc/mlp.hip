@@ -2,21 +2,32 @@
 // online with Adam (Kingma and Ba) on (chromosome, standardised log MSE)
 // pairs.  GELU is the exact form a * Phi(a) = a (1 + erf(a / sqrt 2)) / 2.
 //
-// The network is small (L = 128 inputs, H = 256 hidden at the surrogate
-// workload) and trained in many short steps, so a training step is two
-// launches instead of one per product:
-//   * rows kernel: a workgroup takes R minibatch rows at a time, draws them
-//     from the replay ring (or reads given rows), runs the forward pass and
-//     the whole backward pass for them in LDS and registers, and adds the
-//     rows' gradient contributions to its own slab of partial sums (the
-//     parameter layout plus the loss);
-//   * reduce kernel: one thread per parameter adds the slabs in workgroup
-//     order and applies Adam (or writes the gradient); the last workgroup to
-//     finish advances the step counter.
-// Every sum has a fixed order, so results are bit-reproducible.  Forward
-// products read transposed copies of W1 and W2 (kept in step with every
-// parameter update) so that lanes over output units load contiguous memory;
-// the backward product through W2 reads W2 itself for the same reason.
+// Every product of a forward pass or of a training step is a dense
+// contraction and runs on the matrix cores (v_mfma_f32_16x16x4f32: float32
+// operands and accumulation).  A training step on B minibatch rows is four
+// launches:
+//   layer 1: A1 = X W1^T + b1, H1 = gelu(A1), in tiles of 32 rows x 32 units;
+//            the rows are drawn from the replay ring by the counter-based
+//            generator, or read from a given matrix;
+//   layer 2: A2 = H1 W2^T + b2, and every tile's share of the head gelu(A2) w3;
+//   back:    y = head + b3, dy = 2 (y - t) / B, dA2 = dy w3 gelu'(A2),
+//            dA1 = (dA2 W2) gelu'(A1) (the layers store gelu' of their
+//            pre-activations, so each is evaluated once);
+//   grads:   dW1 = dA1^T X, dW2 = dA2^T H1, db1, db2, dw3 = H2^T dy, db3 and the
+//            loss, all products over the B rows.  Each workgroup owns a tile
+//            of parameters and applies Adam to it (or writes the gradient):
+//            no partial-sum slabs, no atomics on values; the last workgroup
+//            to finish advances the step counter.
+// A forward pass alone is layer 1, layer 2 and a head sum.
+//
+// Every operand is read with the contraction index contiguous, as 16-byte
+// vectors: the layers store activations row-major and also transposed (batch
+// rows contiguous) for the parameter-gradient products, which contract over
+// rows; W2 is kept transposed as well (W2T, H1 x H2) for the product dA2 W2.
+// A workgroup's waves (4; 16 for the gradient products, which contract over
+// all B rows) take interleaved 16-wide slices of the contraction and add
+// their 32 x 32 partial tiles in wave order, so every result has a fixed
+// summation order and is bit-reproducible.
 //
 // Parameters are one flat float32 array: W1 (H1 x L), b1 (H1), W2 (H2 x H1),
 // b2 (H2), w3 (H2), b3 (1); gradients and Adam moments use the same layout.
@@ -31,9 +42,10 @@
 namespace game {
 namespace {
 
-constexpr int kThreads = 1024;
-constexpr int kMaxR = 8;            // rows per workgroup pass (registers)
-constexpr size_t kRowsLds = 98304;  // LDS budget of the rows kernel
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;  // four waves
+constexpr int kT = 32;         // tile edge
 
 __device__ __forceinline__ float gelu(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float a) {
@@ -42,10 +54,120 @@ __device__ __forceinline__ float gelu_grad(float a) {
   return cdf + a * pdf;
 }
 
-struct RowsArgs {
-  const float* params;
-  const float* WT;  // W1^T (L x H1) then W2^T (H1 x H2)
-  int L, H1, H2, B, R, W;
+constexpr int64_t round4(int64_t n) { return (n + 3) & ~int64_t(3); }
+
+// Activations of one step (floats; B4 = B rounded up to 4, ld1/ld2 the hidden
+// widths rounded up to 4).  Row-major: Hd1 (B x ld1), G2 = gelu'(A2)
+// (B x ld2), ypart (B x nT2 head shares).  Transposed, batch rows contiguous
+// (ld B4): XT (L), G1T = gelu'(A1), Hd1T, D1T (H1), Hd2T, D2T (H2), dyres (dy
+// then squared residuals).  tv: standardised targets; ones: 1 for rows < B.
+struct Scratch {
+  float *Hd1, *ypart, *XT, *tv, *ones, *G1T, *Hd1T, *G2, *Hd2T, *dyres, *D2T, *D1T;
+  int B4, ld1, ld2, nT2;
+};
+
+// Lays the scratch out from `base` (null: sizes only); returns the floats
+// used.  A forward pass needs only Hd1 and ypart, which come first.
+int64_t scratch_layout(const MlpDims& d, int B, bool train, float* base, Scratch* s) {
+  Scratch z{};
+  z.B4 = (int)round4(B);
+  z.ld1 = (int)round4(d.H1);
+  z.ld2 = (int)round4(d.H2);
+  z.nT2 = (d.H2 + kT - 1) / kT;
+  int64_t o = 0;
+  auto take = [&](int64_t n) {
+    float* p = base ? base + o : nullptr;
+    o += round4(n);
+    return p;
+  };
+  const int64_t B4 = z.B4;
+  z.Hd1 = take(B4 * z.ld1);
+  z.ypart = take(B4 * z.nT2);
+  if (train) {
+    z.XT = take((int64_t)d.L * B4);
+    z.tv = take(B4);
+    z.ones = take(B4);
+    z.G1T = take((int64_t)d.H1 * B4);
+    z.Hd1T = take((int64_t)d.H1 * B4);
+    z.G2 = take(B4 * z.ld2);
+    z.Hd2T = take((int64_t)d.H2 * B4);
+    z.dyres = take(2 * B4);
+    z.D2T = take((int64_t)d.H2 * B4);
+    z.D1T = take((int64_t)d.H1 * B4);
+  }
+  if (s) *s = z;
+  return o;
+}
+
+// Four consecutive k of one operand row, zero past K or for a missing row.
+__device__ __forceinline__ v4f load4(const float* row, int k, int K, bool vec) {
+  v4f v = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (!row) return v;
+  if (vec && k + 3 < K) return *reinterpret_cast<const v4f*>(row + k);
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    if (k + s < K) v[s] = row[k + s];
+  return v;
+}
+
+__device__ __forceinline__ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// C (32 x 32) = sum_{k < K} A(m, k) B(n, k) with NW waves.  Wave w takes the
+// 16-wide k groups w, w + NW, ...; in a group, lane (i, q) supplies rows i and
+// 16 + i of both operands at k = 4q .. 4q + 3 (fa / fb return those four
+// values), one MFMA per k of the four, so every k of the group is used
+// exactly once.  The waves' partial tiles go to `red` (NW x 4 x 64 v4f,
+// 4 KiB per wave).
+template <int NW, class FA, class FB>
+__device__ __forceinline__ void tile_product(int K, FA fa, FB fb, v4f* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  v4f acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = wave * 16; k0 < K; k0 += 16 * NW) {
+    const int k = k0 + 4 * q;
+    const v4f a0 = fa(i, k), a1 = fa(16 + i, k);
+    const v4f b0 = fb(i, k), b1 = fb(16 + i, k);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], b0[s], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], b1[s], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], b0[s], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], b1[s], acc[1][1], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) red[(wave * 4 + bi * 2 + bj) * 64 + lane] = acc[bi][bj];
+  __syncthreads();
+}
+
+// Thread t < 256's share of the tile after tile_product: block t / 64 =
+// (bi, bj), accumulator lane t % 64, i.e. rows m0 .. m0 + 3 (m0 = 16 bi +
+// 4 (lane / 16)) of column n = 16 bj + lane % 16, the waves' partials added in
+// wave order.  Threads from 256 on hold nothing (n = kT).
+struct TileOut {
+  int m0, n;
+  v4f v;
+};
+template <int NW>
+__device__ __forceinline__ TileOut tile_sum(const v4f* red) {
+  if (threadIdx.x >= 256) return TileOut{0, kT, v4f{0.0f, 0.0f, 0.0f, 0.0f}};
+  const int blk = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  v4f v = red[blk * 64 + lane];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) v += red[(w * 4 + blk) * 64 + lane];
+  return TileOut{16 * (blk >> 1) + 4 * (lane >> 4), 16 * (blk & 1) + (lane & 15), v};
+}
+
+struct Args {
+  const float* P;    // parameters
+  const float* W2T;  // H1 x H2
+  int L, H1, H2, B;
   // rows: explicit (X, target) or drawn from the replay ring
   const float* X;
   const float* target;
@@ -55,301 +177,363 @@ struct RowsArgs {
   const int32_t* step;
   uint32_t k0, k1;
   int n_recent, cap;
-  float* y;       // forward only: scores of the B rows
-  float* slab;    // training: W slabs of (parameters + 1) floats
-  int64_t total;  // parameters
+  Scratch s;
+  float* y;  // forward: scores of the B rows
 };
 
-// Thread layout of the rows kernel: 1024 threads = 4 groups (ks) of 256
-// column lanes (c).  A product over K is split into 4 contiguous K quarters,
-// one per group; the quarters' partial sums are added in group order.
-constexpr int kLanes = 256, kGroups = kThreads / kLanes;
-
-// Partial dot products of column j (lane stride kLanes) over K quarter ks:
-// acc[r] = sum_{k in quarter} W[k * ldw + j] * V[r * ldv + k], r < R.
-__device__ __forceinline__ void quarter_dot(const float* __restrict__ W, int64_t ldw, int j,
-                                            const float* V, int ldv, int K, int ks, int R,
-                                            float (&acc)[kMaxR]) {
-#pragma unroll
-  for (int r = 0; r < kMaxR; ++r) acc[r] = 0.0f;
-  const int q = (K + kGroups - 1) / kGroups;
-  const int k0 = ks * q, k1 = min(K, k0 + q);
-  int k = k0;
-  if (((k0 | q | ldv) & 3) == 0 && (reinterpret_cast<uintptr_t>(V) & 15) == 0) {
-    for (; k + 4 <= k1; k += 4) {
-      float w[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) w[u] = W[(int64_t)(k + u) * ldw + j];
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r)
-        if (r < R) {
-          const float4 v = *reinterpret_cast<const float4*>(&V[r * ldv + k]);
-          acc[r] = fmaf(w[0], v.x, acc[r]);
-          acc[r] = fmaf(w[1], v.y, acc[r]);
-          acc[r] = fmaf(w[2], v.z, acc[r]);
-          acc[r] = fmaf(w[3], v.w, acc[r]);
-        }
-    }
-  }
-  for (; k < k1; ++k) {
-    const float w = W[(int64_t)k * ldw + j];
-#pragma unroll
-    for (int r = 0; r < kMaxR; ++r)
-      if (r < R) acc[r] = fmaf(w, V[r * ldv + k], acc[r]);
-  }
+struct Offs {
+  int64_t W1, b1, W2, b2, w3, b3;
+};
+__host__ __device__ __forceinline__ Offs offs(int L, int H1, int H2) {
+  Offs o;
+  o.W1 = 0;
+  o.b1 = (int64_t)H1 * L;
+  o.W2 = o.b1 + H1;
+  o.b2 = o.W2 + (int64_t)H2 * H1;
+  o.w3 = o.b2 + H2;
+  o.b3 = o.w3 + H2;
+  return o;
 }
 
+// Layer 1: tile (row tile blockIdx.y, unit tile blockIdx.x).  The first unit
+// tile also stores the rows' transposed inputs, targets and ones.
 template <bool kTrain>
-__global__ __launch_bounds__(kThreads) void rows_kernel(RowsArgs a, const DevState* halt) {
+__global__ __launch_bounds__(kThreads) void layer1_kernel(Args a, const DevState* halt) {
   if (run_halted(halt)) return;
-  extern __shared__ __align__(16) float sm[];
-  const int L = a.L, H1 = a.H1, H2 = a.H2, R = a.R;
-  const int Hm = H1 > H2 ? H1 : H2;
-  float* X = sm;              // R x L
-  float* A1 = X + R * L;      // R x H1 pre-activations
-  float* Hd1 = A1 + R * H1;   // R x H1 activations
-  float* D1 = Hd1 + R * H1;   // R x H1: dLoss/dA1
-  float* A2 = D1 + R * H1;    // R x H2
-  float* Hd2 = A2 + R * H2;   // R x H2
-  float* D2 = Hd2 + R * H2;   // R x H2: dLoss/dA2
-  float* red = D2 + R * H2;   // kGroups x R x Hm quarter sums
-  __shared__ float s_t[kMaxR], s_y[kMaxR], s_dy[kMaxR];
-  __shared__ int s_slot[kMaxR];
-  const int tid = threadIdx.x, c = tid % kLanes, ks = tid / kLanes;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int64_t oW1 = 0, ob1 = (int64_t)H1 * L, oW2 = ob1 + H1, ob2 = oW2 + (int64_t)H2 * H1,
-                ow3 = ob2 + H2, ob3 = ow3 + H2;
-  const float* P = a.params;
-  const float* W1T = a.WT;
-  const float* W2T = a.WT + (int64_t)L * H1;
-  float* slab = kTrain ? a.slab + (int64_t)blockIdx.x * (a.total + 1) : nullptr;
-  bool first = true;
-  auto put = [&](int64_t o, float v) { slab[o] = first ? v : slab[o] + v; };
-  // quarter sums of the columns this thread owns -> red[ks][r][j]
-  auto to_red = [&](int j, const float (&acc)[kMaxR]) {
-#pragma unroll
-    for (int r = 0; r < kMaxR; ++r)
-      if (r < R) red[(ks * R + r) * Hm + j] = acc[r];
-  };
-  auto quarters = [&](int r, int j) {
-    float t = 0.0f;
-    for (int g = 0; g < kGroups; ++g) t += red[(g * R + r) * Hm + j];
-    return t;
-  };
-
-  for (int r0 = blockIdx.x * R; r0 < a.B; r0 += a.W * R) {
-    const int nr = min(R, a.B - r0);
-    // ---- rows and targets
-    if (tid < nr) {
-      if (a.X == nullptr) {
-        const int i = r0 + tid;
-        const uint32_t w = philox((uint32_t)*a.step, (uint32_t)i, 0u, kTagMinibatch, a.k0, a.k1).x;
-        int slot;
-        if (i < a.B - a.n_recent) {
+  __shared__ v4f red[16 * 64];
+  __shared__ int s_slot[kT];
+  const Scratch& S = a.s;
+  const int c0 = blockIdx.x * kT, r0 = blockIdx.y * kT, tid = threadIdx.x, L = a.L;
+  const bool lead = kTrain && blockIdx.x == 0;
+  if (tid < kT) {
+    const int r = r0 + tid;
+    int slot = -1;
+    if (r < a.B) {
+      if (a.X) {
+        slot = r;
+      } else {
+        const uint32_t w = philox((uint32_t)*a.step, (uint32_t)r, 0u, kTagMinibatch, a.k0, a.k1).x;
+        if (r < a.B - a.n_recent) {
           slot = (int)__umulhi(w, (uint32_t)a.ss->count);
         } else {
           const int back = (int)__umulhi(w, (uint32_t)a.ss->last);
           slot = (int)(((int64_t)a.ss->head - 1 - back + a.cap) % a.cap);
         }
-        s_slot[tid] = slot;
-        if (kTrain) s_t[tid] = (a.bufy[slot] - a.ss->mu) / a.ss->sigma;
-      } else if (kTrain) {
-        s_t[tid] = a.target[r0 + tid];
       }
     }
-    __syncthreads();
-    for (int r = 0; r < R; ++r)
-      for (int l = tid; l < L; l += kThreads) {
-        float v = 0.0f;
-        if (r < nr) v = a.X ? a.X[(int64_t)(r0 + r) * L + l] : a.buf[(int64_t)s_slot[r] * L + l];
-        X[r * L + l] = v;
+    s_slot[tid] = slot;
+    if (lead && r < S.B4) {
+      float t = 0.0f, one = 0.0f;
+      if (r < a.B) {
+        t = a.X ? a.target[r] : (a.bufy[slot] - a.ss->mu) / a.ss->sigma;
+        one = 1.0f;
       }
-    __syncthreads();
-    // ---- layer 1: A1 = X W1^T + b1
-    for (int j = c; j < H1; j += kLanes) {
-      float acc[kMaxR];
-      quarter_dot(W1T, H1, j, X, L, L, ks, R, acc);
-      to_red(j, acc);
+      S.tv[r] = t;
+      S.ones[r] = one;
     }
-    __syncthreads();
-    for (int e = tid; e < R * H1; e += kThreads) {
-      const int r = e / H1, j = e - r * H1;
-      const float pre = P[ob1 + j] + quarters(r, j);
-      A1[e] = pre;
-      Hd1[e] = gelu(pre);
-    }
-    __syncthreads();
-    // ---- layer 2: A2 = H1 W2^T + b2
-    for (int j = c; j < H2; j += kLanes) {
-      float acc[kMaxR];
-      quarter_dot(W2T, H2, j, Hd1, H1, H1, ks, R, acc);
-      to_red(j, acc);
-    }
-    __syncthreads();
-    for (int e = tid; e < R * H2; e += kThreads) {
-      const int r = e / H2, j = e - r * H2;
-      const float pre = P[ob2 + j] + quarters(r, j);
-      A2[e] = pre;
-      Hd2[e] = gelu(pre);
-    }
-    __syncthreads();
-    // ---- head: y = H2 w3 + b3, wave r sums row r (fixed order)
-    if (wave < R) {
-      float y = 0.0f;
-      for (int j = lane; j < H2; j += 64) y = fmaf(Hd2[wave * H2 + j], P[ow3 + j], y);
-      for (int off = 32; off > 0; off >>= 1) y += __shfl_xor(y, off);
-      if (lane == 0) s_y[wave] = y + P[ob3];
-    }
-    __syncthreads();
-    if (!kTrain) {
-      if (tid < nr) a.y[r0 + tid] = s_y[tid];
-      __syncthreads();
-      continue;
-    }
-    // ---- loss and output gradient: residual = y - t, dy = 2 residual / B
-    if (tid < kMaxR) {
-      const float res = tid < nr ? s_y[tid] - s_t[tid] : 0.0f;
-      s_dy[tid] = 2.0f * res / (float)a.B;
-      s_y[tid] = res * res;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      float dsum = 0.0f, lsum = 0.0f;
-      for (int r = 0; r < nr; ++r) {
-        dsum += s_dy[r];
-        lsum += s_y[r];
-      }
-      put(ob3, dsum);
-      put(a.total, lsum);
-    }
-    // ---- dA2 = dy w3 gelu'(A2)
-    for (int e = tid; e < R * H2; e += kThreads) {
-      const int r = e / H2, j = e - r * H2;
-      D2[e] = s_dy[r] * P[ow3 + j] * gelu_grad(A2[e]);  // zero for rows past the batch
-    }
-    __syncthreads();
-    // ---- gradients of w3 and b2
-    for (int j = tid; j < H2; j += kThreads) {
-      float gw3 = 0.0f, gb2 = 0.0f;
-      for (int r = 0; r < R; ++r) {
-        gw3 = fmaf(Hd2[r * H2 + j], s_dy[r], gw3);
-        gb2 += D2[r * H2 + j];
-      }
-      put(ow3 + j, gw3);
-      put(ob2 + j, gb2);
-    }
-    // ---- gradient of W2: dA2^T H1 (rows j by group, columns i by lane)
-    for (int j = ks; j < H2; j += kGroups)
-      for (int i = c; i < H1; i += kLanes) {
-        float g = 0.0f;
-        for (int r = 0; r < R; ++r) g = fmaf(D2[r * H2 + j], Hd1[r * H1 + i], g);
-        put(oW2 + (int64_t)j * H1 + i, g);
-      }
-    // ---- dA1 = (dA2 W2) gelu'(A1): quarter sums over j
-    for (int i = c; i < H1; i += kLanes) {
-      float acc[kMaxR];
-      quarter_dot(P + oW2, H1, i, D2, H2, H2, ks, R, acc);
-      to_red(i, acc);
-    }
-    __syncthreads();
-    for (int e = tid; e < R * H1; e += kThreads) {
-      const int r = e / H1, i = e - r * H1;
-      D1[e] = quarters(r, i) * gelu_grad(A1[e]);
-    }
-    __syncthreads();
-    // ---- gradient of b1, and of W1: dA1^T X
-    for (int i = tid; i < H1; i += kThreads) {
-      float gb1 = 0.0f;
-      for (int r = 0; r < R; ++r) gb1 += D1[r * H1 + i];
-      put(ob1 + i, gb1);
-    }
-    for (int i = ks; i < H1; i += kGroups)
-      for (int l = c; l < L; l += kLanes) {
-        float g = 0.0f;
-        for (int r = 0; r < R; ++r) g = fmaf(D1[r * H1 + i], X[r * L + l], g);
-        put(oW1 + (int64_t)i * L + l, g);
-      }
-    first = false;
-    __syncthreads();
   }
-  // a workgroup without rows contributes zeros
-  if (kTrain && first)
-    for (int64_t e = tid; e <= a.total; e += kThreads) slab[e] = 0.0f;
+  __syncthreads();
+  const float* src = a.X ? a.X : a.buf;
+  const bool vx = (L & 3) == 0 && aligned16(src);
+  auto fa = [&](int m, int k) {
+    const int slot = s_slot[m];
+    const v4f v = load4(slot >= 0 ? src + (int64_t)slot * L : nullptr, k, L, vx);
+    if (lead && slot >= 0) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (k + s < L) S.XT[(int64_t)(k + s) * S.B4 + r0 + m] = v[s];
+    }
+    return v;
+  };
+  const bool vw = (L & 3) == 0;  // W1 starts the parameter array
+  auto fb = [&](int n, int k) {
+    const int h = c0 + n;
+    return load4(h < a.H1 ? a.P + (int64_t)h * L : nullptr, k, L, vw);
+  };
+  tile_product<4>(L, fa, fb, red);
+  const TileOut o = tile_sum<4>(red);
+  const int h = c0 + o.n, r = r0 + o.m0;
+  if (h < a.H1 && r < S.B4) {
+    const float b1 = a.P[(int64_t)a.H1 * L + h];
+    v4f act, der;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool ok = r + q < a.B;
+      const float pre = o.v[q] + b1;
+      act[q] = ok ? gelu(pre) : 0.0f;
+      der[q] = ok && kTrain ? gelu_grad(pre) : 0.0f;
+      if (ok) S.Hd1[(int64_t)(r + q) * S.ld1 + h] = act[q];
+    }
+    if (kTrain) {
+      *reinterpret_cast<v4f*>(S.G1T + (int64_t)h * S.B4 + r) = der;
+      *reinterpret_cast<v4f*>(S.Hd1T + (int64_t)h * S.B4 + r) = act;
+    }
+  }
 }
 
-struct ReduceArgs {
-  const float* slab;  // W slabs, `stride` floats apart
-  int W;
-  int64_t stride, total;
-  int B;          // rows behind the sums (loss = sum / B)
-  float* grads;   // gradient output (null: Adam)
-  float* loss;    // loss output (null: none; the slabs then have no loss entry)
-  float* params;  // Adam
-  float* WT;
+// Layer 2 and the tile's share of the head: ypart[r][unit tile] = sum over
+// the tile's units j (in order) of gelu(A2[r][j]) w3[j].
+template <bool kTrain>
+__global__ __launch_bounds__(kThreads) void layer2_kernel(Args a, const DevState* halt) {
+  if (run_halted(halt)) return;
+  __shared__ v4f red[16 * 64];
+  __shared__ float s_h[kT][kT + 1];
+  const Scratch& S = a.s;
+  const int c0 = blockIdx.x * kT, r0 = blockIdx.y * kT, tid = threadIdx.x, H1 = a.H1;
+  const Offs po = offs(a.L, H1, a.H2);
+  auto fa = [&](int m, int k) {
+    const int r = r0 + m;
+    return load4(r < a.B ? S.Hd1 + (int64_t)r * S.ld1 : nullptr, k, H1, true);
+  };
+  const float* W2 = a.P + po.W2;
+  const bool vw = ((po.W2 | H1) & 3) == 0;
+  auto fb = [&](int n, int k) {
+    const int j = c0 + n;
+    return load4(j < a.H2 ? W2 + (int64_t)j * H1 : nullptr, k, H1, vw);
+  };
+  tile_product<4>(H1, fa, fb, red);
+  const TileOut o = tile_sum<4>(red);
+  const int j = c0 + o.n, r = r0 + o.m0;
+  const bool jok = j < a.H2;
+  const float b2 = jok ? a.P[po.b2 + j] : 0.0f, w3 = jok ? a.P[po.w3 + j] : 0.0f;
+  v4f act;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const bool ok = jok && r + q < a.B;
+    const float pre = o.v[q] + b2;
+    act[q] = ok ? gelu(pre) : 0.0f;
+    s_h[o.m0 + q][o.n] = act[q] * w3;
+    if (kTrain && ok) S.G2[(int64_t)(r + q) * S.ld2 + j] = gelu_grad(pre);
+  }
+  if (kTrain && jok && r < S.B4) *reinterpret_cast<v4f*>(S.Hd2T + (int64_t)j * S.B4 + r) = act;
+  __syncthreads();
+  if (tid < kT && r0 + tid < a.B) {
+    float sum = 0.0f;
+    for (int n = 0; n < kT; ++n) sum += s_h[tid][n];
+    S.ypart[(int64_t)(r0 + tid) * S.nT2 + blockIdx.x] = sum;
+  }
+}
+
+// y = sum of the head shares in tile order + b3.
+__device__ __forceinline__ float head_sum(const Args& a, int r) {
+  const float* yp = a.s.ypart + (int64_t)r * a.s.nT2;
+  float y = 0.0f;
+  for (int t = 0; t < a.s.nT2; ++t) y += yp[t];
+  return y + a.P[offs(a.L, a.H1, a.H2).b3];
+}
+
+__global__ __launch_bounds__(kThreads) void head_kernel(Args a, const DevState* halt) {
+  if (run_halted(halt)) return;
+  const int r = blockIdx.x * kThreads + threadIdx.x;
+  if (r < a.B) a.y[r] = head_sum(a, r);
+}
+
+// Backward through the head and W2: tile (row tile blockIdx.y, layer-1 unit
+// tile blockIdx.x) of dA1 = (dA2 W2) gelu'(A1), with dA2 formed as the left
+// operand is read; the first unit tile also stores dA2 (transposed), dy and
+// the squared residuals.
+__global__ __launch_bounds__(kThreads) void back_kernel(Args a, const DevState* halt) {
+  if (run_halted(halt)) return;
+  __shared__ v4f red[16 * 64];
+  __shared__ float s_dy[kT];
+  const Scratch& S = a.s;
+  const int c0 = blockIdx.x * kT, r0 = blockIdx.y * kT, tid = threadIdx.x, H2 = a.H2;
+  const bool lead = blockIdx.x == 0;
+  if (tid < kT) {
+    const int r = r0 + tid;
+    float dy = 0.0f;
+    if (r < a.B) {
+      const float res = head_sum(a, r) - S.tv[r];
+      dy = 2.0f * res / (float)a.B;
+      if (lead) {
+        S.dyres[r] = dy;
+        S.dyres[S.B4 + r] = res * res;
+      }
+    }
+    s_dy[tid] = dy;
+  }
+  __syncthreads();
+  const float* w3 = a.P + offs(a.L, a.H1, H2).w3;
+  auto fa = [&](int m, int k) {
+    const int r = r0 + m;
+    v4f d = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (r >= a.B) return d;
+    const v4f g2 = load4(S.G2 + (int64_t)r * S.ld2, k, H2, true);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (k + s < H2) {
+        d[s] = s_dy[m] * w3[k + s] * g2[s];
+        if (lead) S.D2T[(int64_t)(k + s) * S.B4 + r] = d[s];
+      }
+    return d;
+  };
+  const bool vw = (H2 & 3) == 0;
+  auto fb = [&](int n, int k) {
+    const int i = c0 + n;
+    return load4(i < a.H1 ? a.W2T + (int64_t)i * H2 : nullptr, k, H2, vw);
+  };
+  tile_product<4>(H2, fa, fb, red);
+  const TileOut o = tile_sum<4>(red);
+  const int i = c0 + o.n, r = r0 + o.m0;
+  if (i < a.H1 && r < S.B4) {
+    const v4f g1 = *reinterpret_cast<const v4f*>(S.G1T + (int64_t)i * S.B4 + r);
+    v4f d;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d[q] = r + q < a.B ? o.v[q] * g1[q] : 0.0f;
+    *reinterpret_cast<v4f*>(S.D1T + (int64_t)i * S.B4 + r) = d;
+  }
+}
+
+struct GradArgs {
+  int L, H1, H2, B;
+  Scratch s;
+  float* params;  // Adam: updated in place
+  float* W2T;
   float* m;
   float* v;
   int32_t* step;  // step counter, then an arrival counter (zero between launches)
   float lr;
-  int L, H1, H2;
+  float* grads;   // gradient output instead of Adam (null: Adam)
+  float* loss;    // mean squared error of the rows (may be null)
 };
 
-// Adds the slabs in order; writes the gradient, or applies one Adam step with
-// t = step + 1 and refreshes the transposed weights; the last workgroup
-// stores t.
-__global__ void reduce_kernel(ReduceArgs a, const DevState* halt) {
-  if (run_halted(halt)) return;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int t = a.grads ? 0 : *a.step + 1;
-  if (p < a.total || (p == a.total && a.loss)) {
-    float g = 0.0f;
-    for (int w = 0; w < a.W; ++w) g += a.slab[(int64_t)w * a.stride + p];
-    if (p == a.total) {
-      *a.loss = g / (float)a.B;
-    } else if (a.grads) {
-      a.grads[p] = g;
-    } else {
-      const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-      const float mi = b1 * a.m[p] + (1.0f - b1) * g;
-      const float vi = b2 * a.v[p] + (1.0f - b2) * g * g;
-      a.m[p] = mi;
-      a.v[p] = vi;
-      const float mhat = mi / (1.0f - powf(b1, (float)t));
-      const float vhat = vi / (1.0f - powf(b2, (float)t));
-      const float nv = a.params[p] - a.lr * mhat / (sqrtf(vhat) + eps);
-      a.params[p] = nv;
-      const int64_t n1 = (int64_t)a.H1 * a.L, o2 = n1 + a.H1, n2 = (int64_t)a.H2 * a.H1;
-      if (p < n1) {
-        const int64_t j = p / a.L, l = p - j * a.L;
-        a.WT[l * a.H1 + j] = nv;
-      } else if (p >= o2 && p < o2 + n2) {
-        const int64_t q = p - o2, j = q / a.H1, i = q - j * a.H1;
-        a.WT[n1 + i * a.H2 + j] = nv;
-      }
-    }
-  }
-  if (a.grads) return;
-  __shared__ int s_last;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    s_last = atomicAdd(reinterpret_cast<uint32_t*>(a.step + 1), 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (s_last && threadIdx.x == 0) {
-    *a.step = t;
-    a.step[1] = 0;
+// One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on parameter p with
+// gradient g at step t; refreshes W2T for an element of W2.
+__device__ __forceinline__ void adam_update(float* params, float* m, float* v, float* W2T, int64_t p,
+                                            float g, int t, float lr, int L, int H1, int H2) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float mi = b1 * m[p] + (1.0f - b1) * g;
+  const float vi = b2 * v[p] + (1.0f - b2) * g * g;
+  m[p] = mi;
+  v[p] = vi;
+  const float mhat = mi / (1.0f - powf(b1, (float)t));
+  const float vhat = vi / (1.0f - powf(b2, (float)t));
+  const float nv = params[p] - lr * mhat / (sqrtf(vhat) + eps);
+  params[p] = nv;
+  const int64_t o2 = (int64_t)H1 * L + H1, n2 = (int64_t)H2 * H1;
+  if (p >= o2 && p < o2 + n2) {
+    const int64_t q = p - o2, j = q / H1, i = q - j * H1;
+    W2T[i * H2 + j] = nv;
   }
 }
 
-// Transposed copies of W1 and W2 from the parameters.
-__global__ void transpose_kernel(const float* __restrict__ P, float* __restrict__ WT, int L, int H1,
+// The parameter-gradient products, as a list of jobs C (M x N) = A Bt^T over
+// the B rows; the element (m, n) of a job is parameter p0 + m * ldp + n.
+struct Job {
+  const float* A;
+  const float* Bt;
+  int M, N;
+  int64_t p0, ldp;
+  int scalars;  // the (db3, loss) job
+};
+
+__device__ bool find_job(const GradArgs& g, int wg, Job& job, int& tm, int& tn) {
+  const Scratch& S = g.s;
+  const Offs o = offs(g.L, g.H1, g.H2);
+  const Job list[6] = {
+      {S.D1T, S.XT, g.H1, g.L, o.W1, g.L, 0},      // dW1 = dA1^T X
+      {S.D2T, S.Hd1T, g.H2, g.H1, o.W2, g.H1, 0},  // dW2 = dA2^T H1
+      {S.D1T, S.ones, g.H1, 1, o.b1, 1, 0},        // db1 = dA1^T 1
+      {S.D2T, S.ones, g.H2, 1, o.b2, 1, 0},        // db2 = dA2^T 1
+      {S.Hd2T, S.dyres, g.H2, 1, o.w3, 1, 0},      // dw3 = H2^T dy
+      {S.dyres, S.ones, 2, 1, o.b3, 0, 1},         // db3 = dy^T 1, loss sum
+  };
+  for (int q = 0; q < 6; ++q) {
+    const int nm = (list[q].M + kT - 1) / kT, nn = (list[q].N + kT - 1) / kT;
+    if (wg < nm * nn) {
+      job = list[q];
+      tm = wg / nn;
+      tn = wg - tm * nn;
+      return true;
+    }
+    wg -= nm * nn;
+  }
+  return false;
+}
+
+// The gradient products contract over all B rows: 16 waves per tile keep
+// more loads in flight than 4.
+constexpr int kGradWaves = 16;
+
+int grad_tiles(const MlpDims& d) {
+  auto t = [](int M, int N) { return ((M + kT - 1) / kT) * ((N + kT - 1) / kT); };
+  return t(d.H1, d.L) + t(d.H2, d.H1) + t(d.H1, 1) + t(d.H2, 1) + t(d.H2, 1) + t(2, 1);
+}
+
+__global__ __launch_bounds__(64 * kGradWaves) void grads_kernel(GradArgs g, const DevState* halt) {
+  if (run_halted(halt)) return;
+  __shared__ v4f red[kGradWaves * 4 * 64];
+  __shared__ int s_last;
+  const int B4 = g.s.B4, K = g.B;
+  const int t = g.grads ? 0 : *g.step + 1;
+  Job job{};
+  int tm = 0, tn = 0;
+  const bool have = find_job(g, blockIdx.x, job, tm, tn);
+  const int m0 = tm * kT, n0 = tn * kT;
+  auto fa = [&](int m, int k) {
+    return load4(have && m0 + m < job.M ? job.A + (int64_t)(m0 + m) * B4 : nullptr, k, K, true);
+  };
+  auto fb = [&](int n, int k) {
+    return load4(have && n0 + n < job.N ? job.Bt + (int64_t)(n0 + n) * B4 : nullptr, k, K, true);
+  };
+  tile_product<kGradWaves>(K, fa, fb, red);
+  const TileOut o = tile_sum<kGradWaves>(red);
+  const int n = n0 + o.n;
+  if (have && threadIdx.x < 256 && n < job.N) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = m0 + o.m0 + q;
+      if (m >= job.M) continue;
+      const float val = o.v[q];
+      if (job.scalars && m == 1) {
+        if (g.loss) *g.loss = val / (float)g.B;
+        continue;
+      }
+      const int64_t p = job.p0 + (int64_t)m * job.ldp + n;
+      if (g.grads)
+        g.grads[p] = val;
+      else
+        adam_update(g.params, g.m, g.v, g.W2T, p, val, t, g.lr, g.L, g.H1, g.H2);
+    }
+  }
+  if (g.grads) return;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    s_last = atomicAdd(reinterpret_cast<uint32_t*>(g.step + 1), 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (s_last && threadIdx.x == 0) {
+    *g.step = t;
+    g.step[1] = 0;
+  }
+}
+
+// One Adam step from a given gradient (every parameter); the last workgroup
+// stores the step count.
+__global__ void adam_kernel(float* params, float* W2T, const float* grads, float* m, float* v,
+                            int32_t* step, float lr, int L, int H1, int H2, int64_t total,
+                            const DevState* halt) {
+  if (run_halted(halt)) return;
+  __shared__ int s_last;
+  const int t = *step + 1;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < total) adam_update(params, m, v, W2T, p, grads[p], t, lr, L, H1, H2);
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = atomicAdd(reinterpret_cast<uint32_t*>(step + 1), 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (s_last && threadIdx.x == 0) {
+    *step = t;
+    step[1] = 0;
+  }
+}
+
+// W2T from the parameters.
+__global__ void transpose_kernel(const float* __restrict__ P, float* __restrict__ W2T, int L, int H1,
                                  int H2) {
-  const int64_t n1 = (int64_t)H1 * L, n2 = (int64_t)H2 * H1;
+  const int64_t n2 = (int64_t)H2 * H1;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n1) {
-    const int64_t j = e / L, l = e - j * L;
-    WT[l * H1 + j] = P[e];
-  } else if (e < n1 + n2) {
-    const int64_t q = e - n1, j = q / H1, i = q - j * H1;
-    WT[n1 + i * H2 + j] = P[n1 + H1 + q];
+  if (e < n2) {
+    const int64_t j = e / H1, i = e - j * H1;
+    W2T[i * H2 + j] = P[(int64_t)H1 * L + H1 + e];
   }
 }
 
@@ -390,60 +574,43 @@ __global__ void init_kernel(float* __restrict__ p, float* __restrict__ m, float*
   p[i] = (float)(sqrt(6.0 / (double)cols) * (2.0 * u - 1.0));
 }
 
-size_t rows_lds(const MlpDims& d, int R) {
-  const size_t Hm = (size_t)std::max(d.H1, d.H2);
-  return (size_t)R * ((size_t)d.L + 3 * (size_t)d.H1 + 3 * (size_t)d.H2 + 4 * Hm) * sizeof(float);
-}
-
-hipError_t rows_prepare() {
-  static bool done = false;
-  if (done) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rows_kernel<true>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowsLds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(rows_kernel<false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowsLds);
-  if (e == hipSuccess) done = true;
-  return e;
-}
-
-hipError_t launch_rows(bool train, const RowsArgs& a, const MlpDims& d, const DevState* halt,
-                       hipStream_t s) {
-  const hipError_t e = rows_prepare();
-  if (e != hipSuccess) return e;
-  const size_t lds = rows_lds(d, a.R);
-  if (train)
-    hipLaunchKernelGGL(rows_kernel<true>, dim3((unsigned)a.W), dim3(kThreads), lds, s, a, halt);
-  else
-    hipLaunchKernelGGL(rows_kernel<false>, dim3((unsigned)a.W), dim3(kThreads), lds, s, a, halt);
-  return hipGetLastError();
-}
-
-int64_t slab_stride(const MlpDims& d) { return mlp_layout(d.L, d.H1, d.H2).total + 1; }
-
-RowsArgs rows_args(const MlpDims& d, const float* params, const float* WT, int B) {
-  RowsArgs a{};
-  a.params = params;
-  a.WT = WT;
+Args base_args(const MlpDims& d, const float* params, const float* W2T, int B, float* scratch,
+               bool train) {
+  Args a{};
+  a.P = params;
+  a.W2T = W2T;
   a.L = d.L;
   a.H1 = d.H1;
   a.H2 = d.H2;
   a.B = B;
-  a.R = mlp_rows_per_pass(d);
-  a.total = mlp_layout(d.L, d.H1, d.H2).total;
+  scratch_layout(d, B, train, scratch, &a.s);
   return a;
 }
 
-// Workgroups of a training launch: one per R rows, as many slabs as fit.
-int train_wgs(const MlpDims& d, int B, int R, int64_t slab_cap) {
-  int64_t W = (B + R - 1) / R;
-  W = std::min<int64_t>(W, slab_cap / slab_stride(d));
-  return (int)std::max<int64_t>(W, 1);
+dim3 grid_of(int units, int rows) {
+  return dim3((unsigned)((units + kT - 1) / kT), (unsigned)((rows + kT - 1) / kT));
 }
 
-hipError_t launch_reduce(const ReduceArgs& a, const DevState* halt, hipStream_t s) {
-  const int64_t n = a.total + 1;
-  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, halt);
+// The three training launches before the gradient products.
+hipError_t launch_train_rows(const Args& a, const DevState* halt, hipStream_t s) {
+  hipLaunchKernelGGL(layer1_kernel<true>, grid_of(a.H1, a.B), dim3(kThreads), 0, s, a, halt);
+  hipLaunchKernelGGL(layer2_kernel<true>, grid_of(a.H2, a.B), dim3(kThreads), 0, s, a, halt);
+  hipLaunchKernelGGL(back_kernel, grid_of(a.H1, a.B), dim3(kThreads), 0, s, a, halt);
+  return hipGetLastError();
+}
+
+GradArgs grad_args(const MlpDims& d, const Args& a) {
+  GradArgs g{};
+  g.L = d.L;
+  g.H1 = d.H1;
+  g.H2 = d.H2;
+  g.B = a.B;
+  g.s = a.s;
+  return g;
+}
+
+hipError_t launch_grads(const MlpDims& d, const GradArgs& g, const DevState* halt, hipStream_t s) {
+  hipLaunchKernelGGL(grads_kernel, dim3((unsigned)grad_tiles(d)), dim3(64 * kGradWaves), 0, s, g, halt);
   return hipGetLastError();
 }
 
@@ -461,76 +628,60 @@ MlpLayout mlp_layout(int L, int H1, int H2) {
   return o;
 }
 
-int mlp_rows_per_pass(const MlpDims& d) {
-  int R = kMaxR;
-  while (R > 1 && rows_lds(d, R) > kRowsLds) R /= 2;
-  return R;
+int64_t mlp_scratch_floats(const MlpDims& d, int batch, int rows_max) {
+  return std::max(scratch_layout(d, batch, true, nullptr, nullptr),
+                  scratch_layout(d, rows_max, false, nullptr, nullptr));
 }
 
-bool mlp_fits(const MlpDims& d) { return rows_lds(d, 1) <= kRowsLds; }
-
-int64_t mlp_slab_floats(const MlpDims& d, int rows) {
-  const int64_t per = slab_stride(d);
-  const int R = mlp_rows_per_pass(d);
-  int64_t W = std::min<int64_t>((rows + R - 1) / R, kMlpSlabFloats / per);
-  return std::max<int64_t>(W, 1) * per;
-}
-
-hipError_t mlp_transpose(const MlpDims& d, const float* params, float* WT, hipStream_t s) {
-  const int64_t n = (int64_t)d.H1 * d.L + (int64_t)d.H2 * d.H1;
-  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params, WT,
+hipError_t mlp_transpose(const MlpDims& d, const float* params, float* W2T, hipStream_t s) {
+  const int64_t n = (int64_t)d.H2 * d.H1;
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params, W2T,
                      d.L, d.H1, d.H2);
   return hipGetLastError();
 }
 
-hipError_t mlp_init(const MlpDims& d, float* params, float* m, float* v, float* WT, uint64_t seed,
+hipError_t mlp_init(const MlpDims& d, float* params, float* m, float* v, float* W2T, uint64_t seed,
                     hipStream_t s) {
   const int64_t n = mlp_layout(d.L, d.H1, d.H2).total;
   hipLaunchKernelGGL(init_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params, m, v,
                      d.L, d.H1, d.H2, (uint32_t)seed, (uint32_t)(seed >> 32));
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return mlp_transpose(d, params, WT, s);
+  return mlp_transpose(d, params, W2T, s);
 }
 
-hipError_t mlp_forward(const MlpDims& d, const float* params, const float* WT, const float* X, int B,
-                       float* y, const DevState* halt, hipStream_t s) {
+hipError_t mlp_forward(const MlpDims& d, const float* params, const float* W2T, const float* X, int B,
+                       float* y, float* scratch, const DevState* halt, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  RowsArgs a = rows_args(d, params, WT, B);
-  a.W = (B + a.R - 1) / a.R;
+  Args a = base_args(d, params, W2T, B, scratch, false);
   a.X = X;
   a.y = y;
-  return launch_rows(false, a, d, halt, s);
+  hipLaunchKernelGGL(layer1_kernel<false>, grid_of(d.H1, B), dim3(kThreads), 0, s, a, halt);
+  hipLaunchKernelGGL(layer2_kernel<false>, grid_of(d.H2, B), dim3(kThreads), 0, s, a, halt);
+  hipLaunchKernelGGL(head_kernel, dim3((unsigned)((B + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                     a, halt);
+  return hipGetLastError();
 }
 
-hipError_t mlp_grads(const MlpDims& d, const float* params, const float* WT, const float* X,
-                     const float* target, int B, float* slab, int64_t slab_cap, float* grads,
-                     float* loss, const DevState* halt, hipStream_t s) {
-  RowsArgs a = rows_args(d, params, WT, B);
-  a.W = train_wgs(d, B, a.R, slab_cap);
+hipError_t mlp_grads(const MlpDims& d, const float* params, const float* W2T, const float* X,
+                     const float* target, int B, float* scratch, float* grads, float* loss,
+                     const DevState* halt, hipStream_t s) {
+  Args a = base_args(d, params, W2T, B, scratch, true);
   a.X = X;
   a.target = target;
-  a.slab = slab;
-  hipError_t e = launch_rows(true, a, d, halt, s);
+  hipError_t e = launch_train_rows(a, halt, s);
   if (e != hipSuccess) return e;
-  ReduceArgs r{};
-  r.slab = slab;
-  r.W = a.W;
-  r.stride = a.total + 1;
-  r.total = a.total;
-  r.B = B;
-  r.grads = grads;
-  r.loss = loss;
-  return launch_reduce(r, halt, s);
+  GradArgs g = grad_args(d, a);
+  g.grads = grads;
+  g.loss = loss;
+  return launch_grads(d, g, halt, s);
 }
 
-hipError_t mlp_train_step(const MlpDims& d, float* params, float* WT, float* m, float* v,
+hipError_t mlp_train_step(const MlpDims& d, float* params, float* W2T, float* m, float* v,
                           int32_t* step, float lr, const float* buf, const float* bufy,
                           const SurState* ss, uint64_t seed, int B, int n_recent, int cap,
-                          float* slab, int64_t slab_cap, float* loss, const DevState* halt,
-                          hipStream_t s) {
-  RowsArgs a = rows_args(d, params, WT, B);
-  a.W = train_wgs(d, B, a.R, slab_cap);
+                          float* scratch, float* loss, const DevState* halt, hipStream_t s) {
+  Args a = base_args(d, params, W2T, B, scratch, true);
   a.buf = buf;
   a.bufy = bufy;
   a.ss = ss;
@@ -539,46 +690,25 @@ hipError_t mlp_train_step(const MlpDims& d, float* params, float* WT, float* m, 
   a.k1 = (uint32_t)(seed >> 32);
   a.n_recent = n_recent;
   a.cap = cap;
-  a.slab = slab;
-  hipError_t e = launch_rows(true, a, d, halt, s);
+  hipError_t e = launch_train_rows(a, halt, s);
   if (e != hipSuccess) return e;
-  ReduceArgs r{};
-  r.slab = slab;
-  r.W = a.W;
-  r.stride = a.total + 1;
-  r.total = a.total;
-  r.B = B;
-  r.loss = loss;
-  r.params = params;
-  r.WT = WT;
-  r.m = m;
-  r.v = v;
-  r.step = step;
-  r.lr = lr;
-  r.L = d.L;
-  r.H1 = d.H1;
-  r.H2 = d.H2;
-  return launch_reduce(r, halt, s);
+  GradArgs g = grad_args(d, a);
+  g.params = params;
+  g.W2T = W2T;
+  g.m = m;
+  g.v = v;
+  g.step = step;
+  g.lr = lr;
+  g.loss = loss;
+  return launch_grads(d, g, halt, s);
 }
 
-hipError_t mlp_adam(const MlpDims& d, float* params, float* WT, const float* grads, float* m, float* v,
+hipError_t mlp_adam(const MlpDims& d, float* params, float* W2T, const float* grads, float* m, float* v,
                     int32_t* step, float lr, const DevState* halt, hipStream_t s) {
-  ReduceArgs r{};
-  r.slab = grads;  // one slab: the gradient itself (no loss entry)
-  r.W = 1;
-  r.total = mlp_layout(d.L, d.H1, d.H2).total;
-  r.stride = r.total;
-  r.B = 1;
-  r.params = params;
-  r.WT = WT;
-  r.m = m;
-  r.v = v;
-  r.step = step;
-  r.lr = lr;
-  r.L = d.L;
-  r.H1 = d.H1;
-  r.H2 = d.H2;
-  return launch_reduce(r, halt, s);
+  const int64_t total = mlp_layout(d.L, d.H1, d.H2).total;
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, params, W2T,
+                     grads, m, v, step, lr, d.L, d.H1, d.H2, total, halt);
+  return hipGetLastError();
 }
 
 }  // namespace game
