@@ -64,6 +64,7 @@ struct game_ctx {
   // offspring form buffers
   float *O = nullptr, *evg = nullptr, *yhat = nullptr, *rho = nullptr, *loss = nullptr;
   uint64_t* keys = nullptr;
+  int* rank_ws = nullptr;
   int *sel = nullptr, *aud = nullptr, *surv = nullptr;
   double *emse = nullptr, *emis = nullptr, *efit = nullptr, *snap = nullptr;
   float *prm = nullptr, *am = nullptr, *av = nullptr;
@@ -230,6 +231,7 @@ game_status make_plan(const game_config* c, Plan* p, char* err, size_t errlen) {
     const int evrows = std::max<int>((int)P, p->P_eval);
     p->off_O = take((size_t)n_off * Lz * 4);
     p->off_keys = take((size_t)n_off * 8);
+    p->off_rank = take((size_t)sur_rank_ints((int)n_off) * 4);
     p->off_sel = take((size_t)p->k_sel * 4);
     p->off_aud = take((size_t)std::max(p->audit, 1) * 4);
     p->off_surv = take((size_t)P * 4);
@@ -507,16 +509,16 @@ game_status enqueue_offspring_generation(game_ctx* c, hipStream_t s) {
                  mlp_forward(mlp_dims(c), c->prm, c->WT, c->O, p.n_off, c->yhat, c->mscr, st, s),
                  "mlp forward"));
     GAME_TRY(dev(c, sur_keys(0, c->yhat, nullptr, p.n_off, 0, st, c->cfg.seed, c->keys, s), "keys"));
-    GAME_TRY(dev(c, sur_select(c->keys, p.n_off, k, c->sel, st, s), "prescreen"));
+    GAME_TRY(dev(c, sur_select(c->keys, p.n_off, k, c->sel, c->rank_ws, st, s), "prescreen"));
     sel = c->sel;
   } else if (p.sur == GAME_SURROGATE_RANDOM) {
     GAME_TRY(dev(c, sur_keys(1, nullptr, nullptr, p.n_off, kTagPrescreen, st, c->cfg.seed, c->keys, s), "keys"));
-    GAME_TRY(dev(c, sur_select(c->keys, p.n_off, k, c->sel, st, s), "prescreen"));
+    GAME_TRY(dev(c, sur_select(c->keys, p.n_off, k, c->sel, c->rank_ws, st, s), "prescreen"));
     sel = c->sel;
   }
   if (A > 0) {
     GAME_TRY(dev(c, sur_keys(1, nullptr, nullptr, p.n_off, kTagAudit, st, c->cfg.seed, c->keys, s), "keys"));
-    GAME_TRY(dev(c, sur_select(c->keys, p.n_off, A, c->aud, st, s), "audit"));
+    GAME_TRY(dev(c, sur_select(c->keys, p.n_off, A, c->aud, c->rank_ws, st, s), "audit"));
   }
   // exact fitness of the selected children and the audit sample
   GAME_TRY(dev(c, sur_gather(c->O, sel, k, p.L, c->evg, st, s), "gather"));
@@ -531,14 +533,14 @@ game_status enqueue_offspring_generation(game_ctx* c, hipStream_t s) {
   GAME_TRY(enqueue_fitness(c, p.P_eval, t, s));
   if (p.sur == GAME_SURROGATE_MLP) {
     if (A > 0)
-      GAME_TRY(dev(c, sur_spearman(c->yhat, c->aud, c->emse + k, A, c->rho, st, s), "spearman"));
-    GAME_TRY(dev(c, sur_spearman(c->yhat, c->sel, c->emse, k, c->rho + 1, st, s), "spearman"));
+      GAME_TRY(dev(c, sur_spearman(c->yhat, c->aud, c->emse + k, A, c->rho, c->rank_ws, st, s), "spearman"));
+    GAME_TRY(dev(c, sur_spearman(c->yhat, c->sel, c->emse, k, c->rho + 1, c->rank_ws, st, s), "spearman"));
     GAME_TRY(dev(c, sur_append(c->evg, c->emse, p.P_eval, p.L, c->buf, c->bufy, p.cap, c->sst, st, s),
                  "replay append"));
   }
   // next population: elites + best P - E of the selected children
   GAME_TRY(dev(c, sur_keys(2, nullptr, c->efit, k, 0, st, c->cfg.seed, c->keys, s), "keys"));
-  GAME_TRY(dev(c, sur_select(c->keys, k, p.P - p.E, c->surv, st, s), "survivors"));
+  GAME_TRY(dev(c, sur_select(c->keys, k, p.P - p.E, c->surv, c->rank_ws, st, s), "survivors"));
   GAME_TRY(dev(c, sur_snapshot(c->elite, p.E, c->fit, c->mse, c->miscls, c->snap, st, s), "snapshot"));
   GAME_TRY(dev(c,
                sur_merge(c->pop0, c->pop1, c->elite, c->snap, p.E, c->evg, c->surv, c->efit, c->emse,
@@ -705,6 +707,7 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
     auto I = [&](size_t o) { return reinterpret_cast<int*>(c->ws + o); };
     c->O = F(p.off_O);
     c->keys = reinterpret_cast<uint64_t*>(c->ws + p.off_keys);
+    c->rank_ws = I(p.off_rank);
     c->sel = I(p.off_sel);
     c->aud = I(p.off_aud);
     c->surv = I(p.off_surv);
@@ -751,8 +754,7 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
   if (r == GAME_OK) r = enqueue_pack_population(c, st);
   if (r == GAME_OK) {  // prime per-kernel attributes outside any graph capture
     (void)fitness_geometry(p, cfg->task, cfg->dtype, p.P_max);
-    if (p.offspring) r = dev(c, sur_prepare(), "prepare");
-    if (r == GAME_OK) r = dev(c, select_prepare(cfg->selection), "prepare");
+    r = dev(c, select_prepare(cfg->selection), "prepare");
   }
   if (r == GAME_OK && p.offspring) {
     r = dev(c, hipMemsetAsync(c->sst, 0, sizeof(SurState), st), "surrogate state");

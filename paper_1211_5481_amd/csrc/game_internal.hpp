@@ -131,7 +131,7 @@ struct Plan {
   int64_t mlp_scratch;         // floats of MLP activation scratch
   size_t off_O, off_keys, off_sel, off_aud, off_surv, off_evg, off_emse, off_emis, off_efit;
   size_t off_snap, off_yhat, off_rho, off_loss, off_prm, off_am, off_av, off_step;
-  size_t off_WT, off_mscr, off_buf, off_bufy, off_sst, off_log;
+  size_t off_rank, off_WT, off_mscr, off_buf, off_bufy, off_sst, off_log;
   size_t total;
 };
 constexpr int kLogCap = 4096;  // generations of surrogate statistics kept
@@ -224,12 +224,14 @@ struct SurState {  // replay ring buffer, target statistics, log position
   int32_t n_logged;
   int32_t last;  // rows the latest append stored (they end at head - 1)
 };
-hipError_t sur_prepare();
+// rank_ws: sur_rank_ints(n) ints of per-slice rank counts (shared by the
+// selections and statistics of one stream)
+int64_t sur_rank_ints(int n);
 hipError_t sur_keys(int mode, const float* fsrc, const double* dsrc, int n, uint32_t tag,
                     const DevState* st, uint64_t seed, uint64_t* keys, hipStream_t s);
-hipError_t sur_select(const uint64_t* keys, int n, int k, int* out, const DevState* st,
+hipError_t sur_select(const uint64_t* keys, int n, int k, int* out, int* rank_ws, const DevState* st,
                       hipStream_t s);
-hipError_t sur_spearman(const float* x, const int* xi, const double* y, int n, float* out,
+hipError_t sur_spearman(const float* x, const int* xi, const double* y, int n, float* out, int* rank_ws,
                         const DevState* st, hipStream_t s);
 hipError_t sur_gather(const float* src, const int* idx, int n, int L, float* dst, const DevState* st,
                       hipStream_t s);

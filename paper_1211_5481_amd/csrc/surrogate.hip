@@ -9,10 +9,10 @@
 // evaluated offspring.  The audit sample measures the surrogate's rank error
 // (Spearman's rho with average ranks for ties).
 //
-// The small kernels here are single-workgroup selections and statistics over
-// at most a few thousand values, plus row gathers; every sum is in a fixed
-// order and every selection breaks ties by the lower index, so a run is
-// bit-reproducible and each selection matches the CPU rule exactly.
+// The small kernels here are selections and rank statistics over at most a
+// few thousand values (by counting, see below), plus row gathers; every sum
+// is in a fixed order and every selection breaks ties by the lower index, so
+// a run is bit-reproducible and each selection matches the CPU rule exactly.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -23,7 +23,6 @@
 namespace game {
 namespace {
 
-constexpr int kSortThreads = 1024;
 
 // keys for the selections: 0 = float ascending (scores), 1 = random u32 word
 // of block (i, 0, g, tag), 2 = double descending (fitness)
@@ -41,64 +40,91 @@ __global__ void keys_kernel(int mode, const float* __restrict__ fsrc, const doub
   }
 }
 
-// Bitonic sort of (key, index) pairs in LDS by one workgroup; writes the
-// indices of the k smallest (ties to the lower index), in order.
-__global__ __launch_bounds__(kSortThreads) void select_kernel(const uint64_t* __restrict__ keys, int n,
-                                                              int n_pow2, int k, int* __restrict__ out,
-                                                              const DevState* st) {
-  if (run_halted(st)) return;
-  extern __shared__ __align__(16) unsigned char smem[];
-  uint64_t* sk = reinterpret_cast<uint64_t*>(smem);
-  int* si = reinterpret_cast<int*>(smem + (size_t)n_pow2 * 8);
-  for (int i = threadIdx.x; i < n_pow2; i += kSortThreads) {
-    sk[i] = i < n ? keys[i] : ~0ull;
-    si[i] = i < n ? i : 0x7fffffff;
-  }
-  __syncthreads();
-  block_sort_pairs<kSortThreads>(sk, si, n_pow2);
-  for (int i = threadIdx.x; i < k; i += kSortThreads) out[i] = si[i];
+// Selections and rank statistics count instead of sorting: the rank of value
+// i is the number of values before it in the order (key, index), counted in
+// kRankSplits slices of the values by separate workgroups and added in slice
+// order (integers, so exact).  n <= kRankSplits * kRankChunk.
+constexpr int kRankThreads = 256;
+constexpr int kRankSplits = 16;
+constexpr int kRankChunk = 512;
+
+struct KeySrc {
+  const uint64_t* keys;  // explicit keys, or: side 0 orders x[xi[i]] ascending,
+  const float* x;        // side 1 orders y[i] ascending
+  const int* xi;
+  const double* y;
+};
+__device__ __forceinline__ uint64_t key_of(const KeySrc& k, int side, int i) {
+  if (k.keys) return k.keys[i];
+  if (side == 0) return ord_f32(k.x[k.xi ? k.xi[i] : i]);
+  return ~ord_desc_f64(k.y[i]);
 }
 
-// Spearman's rho of (x[i], y[i]), i < n (n <= 4096), average ranks for ties.
-// One workgroup: sort each side, rank runs of equal values by their mean
-// position, then the Pearson correlation of the ranks (fixed-order sums).
-__global__ __launch_bounds__(kSortThreads) void spearman_kernel(const float* __restrict__ x,
-                                                                const int* __restrict__ xi,
-                                                                const double* __restrict__ y, int n,
-                                                                int n_pow2, float* __restrict__ out,
-                                                                const DevState* st) {
+// Slice s = blockIdx.y of side blockIdx.z; counts for value i:
+//   kTies = false: c0 = #{j in slice : (key_j, j) < (key_i, i)}
+//   kTies = true:  c0 = #{j in slice : key_j < key_i}, c1 = #{j in slice : key_j == key_i}
+// at cnt[((side * 2 + c) * S + s) * n + i].
+template <bool kTies>
+__global__ __launch_bounds__(kRankThreads) void rank_part_kernel(KeySrc src, int n, int chunk,
+                                                                 int* __restrict__ cnt,
+                                                                 const DevState* st) {
   if (run_halted(st)) return;
-  extern __shared__ __align__(16) unsigned char smem[];
-  uint64_t* sk = reinterpret_cast<uint64_t*>(smem);
-  int* si = reinterpret_cast<int*>(smem + (size_t)n_pow2 * 8);
-  float* rx = reinterpret_cast<float*>(smem + (size_t)n_pow2 * 12);
-  float* ry = rx + n_pow2;
-  __shared__ double red[kSortThreads / 64][3];
-  for (int side = 0; side < 2; ++side) {
-    for (int i = threadIdx.x; i < n_pow2; i += kSortThreads) {
-      if (i < n) {
-        sk[i] = side == 0 ? ord_f32(x[xi ? xi[i] : i]) : ~ord_desc_f64(y[i]);
-        si[i] = i;
-      } else {
-        sk[i] = ~0ull;
-        si[i] = 0x7fffffff;
-      }
+  __shared__ uint64_t sk[kRankChunk];
+  const int side = blockIdx.z, sl = blockIdx.y, S = gridDim.y;
+  const int j0 = sl * chunk, j1 = min(n, j0 + chunk);
+  for (int j = j0 + (int)threadIdx.x; j < j1; j += kRankThreads) sk[j - j0] = key_of(src, side, j);
+  __syncthreads();
+  const int i = blockIdx.x * kRankThreads + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t ki = key_of(src, side, i);
+  int c0 = 0, c1 = 0;
+  for (int j = j0; j < j1; ++j) {
+    const uint64_t kj = sk[j - j0];
+    if (kTies) {
+      c0 += kj < ki;
+      c1 += kj == ki;
+    } else {
+      c0 += kj < ki || (kj == ki && j < i);
     }
-    __syncthreads();
-    block_sort_pairs<kSortThreads>(sk, si, n_pow2);
-    float* r = side == 0 ? rx : ry;
-    for (int q = threadIdx.x; q < n; q += kSortThreads) {
-      int a = q, b = q;
-      while (a > 0 && sk[a - 1] == sk[q]) --a;
-      while (b + 1 < n && sk[b + 1] == sk[q]) ++b;
-      r[si[q]] = 0.5f * (float)(a + b) + 1.0f;
-    }
-    __syncthreads();
   }
+  cnt[((int64_t)(side * 2) * S + sl) * n + i] = c0;
+  if (kTies) cnt[((int64_t)(side * 2 + 1) * S + sl) * n + i] = c1;
+}
+
+// out[rank] = i for the k values of lowest rank: the indices of the k
+// smallest keys (ties to the lower index), in order.
+__global__ void select_scatter_kernel(const int* __restrict__ cnt, int n, int S, int k,
+                                      int* __restrict__ out, const DevState* st) {
+  if (run_halted(st)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int r = 0;
+  for (int s = 0; s < S; ++s) r += cnt[(int64_t)s * n + i];
+  if (r < k) out[r] = i;
+}
+
+// Spearman's rho of (x[xi[i]], y[i]), i < n, average ranks for ties: value i
+// of a side ranks lt + (eq + 1) / 2 (1-based; lt values below it, eq equal
+// to it, itself included); then the Pearson correlation of the ranks with
+// fixed-order sums (thread-strided, wave tree, waves in order).
+constexpr int kRhoThreads = 1024;
+__global__ __launch_bounds__(kRhoThreads) void spearman_final_kernel(const int* __restrict__ cnt, int n,
+                                                                     int S, float* __restrict__ out,
+                                                                     const DevState* st) {
+  if (run_halted(st)) return;
+  __shared__ double red[kRhoThreads / 64][3];
+  auto rank = [&](int side, int i) {
+    int lt = 0, eq = 0;
+    for (int s = 0; s < S; ++s) {
+      lt += cnt[((int64_t)(side * 2) * S + s) * n + i];
+      eq += cnt[((int64_t)(side * 2 + 1) * S + s) * n + i];
+    }
+    return 0.5f * (float)(2 * lt + eq - 1) + 1.0f;
+  };
   const double mean = 0.5 * (double)(n + 1);
   double sxy = 0.0, sxx = 0.0, syy = 0.0;
-  for (int i = threadIdx.x; i < n; i += kSortThreads) {
-    const double a = rx[i] - mean, b = ry[i] - mean;
+  for (int i = threadIdx.x; i < n; i += kRhoThreads) {
+    const double a = rank(0, i) - mean, b = rank(1, i) - mean;
     sxy += a * b;
     sxx += a * a;
     syy += b * b;
@@ -117,7 +143,7 @@ __global__ __launch_bounds__(kSortThreads) void spearman_kernel(const float* __r
   __syncthreads();
   if (threadIdx.x == 0) {
     double a = 0, b = 0, c = 0;
-    for (int w = 0; w < kSortThreads / 64; ++w) {
+    for (int w = 0; w < kRhoThreads / 64; ++w) {
       a += red[w][0];
       b += red[w][1];
       c += red[w][2];
@@ -290,21 +316,31 @@ hipError_t sur_keys(int mode, const float* fsrc, const double* dsrc, int n, uint
   return hipGetLastError();
 }
 
-hipError_t sur_select(const uint64_t* keys, int n, int k, int* out, const DevState* st,
+hipError_t sur_select(const uint64_t* keys, int n, int k, int* out, int* rank_ws, const DevState* st,
                       hipStream_t s) {
-  const int np2 = pow2_at_least(n);
-  const size_t lds = (size_t)np2 * 12;
-  if (lds > 98304) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSortThreads), lds, s, keys, n, np2, k, out, st);
+  if (n <= 0 || k <= 0) return hipSuccess;
+  if (n > kRankSplits * kRankChunk || k > n) return hipErrorInvalidValue;
+  const int chunk = (n + kRankSplits - 1) / kRankSplits;
+  const unsigned g = (unsigned)((n + kRankThreads - 1) / kRankThreads);
+  const KeySrc src{keys, nullptr, nullptr, nullptr};
+  hipLaunchKernelGGL(rank_part_kernel<false>, dim3(g, kRankSplits, 1), dim3(kRankThreads), 0, s, src, n,
+                     chunk, rank_ws, st);
+  hipLaunchKernelGGL(select_scatter_kernel, dim3(g), dim3(kRankThreads), 0, s, rank_ws, n, kRankSplits, k,
+                     out, st);
   return hipGetLastError();
 }
 
-hipError_t sur_spearman(const float* x, const int* xi, const double* y, int n, float* out,
+hipError_t sur_spearman(const float* x, const int* xi, const double* y, int n, float* out, int* rank_ws,
                         const DevState* st, hipStream_t s) {
-  const int np2 = pow2_at_least(n);
-  const size_t lds = (size_t)np2 * 20;
-  if (lds > 98304) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(spearman_kernel, dim3(1), dim3(kSortThreads), lds, s, x, xi, y, n, np2, out, st);
+  if (n <= 0) return hipSuccess;
+  if (n > kRankSplits * kRankChunk) return hipErrorInvalidValue;
+  const int chunk = (n + kRankSplits - 1) / kRankSplits;
+  const unsigned g = (unsigned)((n + kRankThreads - 1) / kRankThreads);
+  const KeySrc src{nullptr, x, xi, y};
+  hipLaunchKernelGGL(rank_part_kernel<true>, dim3(g, kRankSplits, 2), dim3(kRankThreads), 0, s, src, n,
+                     chunk, rank_ws, st);
+  hipLaunchKernelGGL(spearman_final_kernel, dim3(1), dim3(kRhoThreads), 0, s, rank_ws, n, kRankSplits, out,
+                     st);
   return hipGetLastError();
 }
 
@@ -357,12 +393,7 @@ hipError_t sur_log(const float* rho, const float* loss, float* log, int cap, Sur
   return hipGetLastError();
 }
 
-hipError_t sur_prepare() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(select_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 98304);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(spearman_kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 98304);
-}
+int64_t sur_rank_ints(int n) { return (int64_t)4 * kRankSplits * n; }
+
 
 }  // namespace game
