@@ -185,7 +185,8 @@ def surrogate_compare(args):
         print(f"[bench] seed {seed} plain: {res['plain']}", file=sys.stderr, flush=True)
         for mode in ("mlp", "random"):
             cfg = Config(**b, surrogate=mode, prescreen_frac=0.25, audit=256, surrogate_hidden=256,
-                         surrogate_buffer=50000, surrogate_batch=1024, mse_threshold=target,
+                         surrogate_buffer=50000, surrogate_batch=2048, surrogate_steps=16,
+                         mse_threshold=target,
                          max_generations=4 * args.generations)
             r, el, log = timed_run(cfg)
             G = r["generations"]

@@ -627,8 +627,8 @@ void game_config_default(game_config* c) {
   c->surrogate = GAME_SURROGATE_NONE;
   c->surrogate_hidden = 256;
   c->surrogate_buffer = 50000;
-  c->surrogate_steps = 32;
-  c->surrogate_batch = 1024;
+  c->surrogate_steps = 16;
+  c->surrogate_batch = 2048;
   c->audit = 256;
   c->prescreen_frac = 0.25;
   c->surrogate_lr = 3e-3;

@@ -39,8 +39,8 @@ class Config:
     surrogate: str = "none"           # offspring form prescreen: none | mlp | random
     surrogate_hidden: int = 256
     surrogate_buffer: int = 50000
-    surrogate_steps: int = 32
-    surrogate_batch: int = 1024
+    surrogate_steps: int = 16
+    surrogate_batch: int = 2048
     audit: int = 256
     prescreen_frac: float = 0.25
     surrogate_lr: float = 3e-3
