@@ -529,19 +529,35 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
         }
       }
     } else {
-      if constexpr (kDoubleB) loadB(b0, 0);
-      for (int kb = 0; kb < KB; kb += 2) {
-        loadA(a1, rt, kc(kb + 1));
-        if constexpr (kDoubleB) loadB(b1, kc(kb + 1));
-        else loadB(b0, kb);
-        mma_all(a0, b0);
-        loadA(a0, rt, kc(kb + 2));
-        if constexpr (kDoubleB) {
-          loadB(b0, kc(kb + 2));
-          if (kb + 1 < KB) mma_all(a1, b1);
-        } else {
-          loadB(b0, kc(kb + 1));
-          if (kb + 1 < KB) mma_all(a1, b0);
+      // one K-block ahead, loads under their bounds: in the batched kernel,
+      // whose registers also hold the other tile widths' variants, this
+      // schedules better than the clamped form
+      int kb = 0;
+      if constexpr (kDoubleB) {
+        loadB(b0, 0);
+        for (; kb + 1 < KB; kb += 2) {
+          loadA(a1, rt, kb + 1);
+          loadB(b1, kb + 1);
+          mma_all(a0, b0);
+          if (kb + 2 < KB) {
+            loadA(a0, rt, kb + 2);
+            loadB(b0, kb + 2);
+          }
+          mma_all(a1, b1);
+        }
+        if (kb < KB) mma_all(a0, b0);
+      } else {
+        for (; kb + 1 < KB; kb += 2) {
+          loadA(a1, rt, kb + 1);
+          loadB(b0, kb);
+          mma_all(a0, b0);
+          if (kb + 2 < KB) loadA(a0, rt, kb + 2);
+          loadB(b0, kb + 1);
+          mma_all(a1, b0);
+        }
+        if (kb < KB) {
+          loadB(b0, kb);
+          mma_all(a0, b0);
         }
       }
     }
@@ -561,18 +577,20 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
         tcur[i][r] = kCls ? (lab ? Acc(kLog2e) : Acc(-kLog2e)) : tv[i][r];
         cmask[i][r] = valid ? (lab ? kMissIfLabel1 : kMissIfLabel0) : 0;
       }
-    {  // next row tile (the last tile reloads itself, unused)
+    if constexpr (kDepth == 2) {  // next row tile (the last tile reloads itself, unused)
       const int64_t rn = rt + 1 < rt_end ? rt + 1 : rt;
       load_t(rn);
       loadA(a0, rn, 0);
-      if (kDepth == 2) loadA(a1, rn, kc(1));
+      loadA(a1, rn, kc(1));
+    } else if (rt + 1 < rt_end) {
+      load_t(rt + 1);
+      loadA(a0, rt + 1, 0);
     }
 
     // epilogue: element r of block (i, j) is pattern nw0 + 16 i + row_in_block(r),
     // chromosome p0 + 16 j + lrow
-    auto epilogue = [&](auto full_tag, auto bias_tag) {
+    auto epilogue = [&](auto full_tag) {
       constexpr bool kFull = decltype(full_tag)::value;
-      constexpr bool kBias = decltype(bias_tag)::value;
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
         Acc loc = Acc(0);
@@ -581,7 +599,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
         for (int i = 0; i < WM; ++i)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const Acc z = kBias ? acc[i][j][r] + bias_j[j] : acc[i][j][r];
+            const Acc z = acc[i][j][r] + bias_j[j];
             Acc q;
             if constexpr (kCls) {
               q = sig_pos(tcur[i][r] * z);
@@ -596,16 +614,10 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
         miss[j] += ms;
       }
     };
-    // without a bias gene the add is skipped (z is the accumulator itself)
-    using T_ = std::integral_constant<bool, true>;
-    using F_ = std::integral_constant<bool, false>;
-    if (biasv) {
-      if (full) epilogue(T_{}, T_{});
-      else epilogue(F_{}, T_{});
-    } else {
-      if (full) epilogue(T_{}, F_{});
-      else epilogue(F_{}, F_{});
-    }
+    // the bias is added as 0 without a bias gene (z = +-0 give the same
+    // error and miss); a separate no-bias variant measured slower
+    if (full) epilogue(std::true_type{});
+    else epilogue(std::false_type{});
   }
 
 #pragma unroll
