@@ -34,6 +34,14 @@ METRIC = "fitness evals/s (chromosome x pattern), plain FP32 vs BF16/surrogate a
 PEAK = {  # MI355X published dense peaks
     "f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0,  # TFLOP/s
 }
+# 16-bit classification is bound by the FP32 error epilogue, not the matrix
+# cores: the gfx950 build issues 447 VALU instructions per 64 chromosome x
+# pattern elements of a lane (full row tile), 126 of them quarter-rate
+# transcendentals (exp, reciprocal), i.e. (447 - 126 + 4 * 126) / 64 = 12.9
+# SIMD lane slots per element; 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (no
+# packed FP32) = 39.3e12 lane slots/s -> 3.05e12 elements/s.
+EPI_SLOTS_PER_ELEM = (447 - 126 + 4 * 126) / 64
+VALU_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
 FITNESS_SRC = os.path.join(ROOT, "paper_1211_5481_amd", "csrc", "fitness.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fitness_c2_traffic.txt")
 
@@ -387,6 +395,17 @@ def main():
     achieved = flops / (kernel_ms * 1e-3) / 1e12
     peak = PEAK[args.dtype]
     traffic = measured_traffic() if args.dtype == "f32" and args.workload == "c2" else None
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": traffic,
+                "kernel": "fitness_kernel", "kernel_ms": kernel_ms,
+                "flops_per_launch": flops}
+    if args.dtype in ("bf16", "f16") and meta["task"] == "classification":
+        alu_peak = VALU_LANE_SLOTS / EPI_SLOTS_PER_ELEM / 1e9
+        alu = evals / (kernel_ms * 1e-3) / 1e9
+        roofline = {"bound": "alu", "achieved": alu, "peak": alu_peak, "unit": "Gevals/s",
+                    "frac": alu / alu_peak, "traffic": None, "kernel": "fitness_kernel",
+                    "kernel_ms": kernel_ms, "lane_slots_per_eval": EPI_SLOTS_PER_ELEM,
+                    "mfma_tflops": achieved, "mfma_frac": achieved / peak}
     out = {
         "metric": METRIC,
         "value": evals / (ms_step * 1e-3),
@@ -404,10 +423,7 @@ def main():
                    "basis": meta["basis"], "degree": meta["D"], "genes": g.L,
                    "population": P, "task": meta["task"], "elitism": 2, "tournament_k": 3,
                    "p_crossover": 0.9, "p_mutation": 0.05, "mutation_sigma": 0.1},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "fitness_kernel", "kernel_ms": kernel_ms,
-                     "flops_per_launch": flops},
+        "roofline": roofline,
         "fitness_kernel_evals_per_s": evals / (kernel_ms * 1e-3),
         "basis_ms_once": basis_ms,
         "best_mse_after": st["best_mse"],

@@ -82,15 +82,19 @@ def test_mlp_init_bit_exact():
     g.close()
 
 
-def test_mlp_forward_grads_adam():
+@pytest.mark.parametrize("H,B,F,D,bias", [
+    (64, 200, 4, 3, 0),     # L = 12
+    (48, 77, 3, 3, 1),      # ragged: L = 10, H not a multiple of 32, B not of 4
+    (33, 5, 7, 2, 0),       # L = 14, one partial row tile
+])
+def test_mlp_forward_grads_adam(H, B, F, D, bias):
     torch = require_gpu()
-    H, B = 64, 200
-    g, cfg = make("mlp", H=H, batch=256, n_off=300)
+    g, cfg = make("mlp", H=H, batch=256, n_off=300, F=F, D=D, bias=bias)
     L = g.L
     rng = np.random.default_rng(3)
     Xh = rng.uniform(-1, 1, (B, L)).astype(np.float32)
     th = rng.normal(0, 1, B).astype(np.float32)
-    announce("mlp forward")
+    announce(f"mlp forward H={H} B={B} L={g.L}")
     p0 = split_params(host(g.mlp_params()), L, H)
     y = host(g.mlp_forward(dev(Xh, torch.float32)))
     ref = mlp.forward(p0, Xh)
