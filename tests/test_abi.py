@@ -76,6 +76,8 @@ def test_query_derived_sizes():
     (dict(max_generations=0), L.GAME_E_INVALID),
     (dict(bias=2), L.GAME_E_INVALID),
     (dict(n_features=600, degree=8, basis="trig"), L.GAME_E_INVALID),
+    (dict(n_features=256, degree=8, basis="trig"), L.GAME_OK),              # L = 4096, the limit
+    (dict(n_features=256, degree=8, basis="trig", bias=1), L.GAME_E_INVALID),  # L = 4097
     (dict(n_offspring=7), L.GAME_E_INVALID),            # cannot refill P - elitism
     (dict(n_offspring=9000), L.GAME_E_INVALID),
     (dict(surrogate="mlp", n_offspring=80, prescreen_frac=0.1), L.GAME_E_INVALID),
