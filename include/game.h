@@ -370,9 +370,12 @@ game_status game_load(game_ctx* ctx, const void* host_buf, size_t bytes);
 game_status game_get_state(game_ctx* ctx, game_state* out, float* best_genes_host);
 
 /*
- * Measurement: launch only the fitness contraction kernel for the current
- * population `reps` times on the context's stream, bracketed by two HIP
- * events, and report the mean duration of one launch in *ms.  Blocking.
+ * Measurement: launch only the fitness kernel for the current population
+ * `reps` times on the context's stream, bracketed by two HIP events, and
+ * report the mean duration of one launch in *ms.  Blocking.  Each launch is
+ * the one a generation runs (contraction, reduction, ranking and best
+ * tracking), so the state is updated as by an evaluation of the current
+ * population (game_eval_fitness with genes NULL).
  * The population's gene tile is packed once before the timed launches.
  */
 game_status game_time_fitness(game_ctx* ctx, int32_t reps, float* ms);

@@ -1164,7 +1164,8 @@ game_status game_time_fitness(game_ctx* c, int32_t reps, float* ms) {
   if (reps < 1 || !ms) return fail(GAME_E_INVALID, "reps must be >= 1 and ms non-NULL");
   const Plan& p = c->plan;
   if (!c->tile_fresh) GAME_TRY(enqueue_pack_population(c, c->stream));
-  const FitTail tail = make_tail(c, p.P, false, nullptr, nullptr, nullptr);
+  // the population tail (ranking, best tracking) as in a generation
+  const FitTail tail = make_tail(c, p.P, true, nullptr, nullptr, nullptr);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   GAME_TRY(dev(c, hipEventCreate(&e0), "event create"));
   game_status s = dev(c, hipEventCreate(&e1), "event create");
