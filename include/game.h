@@ -7,7 +7,9 @@
  *   - every pattern (f_1..f_F, t) has each feature expanded in a polynomial
  *     sequence of degree D (eq. 1; the trigonometric "polytrigo" sequence of
  *     eq. 6 has cos and sin groups, B = 2), giving the basis row
- *     Phi[n, i*K + k] = phi_{k+1}(x[n, i]),  K = B*D,  M = F*K;
+ *     Phi[n, i*K + k] = phi_{k+1}(x[n, i]),  K = B*D,  M = F*K
+ *     (with `shared`, the paper's literal model of one coefficient per basis
+ *     function for all features: Phi[n, k] = sum_i phi_{k+1}(x[n, i]), M = K);
  *   - a chromosome holds one coefficient (gene) per basis column, plus an
  *     optional constant a_0 stored last (L = M or M + 1 genes), and its output
  *     on pattern n is z = sum_m Phi[n, m] G[m] (+ a_0)  (eq. 2);
@@ -16,10 +18,11 @@
  *     (eq. 3 with the logistic output); a chromosome's error is the mean over
  *     all patterns (MSE) and its fitness is 1 - MSE; a pattern counts as
  *     misclassified when [z >= 0] differs from l;
- *   - a generation applies elitism, tournament selection, one-point
- *     crossover and Gaussian mutation, with genes kept in [-1, 1] (Sec. 3
- *     operator list; Sec. 5 rates), every random draw coming from a
- *     Philox4x32-10 counter (Salmon et al., SC'11) keyed by the seed;
+ *   - a generation applies elitism, tournament, roulette or ranking
+ *     selection, one-point crossover, Gaussian mutation and optional random
+ *     immigrants, with genes kept in [-1, 1] (Sec. 3 operator list; Sec. 4;
+ *     Sec. 5 rates), every random draw coming from a Philox4x32-10 counter
+ *     (Salmon et al., SC'11) keyed by the seed;
  *   - training repeats evaluation and evolution until a generation count or
  *     an error threshold is reached (Sec. 4).
  *
