@@ -15,20 +15,22 @@ def bits(a, dt=np.uint32):
     return np.ascontiguousarray(a).view(dt)
 
 
-def make_runs(specs, dtype="f32"):
-    """specs: (task, N, F, D, P, max_generations, threshold, seed)."""
+def make_runs(specs, dtype="f32", extra=None):
+    """specs: (task, N, F, D, P, max_generations, threshold, seed); extra:
+    per-run dicts of further Config fields."""
     torch = require_gpu()
     from paper_1211_5481_amd import Config
     runs = []
-    for task, N, F, D, P, G, thr, seed in specs:
+    for n, (task, N, F, D, P, G, thr, seed) in enumerate(specs):
         if task == "classification":
             X, t = synth.classification_dataset(N, F, seed=seed)
             basis = "trig"
         else:
             X, t, _ = synth.regression_dataset(N, F, 3, 0.05, seed=seed)
             basis = "chebyshev"
+        kw = extra[n] if extra else {}
         cfg = Config(n_patterns=N, n_features=F, degree=D, basis=basis, task=task, dtype=dtype,
-                     pop_size=P, max_generations=G, mse_threshold=thr, seed=seed + 1000)
+                     pop_size=P, max_generations=G, mse_threshold=thr, seed=seed + 1000, **kw)
         runs.append((cfg, dev(X, torch.float32), dev(t, torch.float32)))
     return runs
 
@@ -173,3 +175,26 @@ def test_full_batched_workload_sampled():
                              sp["task"], Phi=Phi)["mse"]
         assert mse.min() >= ref * (1 - 2e-5), f"run {i}"
     b.close()
+
+
+def test_batch_with_immigrants_and_shared_model_equals_runs_alone():
+    """Runs with random immigrants, the shared-coefficient model and a bias
+    gene batch like any other run."""
+    from paper_1211_5481_amd import Batch
+    extra = [dict(n_immigrants=20), dict(shared=1, bias=1), dict(shared=1, n_immigrants=5),
+             dict(bias=1), {}, dict(n_immigrants=100)]
+    runs = make_runs(SPECS, extra=extra)
+    announce("batched runs with immigrants / shared model vs alone")
+    b = Batch(runs)
+    results = b.run()
+    compare_with_alone(b, runs, results)
+    b.close()
+
+
+def test_batch_rejects_wheel_selection():
+    torch = require_gpu()
+    from paper_1211_5481_amd import Batch, _lib
+    runs = make_runs(SPECS[:2], extra=[dict(selection="roulette"), {}])
+    with pytest.raises(_lib.GameError) as e:
+        Batch(runs)
+    assert e.value.status == _lib.GAME_E_UNSUPPORTED
