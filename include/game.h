@@ -391,7 +391,8 @@ void game_destroy(game_ctx* ctx);
  * configuration, patterns, population and stop rule) advanced together.
  * Every generation is one persistent fitness launch in which workgroups take
  * (run, chromosome tile, row range) items from a device queue, followed by
- * one breed launch over all runs; chunks of generations are replayed from a
+ * the wheel or rank order of each roulette / ranking run and one breed
+ * launch over all runs; chunks of generations are replayed from a
  * captured HIP graph.  Requirements: 1..4096 runs, one dtype for all (F32,
  * BF16 or F16), the generational GA (no offspring form, no re-score), gene
  * counts whose tiles fit the LDS-staged kernel.  Each run computes exactly

@@ -1261,8 +1261,6 @@ game_status batch_layout(const game_config* cfgs, int n, BatchLayout* L, int* dt
     if (p.offspring || cfgs[i].rescore_top > 0)
       return fail(GAME_E_UNSUPPORTED, "run %d: the batched form runs the generational GA only", i);
     if (!p.lds) return fail(GAME_E_UNSUPPORTED, "run %d: too many genes for the LDS-staged kernel", i);
-    if (cfgs[i].selection != GAME_SEL_TOURNAMENT)
-      return fail(GAME_E_UNSUPPORTED, "run %d: the batched form selects by tournament", i);
     L->ws_off[i] = off;
     off = align256(off + p.total);
     G = std::max(G, cfgs[i].max_generations);
@@ -1453,6 +1451,10 @@ game_status batch_graph(game_batch* b) {
   game_status st = GAME_OK;
   for (int i = 0; i < kBatchChunk && st == GAME_OK; ++i) {
     st = batch_fitness(b, b->cap, true);
+    // roulette / ranking runs build their wheel or rank order first
+    for (int r = 0; r < b->n && st == GAME_OK; ++r)
+      if (b->ctx[r]->cfg.selection != GAME_SEL_TOURNAMENT)
+        st = enqueue_select_prep(b->ctx[r], b->ctx[r]->fit, b->cap);
     if (st == GAME_OK)
       st = bdev(b, launch_breed_batch(b->dtype, b->dbreed, b->n, b->breed_grid, b->q, b->G, b->cap), "batched breed");
   }

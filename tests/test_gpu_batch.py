@@ -191,10 +191,15 @@ def test_batch_with_immigrants_and_shared_model_equals_runs_alone():
     b.close()
 
 
-def test_batch_rejects_wheel_selection():
-    torch = require_gpu()
-    from paper_1211_5481_amd import Batch, _lib
-    runs = make_runs(SPECS[:2], extra=[dict(selection="roulette"), {}])
-    with pytest.raises(_lib.GameError) as e:
-        Batch(runs)
-    assert e.value.status == _lib.GAME_E_UNSUPPORTED
+def test_batch_with_wheel_selection_equals_runs_alone():
+    """Roulette and ranking runs in a batch (each builds its wheel or rank
+    order before the batched breed) equal the same runs alone."""
+    from paper_1211_5481_amd import Batch
+    extra = [dict(selection="roulette"), dict(selection="ranking"), {},
+             dict(selection="ranking", n_immigrants=10), dict(selection="roulette", bias=1), {}]
+    runs = make_runs(SPECS, extra=extra)
+    announce("batched roulette / ranking runs vs alone")
+    b = Batch(runs)
+    results = b.run()
+    compare_with_alone(b, runs, results)
+    b.close()
