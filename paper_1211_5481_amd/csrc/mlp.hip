@@ -116,8 +116,9 @@ __device__ __forceinline__ bool aligned16(const void* p) { return (reinterpret_c
 // 16-wide k groups w, w + NW, ...; in a group, lane (i, q) supplies rows i and
 // 16 + i of both operands at k = 4q .. 4q + 3 (fa / fb return those four
 // values), one MFMA per k of the four, so every k of the group is used
-// exactly once.  The waves' partial tiles go to `red` (NW x 4 x 64 v4f,
-// 4 KiB per wave).
+// exactly once.  The next group's operands are loaded before the current
+// group's MFMAs, so two groups' loads are in flight.  The waves' partial
+// tiles go to `red` (NW x 4 x 64 v4f, 4 KiB per wave).
 template <int NW, class FA, class FB>
 __device__ __forceinline__ void tile_product(int K, FA fa, FB fb, v4f* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -127,16 +128,31 @@ __device__ __forceinline__ void tile_product(int K, FA fa, FB fb, v4f* red) {
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k0 = wave * 16; k0 < K; k0 += 16 * NW) {
+  int k0 = wave * 16;
+  v4f a0, a1, b0, b1;
+  if (k0 < K) {
     const int k = k0 + 4 * q;
-    const v4f a0 = fa(i, k), a1 = fa(16 + i, k);
-    const v4f b0 = fb(i, k), b1 = fb(16 + i, k);
+    a0 = fa(i, k);
+    a1 = fa(16 + i, k);
+    b0 = fb(i, k);
+    b1 = fb(16 + i, k);
+  }
+  for (; k0 < K; k0 += 16 * NW) {
+    const v4f c0 = a0, c1 = a1, d0 = b0, d1 = b1;
+    const int kn = k0 + 16 * NW;
+    if (kn < K) {
+      const int k = kn + 4 * q;
+      a0 = fa(i, k);
+      a1 = fa(16 + i, k);
+      b0 = fb(i, k);
+      b1 = fb(16 + i, k);
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], b0[s], acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], b1[s], acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], b0[s], acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], b1[s], acc[1][1], 0, 0, 0);
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(c0[s], d0[s], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(c0[s], d1[s], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(c1[s], d0[s], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(c1[s], d1[s], acc[1][1], 0, 0, 0);
     }
   }
 #pragma unroll
