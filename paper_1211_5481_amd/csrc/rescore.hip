@@ -9,7 +9,8 @@
 // (eq. 3; classification against the class label) in double.  In the
 // shared-coefficient model (M == K) a pattern's basis value k is the sum over
 // its features in double, rounded to float32 once, as the FP32 path stores
-// it; the sums are formed eight columns at a time in registers.  Block sums
+// it; each column re-runs the features' recurrences (K times the work of the
+// per-feature model, but no per-column array).  Block sums
 // are combined in a fixed order by the last workgroup to arrive, so results
 // are bit-reproducible.  For a population evaluation the same workgroup then
 // tracks the best chromosome by the float32 MSE and applies the stop test.
@@ -76,24 +77,19 @@ __global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
     float z[kMaxRescore];
 #pragma unroll
     for (int e = 0; e < kMaxRescore; ++e) z[e] = 0.0f;
-    for (int k0 = 0; shared && k0 < a.K; k0 += 8) {
-      double acc[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-      for (int i = 0; i < a.F; ++i)
-        expand_feature(a.basis, a.D, (double)a.X[nrow * a.F + i], [&](int k, double val) {
-#pragma unroll
-          for (int q = 0; q < 8; ++q)
-            if (k - k0 == q) acc[q] += val;
+    for (int k = 0; shared && k < a.K; ++k) {
+      double sum = 0.0;
+      for (int i = 0; i < a.F; ++i) {
+        double v = 0.0;
+        expand_feature(a.basis, a.D, (double)a.X[nrow * a.F + i], [&](int kk, double val) {
+          if (kk == k) v = val;
         });
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (k0 + q >= a.K) break;
-        const float vf = (float)acc[q];
-#pragma unroll
-        for (int e = 0; e < kMaxRescore; ++e)
-          if (e < a.n) z[e] = fmaf(vf, g_lds[e * a.L + k0 + q], z[e]);
+        sum += v;
       }
+      const float vf = (float)sum;
+#pragma unroll
+      for (int e = 0; e < kMaxRescore; ++e)
+        if (e < a.n) z[e] = fmaf(vf, g_lds[e * a.L + k], z[e]);
     }
     for (int i = 0; !shared && i < a.F; ++i) {
       const float* gi = g_lds + i * a.K;
