@@ -198,3 +198,34 @@ def test_tile_widths_and_row_groups(case):
     assert np.array_equal(again.view(np.uint64), mse.view(np.uint64))
     g.close()
     h.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_nan_and_saturating_chromosomes(dtype):
+    """A NaN gene makes every output NaN: the MSE is NaN and, z >= 0 being
+    false, every class-1 pattern counts as missed; a chromosome of huge genes
+    saturates the sigmoid, so its error is exactly the share of patterns on
+    the wrong side (oracle in float64, boundary patterns excepted)."""
+    torch = require_gpu()
+    from paper_1211_5481_amd import Config, Game
+    N, F, D = 1000, 4, 3
+    X, t = synth.classification_dataset(N, F, seed=22)
+    cfg = Config(n_patterns=N, n_features=F, degree=D, basis="chebyshev", task="classification",
+                 dtype=dtype, pop_size=16)
+    g = Game(cfg, dev(X, cfg.io_dtype), dev(t, cfg.io_dtype))
+    G = synth.random_population(3, g.L, seed=5)
+    G[0, 3] = np.nan
+    G[1] = np.sign(G[1]) * 1e20
+    announce(f"nan / saturating chromosomes {dtype}")
+    mse, miscls, fit = (host(a) for a in g.eval_fitness(dev(G, torch.float32)))
+    lab1 = np.mean(t >= 0.5)
+    assert np.isnan(mse[0]) and np.isnan(fit[0])
+    assert miscls[0] == lab1
+    Xo, to, Go = oracle_inputs(X, t, G, dtype)
+    ref = model.evaluate(Xo, to, Go[1:2], "chebyshev", D, "classification")
+    # saturated: each pattern's error is 0 or 1, so mse equals the miss rate
+    assert abs(mse[1] - miscls[1]) <= 1.0 / N
+    assert abs(miscls[1] - ref["miscls"][0]) <= 3.0 / N
+    check_against_oracle(X, t, G[2:3], "chebyshev", D, "classification", 0, dtype, mse[2:3],
+                         miscls[2:3], fit[2:3], label="finite")
+    g.close()
