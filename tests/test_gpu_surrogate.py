@@ -325,3 +325,59 @@ def test_advance_equals_steps_in_offspring_form():
     assert a.state() == b.state()
     a.close()
     b.close()
+
+
+def test_workload_c5_full_size_sampled():
+    """The surrogate workload at its benchmarked shape (1M patterns, 16
+    features, Legendre D = 8, P = 2048, 8192 offspring, MLP 128-256-256-1,
+    16 steps of 2048 rows, 256-child audit), one generation after the
+    warm-up: the children are the oracle's, the MLP scores (sampled) match
+    the oracle's forward pass, the prescreen keeps the elites and only
+    children from the oracle's selection by those scores, the survivors'
+    exact MSE (sampled) match the float64 oracle, and the logged Spearman
+    statistics match the oracle's on the device's scores and errors."""
+    torch = require_gpu()
+    from paper_1211_5481_amd import Config, Game
+    from oracle import model
+    N, F, D, P, n_off, A, k = 1_000_000, 16, 8, 2048, 8192, 256, 2048
+    X, t = synth.classification_dataset(N, F, seed=synth.data_seed(3))
+    cfg = Config(n_patterns=N, n_features=F, degree=D, basis="legendre", task="classification",
+                 dtype="f32", pop_size=P, n_offspring=n_off, surrogate="mlp", prescreen_frac=0.25,
+                 audit=A, surrogate_hidden=256, surrogate_buffer=50000, surrogate_batch=2048,
+                 surrogate_steps=16, tournament_k=K_TOURN, p_crossover=PC, p_mutation=PM,
+                 mutation_sigma=SIGMA, seed=synth.ga_seed(5))
+    g = Game(cfg, dev(X, torch.float32), dev(t, torch.float32))
+    announce("c5 full size: warm-up and generation 0")
+    g.step()
+    pop = host(g.population)
+    fit = host(g.eval_fitness()[2])
+    children = children_of(pop, fit, 1, n_off, cfg.seed)
+    params = split_params(host(g.mlp_params()), g.L, 256)
+    announce("c5 full size: scores of the 8192 children")
+    yhat = host(g.mlp_forward(dev(children, torch.float32)))
+    rows = np.random.default_rng(5).choice(n_off, 256, replace=False)
+    ref_y = mlp.forward(params, children[rows])["y"]
+    assert np.abs(yhat[rows] - ref_y).max() <= 1e-4 * max(1.0, np.abs(ref_y).max())
+    sel = rank.smallest_k(yhat, k)
+    aud = rank.smallest_k(rank.random_keys(n_off, 1, rank.TAG_AUDIT, cfg.seed), A)
+    announce("c5 full size: generation 1")
+    g.step()
+    new = host(g.population)
+    E = cfg.elitism
+    assert np.array_equal(bits(new[:E]), bits(pop[ga.elites(fit, E)]))
+    assert drawn_from(children[sel], new[E:])
+    mse_new = host(g.eval_fitness()[0])
+    # the survivors' exact MSE against the float64 oracle (sampled)
+    idx = np.array([0, E, P - 1])
+    Xo = X.astype(np.float32).astype(np.float64)
+    to = t.astype(np.float32).astype(np.float64)
+    ref = model.evaluate(Xo, to, new[idx].astype(np.float64), "legendre", D, "classification")
+    np.testing.assert_allclose(mse_new[idx], ref["mse"], rtol=1e-5)
+    # the logged rank statistics of generation 1, from the device's values
+    mse_sel = host(g.eval_fitness(dev(children[sel], torch.float32))[0])
+    mse_aud = host(g.eval_fitness(dev(children[aud], torch.float32))[0])
+    log = g.surrogate_log()
+    assert log.shape[0] == 2
+    assert abs(log[1, 0] - rank.spearman(yhat[aud], mse_aud)) <= 1e-5
+    assert abs(log[1, 1] - rank.spearman(yhat[sel], mse_sel)) <= 1e-5
+    g.close()
