@@ -395,15 +395,17 @@ def main():
     achieved = flops / (kernel_ms * 1e-3) / 1e12
     peak = PEAK[args.dtype]
     traffic = measured_traffic() if args.dtype == "f32" and args.workload == "c2" else None
+    # FP64 runs the streaming kernel; the other types stage gene tiles in LDS
+    kname = "fitness_kernel" if args.dtype == "f64" else "fitness_lds_kernel"
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic,
-                "kernel": "fitness_kernel", "kernel_ms": kernel_ms,
+                "kernel": kname, "kernel_ms": kernel_ms,
                 "flops_per_launch": flops}
     if args.dtype in ("bf16", "f16") and meta["task"] == "classification":
         alu_peak = VALU_LANE_SLOTS / EPI_SLOTS_PER_ELEM / 1e9
         alu = evals / (kernel_ms * 1e-3) / 1e9
         roofline = {"bound": "alu", "achieved": alu, "peak": alu_peak, "unit": "Gevals/s",
-                    "frac": alu / alu_peak, "traffic": None, "kernel": "fitness_kernel",
+                    "frac": alu / alu_peak, "traffic": None, "kernel": kname,
                     "kernel_ms": kernel_ms, "lane_slots_per_eval": EPI_SLOTS_PER_ELEM,
                     "mfma_tflops": achieved, "mfma_frac": achieved / peak}
     out = {

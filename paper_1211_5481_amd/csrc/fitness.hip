@@ -29,7 +29,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include "game_internal.hpp"
 #include "select.hpp"
@@ -375,46 +377,72 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 }
 
 // Persistent decomposition, used when the gene tile fits in LDS.  The grid
-// holds as many workgroups as can be resident; workgroup (row range wr,
+// holds as many workgroups as can be resident; a work item (row range wr,
 // chromosome tile pt) stages its gene tile in LDS once (row stride padded so
 // the 16 rows a quarter-wave reads sit in distinct banks) and walks its
-// contiguous range of 128-pattern row tiles.  The four waves are stacked over
-// rows, each computing 32 patterns x TP chromosomes (2 x WN blocks of
-// 16 x 16), so every Phi row is read by exactly one wave.  The next row
-// tile's targets and first Phi K-blocks are fetched before the current
-// epilogue.
+// contiguous range of 32-pattern row units.  The four waves of an item take
+// the range's units round-robin, each computing 32 patterns x TP chromosomes
+// (2 x WN blocks of 16 x 16) per unit, so every Phi row is read by exactly
+// one wave.  Range boundaries fall on blocks of ub units: with ub = 4
+// (128-pattern row tiles) the four waves of a range do equal work; with
+// ub = 1 a range of U units gives U mod 4 of its waves one unit more, and
+// which waves those are is rotated by two (item_rot below) between the two
+// workgroups that share a CU, whose waves w run on the same SIMD, so their
+// extra units do not stack on one SIMD.  The host picks the ub whose busiest
+// SIMD carries fewer units (fitness_range_block).  The next unit's targets
+// and first Phi K-blocks are fetched before the current epilogue.
 //
 // One work item of the LDS-staged kernels: chromosome tile pt (TP = 16 WN
-// chromosomes, staged in LDS) against row range wr of n_ranges (consecutive
-// 128-pattern row tiles, 32 rows per wave); writes the range's partial sums
-// part_sse / part_miss[wr][pt * TP ..].  The single-context and the batched
-// kernels run exactly this code, so a chromosome's sums do not depend on
-// which of them evaluated it.  kDepth is how many K-blocks ahead the Phi
-// fragments are loaded (1 or 2): it moves loads, not arithmetic.
+// chromosomes, staged in LDS) against row range wr of n_ranges; writes the
+// range's partial sums part_sse / part_miss[wr][pt * TP ..].  The
+// single-context and the batched kernels run exactly this code, so a
+// chromosome's sums do not depend on which of them evaluated it.  kDepth is
+// how many K-blocks ahead the Phi fragments are loaded (1 or 2): it moves
+// loads, not arithmetic.
+//
+// Rotation of item lt of a launch of n_items items (grid rounded up to a
+// multiple of 8, remapped so each XCD runs a contiguous block of per items).
+// An XCD's dispatcher gives each of its cpx CUs one workgroup before any
+// second, so the k-th and (k + cpx)-th of its items share a CU: with ub = 1
+// they get opposite rotations.  Placement only moves time; the sums of an
+// item depend on (lt, n_items, cpx, ub) alone, which the batched kernel
+// reproduces.
+__device__ __forceinline__ int item_rot(int64_t lt, int64_t n_items, int cpx, int ub) {
+  const int64_t per = (n_items + 7) / 8;
+  return ub == 1 ? 2 * (int)(((lt % per) / cpx) & 1) : 0;
+}
+
 template <class Tr, bool kCls, int WN, int kDepth>
 __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
                                          const typename Tr::T* __restrict__ tile,
                                          const typename Tr::Acc* __restrict__ biasv,
                                          const typename Tr::Acc* __restrict__ tvec, int64_t N,
-                                         int M_pad, int ldsw, int64_t n_rt, int n_ranges, int pt,
-                                         int wr, int part_ld, double* __restrict__ part_sse,
+                                         int M_pad, int ldsw, int n_ranges, int pt, int wr,
+                                         int ub, int rot, int part_ld,
+                                         double* __restrict__ part_sse,
                                          uint32_t* __restrict__ part_miss, uint32_t* lds) {
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
   using AccV = typename Tr::AccV;
   using Ld = typename Tr::Ld;
-  constexpr int WM = 2, TN = 128, TP = 16 * WN;
+  constexpr int WM = 2, TU = 32, TP = 16 * WN;
   constexpr int kLdWords = (int)(sizeof(Ld) / 4);
   constexpr int kBlkWords = Tr::kBlk * (int)sizeof(T) / 4;
   // LDS: the gene tile (TP rows of ldsw words), then the per-wave column sums
   double (*s_sse)[TP] = reinterpret_cast<double (*)[TP]>(lds + TP * ldsw);
   uint32_t (*s_miss)[TP] = reinterpret_cast<uint32_t (*)[TP]>(lds + TP * ldsw + 8 * TP);
 
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // the wave index is uniform in a wave; saying so keeps the unit loop and
+  // the full/ragged test on scalar registers and branches
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lrow = lane & 15, lgrp = lane >> 4;
   const int KB = M_pad / Tr::kBlk;
-  const int64_t rt_begin = (int64_t)wr * n_rt / n_ranges;
-  const int64_t rt_end = (int64_t)(wr + 1) * n_rt / n_ranges;
+  const int64_t n_units = (N + TU - 1) / TU;
+  const int64_t n_blk = (n_units + ub - 1) / ub;
+  const int64_t u_begin = (int64_t)wr * n_blk / n_ranges * ub;
+  const int64_t u_end = min(n_units, (int64_t)(wr + 1) * n_blk / n_ranges * ub);
+  const int64_t u_first = u_begin + ((wave + rot) & 3);  // this wave's units: u_first, +4, ...
 
   // stage the gene tile (rows pt*TP .. +TP) into LDS
   {
@@ -432,7 +460,6 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
   const int bofs0 = lrow * ldsw + lgrp * kLdWords;  // + 16 j ldsw for block j
 
   auto row_in_block = [&](int r) { return Tr::kRowInterleave ? lgrp + 4 * r : 4 * lgrp + r; };
-  auto tile_rows = [&](int64_t rt) { return rt * TN + wave * 32; };
 
   double sse[WN];
   uint32_t miss[WN];
@@ -444,15 +471,15 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
 
   Ld a0[WM], a1[WM], b0[WN], b1[WN];
   Acc tv[WM][4];
-  auto load_t = [&](int64_t rt) {
-    const int64_t nw0 = tile_rows(rt);
+  auto load_t = [&](int64_t u) {
+    const int64_t nw0 = u * TU;
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) tv[i][r] = tvec[nw0 + i * 16 + row_in_block(r)];
   };
-  auto loadA = [&](Ld* a, int64_t rt, int kb) {
-    const int64_t nw0 = tile_rows(rt);
+  auto loadA = [&](Ld* a, int64_t u, int kb) {
+    const int64_t nw0 = u * TU;
 #pragma unroll
     for (int i = 0; i < WM; ++i)
       a[i] = *reinterpret_cast<const Ld*>(phi + (nw0 + i * 16 + lrow) * (int64_t)M_pad +
@@ -464,14 +491,14 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
       b[j] = *reinterpret_cast<const Ld*>(&lds[bofs0 + j * 16 * ldsw + kb * kBlkWords]);
   };
 
-  if (rt_begin < rt_end) {
-    load_t(rt_begin);
-    loadA(a0, rt_begin, 0);
-    if (kDepth == 2) loadA(a1, rt_begin, KB > 1 ? 1 : 0);
+  if (u_first < u_end) {
+    load_t(u_first);
+    loadA(a0, u_first, 0);
+    if (kDepth == 2) loadA(a1, u_first, KB > 1 ? 1 : 0);
   }
   __syncthreads();
 
-  for (int64_t rt = rt_begin; rt < rt_end; ++rt) {
+  for (int64_t u = u_first; u < u_end; u += 4) {
     AccV acc[WM][WN];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
@@ -503,11 +530,11 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
       Ld a2[WM], a3[WM];
       if constexpr (kDoubleB) loadB(b0, 0);
       for (int kb = 0; kb < KB; kb += 4) {
-        loadA(a2, rt, kc(kb + 2));
+        loadA(a2, u, kc(kb + 2));
         if constexpr (kDoubleB) loadB(b1, kc(kb + 1));
         else loadB(b0, kb);
         mma_all(a0, b0);
-        loadA(a3, rt, kc(kb + 3));
+        loadA(a3, u, kc(kb + 3));
         if constexpr (kDoubleB) {
           loadB(b0, kc(kb + 2));
           if (kb + 1 < KB) mma_all(a1, b1);
@@ -515,11 +542,11 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
           loadB(b0, kc(kb + 1));
           if (kb + 1 < KB) mma_all(a1, b0);
         }
-        loadA(a0, rt, kc(kb + 4));
+        loadA(a0, u, kc(kb + 4));
         if constexpr (kDoubleB) loadB(b1, kc(kb + 3));
         else loadB(b0, kc(kb + 2));
         if (kb + 2 < KB) mma_all(a2, b0);
-        loadA(a1, rt, kc(kb + 5));
+        loadA(a1, u, kc(kb + 5));
         if constexpr (kDoubleB) {
           loadB(b0, kc(kb + 4));
           if (kb + 3 < KB) mma_all(a3, b1);
@@ -536,11 +563,11 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
       if constexpr (kDoubleB) {
         loadB(b0, 0);
         for (; kb + 1 < KB; kb += 2) {
-          loadA(a1, rt, kb + 1);
+          loadA(a1, u, kb + 1);
           loadB(b1, kb + 1);
           mma_all(a0, b0);
           if (kb + 2 < KB) {
-            loadA(a0, rt, kb + 2);
+            loadA(a0, u, kb + 2);
             loadB(b0, kb + 2);
           }
           mma_all(a1, b1);
@@ -548,10 +575,10 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
         if (kb < KB) mma_all(a0, b0);
       } else {
         for (; kb + 1 < KB; kb += 2) {
-          loadA(a1, rt, kb + 1);
+          loadA(a1, u, kb + 1);
           loadB(b0, kb);
           mma_all(a0, b0);
-          if (kb + 2 < KB) loadA(a0, rt, kb + 2);
+          if (kb + 2 < KB) loadA(a0, u, kb + 2);
           loadB(b0, kb + 1);
           mma_all(a1, b0);
         }
@@ -563,9 +590,9 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
     }
     (void)b1;
 
-    // this tile's targets -> per-pattern coefficients, then prefetch the next tile
-    const int64_t nw0 = tile_rows(rt);
-    const bool full = (rt + 1) * TN <= N;
+    // this unit's targets -> per-pattern coefficients, then prefetch the next unit
+    const int64_t nw0 = u * TU;
+    const bool full = (u + 1) * TU <= N;
     Acc tcur[WM][4];   // regression: target; classification: -s log2(e)
     int cmask[WM][4];  // classification: class mask of missed outputs
 #pragma unroll
@@ -577,14 +604,14 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
         tcur[i][r] = kCls ? (lab ? Acc(kLog2e) : Acc(-kLog2e)) : tv[i][r];
         cmask[i][r] = valid ? (lab ? kMissIfLabel1 : kMissIfLabel0) : 0;
       }
-    if constexpr (kDepth == 2) {  // next row tile (the last tile reloads itself, unused)
-      const int64_t rn = rt + 1 < rt_end ? rt + 1 : rt;
-      load_t(rn);
-      loadA(a0, rn, 0);
-      loadA(a1, rn, kc(1));
-    } else if (rt + 1 < rt_end) {
-      load_t(rt + 1);
-      loadA(a0, rt + 1, 0);
+    if constexpr (kDepth == 2) {  // next unit (the last unit reloads itself, unused)
+      const int64_t un = u + 4 < u_end ? u + 4 : u;
+      load_t(un);
+      loadA(a0, un, 0);
+      loadA(a1, un, kc(1));
+    } else if (u + 4 < u_end) {
+      load_t(u + 4);
+      loadA(a0, u + 4, 0);
     }
 
     // epilogue: element r of block (i, j) is pattern nw0 + 16 i + row_in_block(r),
@@ -646,7 +673,7 @@ template <class Tr, bool kCls, int WN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fitness_lds_kernel(
     const typename Tr::T* __restrict__ phi, const typename Tr::T* __restrict__ tile,
     const typename Tr::Acc* __restrict__ biasv, const typename Tr::Acc* __restrict__ tvec,
-    int64_t N, int M_pad, int ldsw, int64_t n_rt, int n_pt, int n_ranges, int64_t n_items,
+    int64_t N, int M_pad, int ldsw, int n_pt, int n_ranges, int64_t n_items, int cpx, int ub,
     int part_ld, double* __restrict__ part_sse, uint32_t* __restrict__ part_miss,
     const DevState* st, const FitTail tail) {
   extern __shared__ __align__(16) uint32_t lds[];
@@ -657,8 +684,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   if (lt >= n_items) return;
   const int pt = (int)(lt % n_pt);
   const int wr = (int)(lt / n_pt);
-  lds_item<Tr, kCls, WN, 2>(phi, tile, biasv, tvec, N, M_pad, ldsw, n_rt, n_ranges, pt, wr, part_ld,
-                         part_sse, part_miss, lds);
+  lds_item<Tr, kCls, WN, 2>(phi, tile, biasv, tvec, N, M_pad, ldsw, n_ranges, pt, wr,
+                            ub, item_rot(lt, n_items, cpx, ub), part_ld, part_sse, part_miss,
+                            lds);
   fitness_tail<16 * WN>(tail, pt, n_pt, n_ranges, part_ld, part_sse, part_miss);
 }
 
@@ -670,7 +698,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // resets the queue for the next launch.
 template <class Tr>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fitness_batch_kernel(
-    const BatchFitRun* __restrict__ runs, int n_runs, int64_t n_items, BatchQueue* q,
+    const BatchFitRun* __restrict__ runs, int n_runs, int64_t n_items, int cpx, BatchQueue* q,
     uint64_t* t_start, int t_cap) {
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
@@ -703,11 +731,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const T* tile = static_cast<const T*>(r.tile);
     const Acc* biasv = static_cast<const Acc*>(r.biasv);
     const Acc* tvec = static_cast<const Acc*>(r.tvec);
-#define GAME_BATCH_ITEM(CLS, WN)                                                                   \
-  do {                                                                                             \
-    lds_item<Tr, CLS, WN, 1>(phi, tile, biasv, tvec, r.N, r.M_pad, r.ldsw, r.n_rt, r.n_ranges, pt, wr, \
-                          r.part_ld, r.psse, r.pmiss, lds);                                        \
-    fitness_tail<16 * WN>(r.tail, pt, r.n_pt, r.n_ranges, r.part_ld, r.psse, r.pmiss);             \
+#define GAME_BATCH_ITEM(CLS, WN)                                                                 \
+  do {                                                                                           \
+    lds_item<Tr, CLS, WN, 1>(phi, tile, biasv, tvec, r.N, r.M_pad, r.ldsw, r.n_ranges, pt, wr,   \
+                             r.ub, item_rot(local, (int64_t)r.n_pt * r.n_ranges, cpx, r.ub), \
+                             r.part_ld, r.psse, r.pmiss, lds);                                   \
+    fitness_tail<16 * WN>(r.tail, pt, r.n_pt, r.n_ranges, r.part_ld, r.psse, r.pmiss);           \
   } while (0)
     if (r.task == GAME_CLASSIFICATION) {
       if (r.tile_p == 128) GAME_BATCH_ITEM(true, 8);
@@ -787,6 +816,9 @@ hipError_t lds_prepare(int task, int tp) {
   return e;
 }
 
+int device_cus();
+int cus_per_xcd();
+
 template <class Tr, int WN>
 hipError_t launch_lds_wn(int task, const FitnessGeom& g, const Plan& p, const void* phi,
                          const void* tile, const void* biasv, const void* tvec, double* psse,
@@ -800,12 +832,12 @@ hipError_t launch_lds_wn(int task, const FitnessGeom& g, const Plan& p, const vo
   if (task == GAME_CLASSIFICATION)
     hipLaunchKernelGGL((fitness_lds_kernel<Tr, true, WN>), dim3((unsigned)g.grid), dim3(256), lds, s,
                        (const T*)phi, (const T*)tile, (const Acc*)biasv, (const Acc*)tvec, p.N,
-                       p.M_pad, ldsw, p.n_rt, g.n_pt, (int)g.n_rg, g.n_items, p.P_max_pad, psse,
+                       p.M_pad, ldsw, g.n_pt, (int)g.n_rg, g.n_items, cus_per_xcd(), g.ub, p.P_max_pad, psse,
                        pmiss, st, tail);
   else
     hipLaunchKernelGGL((fitness_lds_kernel<Tr, false, WN>), dim3((unsigned)g.grid), dim3(256), lds,
                        s, (const T*)phi, (const T*)tile, (const Acc*)biasv, (const Acc*)tvec, p.N,
-                       p.M_pad, ldsw, p.n_rt, g.n_pt, (int)g.n_rg, g.n_items, p.P_max_pad, psse,
+                       p.M_pad, ldsw, g.n_pt, (int)g.n_rg, g.n_items, cus_per_xcd(), g.ub, p.P_max_pad, psse,
                        pmiss, st, tail);
   return hipGetLastError();
 }
@@ -825,7 +857,6 @@ hipError_t launch_lds(int task, const FitnessGeom& g, const Plan& p, const void*
   return hipErrorInvalidValue;
 }
 
-// Workgroups of an LDS kernel that are resident at once on the device.
 int device_cus() {
   static int cus = 0;
   if (cus) return cus;
@@ -835,6 +866,13 @@ int device_cus() {
   return cus;
 }
 
+// CUs of one of the 8 XCDs (the dispatcher's unit of workgroup placement).
+int cus_per_xcd() {
+  const int c = device_cus() / 8;
+  return c > 0 ? c : 1;
+}
+
+// Workgroups of an LDS kernel that are resident at once on the device.
 template <class Tr>
 int lds_resident(int task, int M_pad, int tp) {
   static int cache[2][3][8192 / 8 + 1] = {};
@@ -912,7 +950,7 @@ hipError_t batch_launch(const BatchFitRun* runs, int n_runs, int64_t n_items, in
   const hipError_t e = batch_prepare<Tr>();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fitness_batch_kernel<Tr>, dim3((unsigned)grid), dim3(256), lds, s, runs, n_runs,
-                     n_items, q, t_start, t_cap);
+                     n_items, cus_per_xcd(), q, t_start, t_cap);
   return hipGetLastError();
 }
 }  // namespace
@@ -935,6 +973,38 @@ hipError_t launch_fitness_batch(int dtype, const BatchFitRun* runs, int n_runs, 
     case GAME_F16: return batch_launch<F16Tr>(runs, n_runs, n_items, grid, lds, q, t_start, t_cap, s);
   }
   return hipErrorInvalidValue;
+}
+
+// Range boundary block for the LDS kernels (see lds_item): 1 when 32-row
+// units with rotated extra units leave the busiest SIMD fewer units than
+// whole 128-row tiles, else 4.  Placement model: all items resident at once,
+// item lt on XCD lt / per and CU (lt % per) % cpx of it, wave w of every item
+// on SIMD w.  With more items than resident workgroups there is no fixed
+// placement, and tiles are kept.
+int fitness_range_block(int64_t N, int64_t n_rg, int n_pt, int slots) {
+  const int64_t n_items = n_rg * n_pt;
+  if (slots <= 0 || n_items > slots || n_rg < 1) return 4;
+  const int cpx = cus_per_xcd();
+  const int64_t n_units = (N + 31) / 32, per = (n_items + 7) / 8;
+  int64_t worst[2] = {0, 0};
+  std::vector<int64_t> load((size_t)8 * cpx * 4);
+  for (int m = 0; m < 2; ++m) {
+    const int ub = m == 0 ? 4 : 1;
+    const int64_t n_blk = (n_units + ub - 1) / ub;
+    std::fill(load.begin(), load.end(), 0);
+    for (int64_t lt = 0; lt < n_items; ++lt) {
+      const int64_t wr = lt / n_pt, k = lt % per;
+      const int rot = ub == 1 ? 2 * (int)((k / cpx) & 1) : 0;
+      const int64_t b = wr * n_blk / n_rg * ub, e = std::min(n_units, (wr + 1) * n_blk / n_rg * ub);
+      const size_t cu = (size_t)(lt / per) * cpx + (size_t)(k % cpx);
+      for (int w = 0; w < 4; ++w) {
+        const int64_t f = b + ((w + rot) & 3);
+        load[cu * 4 + w] += f < e ? (e - f + 3) / 4 : 0;
+      }
+    }
+    worst[m] = *std::max_element(load.begin(), load.end());
+  }
+  return worst[1] < worst[0] ? 1 : 4;
 }
 
 int fitness_persistent_slots(const Plan& p, int task, int dtype) {

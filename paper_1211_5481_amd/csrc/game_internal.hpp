@@ -157,12 +157,16 @@ struct FitnessGeom {
   int64_t n_rg;    // row groups (= partial rows)
   int64_t n_items; // workgroups doing work
   int64_t grid;    // launched workgroups (multiple of 8)
+  int ub;          // LDS kernels: 32-row units per range boundary block (1 or 4)
 };
 // Workgroups of the persistent (LDS) fitness kernel resident at once, or 0
 // when the configuration uses the non-persistent kernel.
 int fitness_persistent_slots(const Plan& p, int task, int dtype);
 // LDS-staged kernel: does a tile of tp chromosomes fit, and its dynamic LDS
 int fitness_lds_fits(int dtype, int M_pad, int tp);
+// Range boundary block (1 or 4 units of 32 rows) for n_rg row ranges of N
+// patterns and n_pt chromosome tiles, given the resident workgroup count.
+int fitness_range_block(int64_t N, int64_t n_rg, int n_pt, int slots);
 size_t fitness_lds_bytes(int dtype, int M_pad, int tp);
 int fitness_lds_stride(int dtype, int M_pad);  // LDS words per staged gene row
 FitnessGeom fitness_geometry(const Plan& p, int task, int dtype, int P_eval);
@@ -307,7 +311,7 @@ struct BatchFitRun {
   FitTail tail;
   int64_t N, n_rt;
   int64_t item0;      // queue position of this context's first item
-  int M_pad, ldsw, n_pt, n_ranges, part_ld, task, tile_p, pad;
+  int M_pad, ldsw, n_pt, n_ranges, part_ld, task, tile_p, ub;
 };
 // One context's share of a batched breed launch.
 struct BatchBreedRun {

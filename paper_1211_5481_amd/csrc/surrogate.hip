@@ -300,12 +300,6 @@ __global__ void log_kernel(const float* __restrict__ rho, const float* __restric
   ss->n_logged += 1;
 }
 
-int pow2_at_least(int n) {
-  int p = 1;
-  while (p < n) p <<= 1;
-  return p;
-}
-
 }  // namespace
 
 hipError_t sur_keys(int mode, const float* fsrc, const double* dsrc, int n, uint32_t tag,

@@ -86,6 +86,26 @@ def test_batch_equals_runs_alone():
     b.close()
 
 
+def test_batch_benchmark_geometry_equals_alone():
+    """100 000 patterns, 1000 chromosomes in 8 tiles x 64 row ranges: the
+    geometry whose ranges end on 32-row units with rotated extra units (the
+    placement model prefers it to whole row tiles there), next to a run that
+    keeps whole tiles; batched and alone must agree bit for bit."""
+    from paper_1211_5481_amd import Batch, Config
+    specs = [("classification", 100_000, 10, 6, 1000, 3, 0.0, 31),
+             ("regression", 20000, 8, 6, 256, 3, 0.0, 32)]
+    runs = make_runs(specs)
+    fixed = [(128, 64), (64, 16)]
+    runs = [(Config(**{**c.__dict__, "tile_p": tp, "row_groups": rg}), X, t)
+            for (c, X, t), (tp, rg) in zip(runs, fixed)]
+    announce("batched f32 runs at 100000 x 1000 (8 x 64 items) vs alone")
+    b = Batch(runs)
+    assert b.tiles() == ([f[0] for f in fixed], [f[1] for f in fixed])
+    results = b.run()
+    compare_with_alone(b, runs, results)
+    b.close()
+
+
 def test_batch_threshold_and_second_run():
     from paper_1211_5481_amd import Batch, Config, Game
     specs = [("regression", 5000, 6, 4, 128, 30, 0.0, 11),
