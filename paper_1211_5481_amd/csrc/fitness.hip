@@ -444,15 +444,6 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
   const int64_t u_end = min(n_units, (int64_t)(wr + 1) * n_blk / n_ranges * ub);
   const int64_t u_first = u_begin + ((wave + rot) & 3);  // this wave's units: u_first, +4, ...
 
-  // stage the gene tile (rows pt*TP .. +TP) into LDS
-  {
-    const int units = M_pad / Tr::kPerLane;  // Ld units per gene row
-    const Ld* src = reinterpret_cast<const Ld*>(tile + (int64_t)pt * TP * M_pad);
-    for (int v = tid; v < TP * units; v += 256) {
-      const int r = v / units, c = v - r * units;
-      *reinterpret_cast<Ld*>(&lds[r * ldsw + c * kLdWords]) = src[v];
-    }
-  }
   const int p0 = pt * TP;
   Acc bias_j[WN];
 #pragma unroll
@@ -495,6 +486,40 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
     load_t(u_first);
     loadA(a0, u_first, 0);
     if (kDepth == 2) loadA(a1, u_first, KB > 1 ? 1 : 0);
+  }
+  // stage the gene tile (rows pt*TP .. +TP) into LDS with 64 bytes of loads
+  // in flight per thread before their stores (a load-store loop waits out
+  // the full memory latency once per element); the first unit's Phi loads
+  // above are already on their way.  Named registers, not an array, so
+  // nothing is placed in scratch memory.
+  {
+    const int units = M_pad / Tr::kPerLane;  // Ld units per gene row
+    const int total = TP * units;
+    const Ld* src = reinterpret_cast<const Ld*>(tile + (int64_t)pt * TP * M_pad);
+    auto ld = [&](int v) {
+      Ld x{};
+      if (v < total) x = src[v];
+      return x;
+    };
+    auto st = [&](int v, const Ld& x) {
+      if (v < total) {
+        const int r = v / units, c = v - r * units;
+        *reinterpret_cast<Ld*>(&lds[r * ldsw + c * kLdWords]) = x;
+      }
+    };
+    if constexpr (sizeof(Ld) == 8) {
+      for (int v = tid; v < total; v += 256 * 8) {
+        const Ld g0 = ld(v), g1 = ld(v + 256), g2 = ld(v + 512), g3 = ld(v + 768);
+        const Ld g4 = ld(v + 1024), g5 = ld(v + 1280), g6 = ld(v + 1536), g7 = ld(v + 1792);
+        st(v, g0), st(v + 256, g1), st(v + 512, g2), st(v + 768, g3);
+        st(v + 1024, g4), st(v + 1280, g5), st(v + 1536, g6), st(v + 1792, g7);
+      }
+    } else {
+      for (int v = tid; v < total; v += 256 * 4) {
+        const Ld g0 = ld(v), g1 = ld(v + 256), g2 = ld(v + 512), g3 = ld(v + 768);
+        st(v, g0), st(v + 256, g1), st(v + 512, g2), st(v + 768, g3);
+      }
+    }
   }
   __syncthreads();
 
