@@ -154,7 +154,7 @@ __device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, i
   double* s_red = sh.red;
   uint64_t* s_redm = sh.redm;
   // the partial row was stored at agent scope; order it before the arrival
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  agent_stores_done();
   __syncthreads();
   if (threadIdx.x == 0) s_flag = atomicAdd(&t.counters[pt], 1u) == (uint32_t)(n_rg - 1);
   __syncthreads();
@@ -165,17 +165,19 @@ __device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, i
   const int64_t b = seg * chunk, e = min(n_rg, b + chunk);
   double sum = 0.0;
   uint64_t cnt = 0;
+  // 16 rows in flight per thread: these device-scope loads go past the
+  // XCD's L2, so each batch is a full memory round trip
   int64_t r = b;
-  for (; r + 8 <= e; r += 8) {
-    double v[8];
-    uint32_t m[8];
+  for (; r + 16 <= e; r += 16) {
+    double v[16];
+    uint32_t m[16];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 16; ++q) {
       v[q] = ld_agent(psse + (r + q) * part_ld + p);
       m[q] = ld_agent(pmiss + (r + q) * part_ld + p);
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 16; ++q) {
       sum += v[q];
       cnt += m[q];
     }
@@ -203,7 +205,7 @@ __device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, i
     if (t.miscls2) t.miscls2[p] = mc;
     if (t.fit2) t.fit2[p] = f;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  agent_stores_done();
   __syncthreads();
   if (threadIdx.x == 0) {
     t.counters[pt] = 0u;

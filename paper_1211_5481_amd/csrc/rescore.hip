@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
     for (int w = 0; w < kThreads / 64; ++w) s += s_red[w][tid];
     st_agent(a.part + (int64_t)blockIdx.x * 2 * kMaxRescore + tid, s);
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  agent_stores_done();
   __syncthreads();
   if (tid == 0) s_flag = atomicAdd(a.counter, 1u) == gridDim.x - 1;
   __syncthreads();

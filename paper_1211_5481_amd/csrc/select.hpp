@@ -77,24 +77,30 @@ __device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Order this thread's earlier st_agent stores before an arrival count that
+// follows a barrier.  Every value one workgroup of a launch hands to another
+// is written with st_agent (device-scope stores, acknowledged once visible
+// at device scope) and read with ld_agent, so waiting for the stores'
+// acknowledgements is the ordering the consumer needs.  A device-scope
+// release fence would in addition write back the XCD's whole L2 for plain
+// stores, which no workgroup of these launches reads from another; with one
+// such write-back per workgroup it cost 10-13 us of a fitness launch.
+__device__ __forceinline__ void agent_stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // Top n_top indices of fit[0..P) by repeated arg-max, computed by one
 // workgroup of kThreads threads (all of which must call this).  kAgent: fit
-// was written earlier in the same launch by other workgroups.
+// was written earlier in the same launch by other workgroups.  Up to
+// kCache values per thread are read once into registers (all loads in
+// flight together), so the n_top passes cost no further memory round trips;
+// larger P re-reads fit on every pass.
 template <int kThreads, bool kAgent = false>
 __device__ void block_topk(const double* __restrict__ fit, int P, int n_top, int* __restrict__ top) {
+  constexpr int kCache = 8;
   __shared__ int chosen[kMaxElite];
   __shared__ double wkey[kThreads / 64];
   __shared__ int widx[kThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = 0; e < n_top; ++e) {
-    Ranked best{-INFINITY, 0x7fffffff};
-    for (int i = tid; i < P; i += kThreads) {
-      bool taken = false;
-      for (int q = 0; q < e; ++q) taken |= (chosen[q] == i);
-      if (taken) continue;
-      const Ranked c{rank_key(kAgent ? ld_agent(fit + i) : fit[i]), i};
-      if (better(c, best)) best = c;
-    }
+  auto pick = [&](Ranked best, int e) {  // workgroup arg-max of the threads' candidates
     for (int off = 32; off > 0; off >>= 1) {
       const Ranked o{__shfl_xor(best.key, off), __shfl_xor(best.idx, off)};
       if (better(o, best)) best = o;
@@ -114,6 +120,39 @@ __device__ void block_topk(const double* __restrict__ fit, int P, int n_top, int
       top[e] = b.idx;
     }
     __syncthreads();
+  };
+  if (P <= kThreads * kCache) {
+    double key[kCache];
+#pragma unroll
+    for (int q = 0; q < kCache; ++q) {
+      const int i = tid + q * kThreads;
+      key[q] = i < P ? rank_key(kAgent ? ld_agent(fit + i) : fit[i]) : -INFINITY;
+    }
+    uint32_t taken = 0u;  // bit q: value q of this thread already chosen
+    for (int e = 0; e < n_top; ++e) {
+      Ranked best{-INFINITY, 0x7fffffff};
+#pragma unroll
+      for (int q = 0; q < kCache; ++q) {
+        const int i = tid + q * kThreads;
+        const Ranked c{key[q], i};
+        if (i < P && !((taken >> q) & 1u) && better(c, best)) best = c;
+      }
+      pick(best, e);
+      const int w = chosen[e];
+      if (w < P && w % kThreads == tid) taken |= 1u << (w / kThreads);
+    }
+    return;
+  }
+  for (int e = 0; e < n_top; ++e) {
+    Ranked best{-INFINITY, 0x7fffffff};
+    for (int i = tid; i < P; i += kThreads) {
+      bool taken = false;
+      for (int q = 0; q < e; ++q) taken |= (chosen[q] == i);
+      if (taken) continue;
+      const Ranked c{rank_key(kAgent ? ld_agent(fit + i) : fit[i]), i};
+      if (better(c, best)) best = c;
+    }
+    pick(best, e);
   }
 }
 
