@@ -88,6 +88,45 @@ __device__ __forceinline__ int tournament(const BreedArgs& a, uint32_t j, uint32
   return win.idx;
 }
 
+// Both tournaments of pair j with every candidate's fitness load in flight
+// at once (the loop above waits for each load before drawing the next), for
+// k <= kTourMax; the same candidates, compared in the same order.
+constexpr int kTourMax = 8;
+__device__ __forceinline__ void tournament_pair(const BreedArgs& a, uint32_t j, uint32_t g, int* pa,
+                                                int* pb) {
+  int cand[2][kTourMax];
+  double key[2][kTourMax];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+#pragma unroll
+    for (int q = 0; q < kTourMax / 4; ++q) {
+      if (4 * q >= a.k) continue;
+      const u32x4 blk = philox(j, 4u * (uint32_t)s + (uint32_t)q, g, kTagSel, a.k0, a.k1);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) cand[s][4 * q + w] = (int)__umulhi(word_of(blk, w), (uint32_t)a.P);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int i = 0; i < kTourMax; ++i)
+      if (i < a.k) key[s][i] = a.fit[cand[s][i]];
+  int out[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    Ranked win{0.0, -1};
+#pragma unroll
+    for (int i = 0; i < kTourMax; ++i) {
+      if (i >= a.k) continue;
+      const Ranked c{rank_key(key[s][i]), cand[s][i]};
+      if (win.idx < 0 || better(c, win)) win = c;
+    }
+    out[s] = win.idx;
+  }
+  *pa = out[0];
+  *pb = out[1];
+}
+
 // Parent s of pair j: a tournament, or a 64-bit draw r from block
 // (j, s, g, ROULETTE) (word 1 high, word 0 low) scaled to the wheel's integer
 // total, t = floor(r T / 2^64), and the first slot whose cumulative weight
@@ -169,19 +208,23 @@ __device__ __forceinline__ void breed_block(const BreedArgs& a, DevState* st, in
     for (int l = lane; l < a.L; l += 64) put_gene<O, B>(a, dst, wave, l, row[l]);
   } else if (2 * (wave - a.E) < a.n_children) {
     const int j = wave - a.E;
-    const int pa = select_parent(a, (uint32_t)j, 0u, g);
-    const int pb = select_parent(a, (uint32_t)j, 1u, g);
+    int pa, pb;
+    if (a.sel == GAME_SEL_TOURNAMENT && a.k <= kTourMax) {
+      tournament_pair(a, (uint32_t)j, g, &pa, &pb);
+    } else {
+      pa = select_parent(a, (uint32_t)j, 0u, g);
+      pb = select_parent(a, (uint32_t)j, 1u, g);
+    }
     const u32x4 xb = philox((uint32_t)j, 8u, g, kTagSel, a.k0, a.k1);
     int cut = a.L;  // no crossover: child0 = a, child1 = b
     if ((uint64_t)xb.x < a.thr_c && a.L >= 2) cut = 1 + (int)__umulhi(xb.y, (uint32_t)(a.L - 1));
-    const float* ra = src + (int64_t)pa * a.L;
-    const float* rb = src + (int64_t)pb * a.L;
+    const float* __restrict__ ra = src + (int64_t)pa * a.L;
+    const float* __restrict__ rb = src + (int64_t)pb * a.L;
     const uint32_t c0 = 2u * (uint32_t)j, c1 = c0 + 1u;
     const bool has1 = (int)c1 < a.n_children;
     const int first_imm = a.n_children - a.n_imm;  // children from here on are immigrants
     const bool imm0 = (int)c0 >= first_imm, imm1 = (int)c1 >= first_imm;
-    for (int l = lane; l < a.L; l += 64) {
-      const float ga = ra[l], gb = rb[l];
+    auto child_genes = [&](int l, float ga, float gb) {
       const float x0 = l < cut ? ga : gb;
       const float x1 = l < cut ? gb : ga;
       const uint32_t ul = (uint32_t)l;
@@ -190,6 +233,14 @@ __device__ __forceinline__ void breed_block(const BreedArgs& a, DevState* st, in
       if (has1)
         put_gene<O, B>(a, dst, a.E + (int)c1, l,
                        imm1 ? immigrant_gene(c1, ul, g, a) : mutate_gene(x1, c1, ul, g, a));
+    };
+    // two strides of parent genes loaded before the first child gene is stored
+    for (int l = lane; l < a.L; l += 128) {
+      const bool two = l + 64 < a.L;
+      const float ga = ra[l], gb = rb[l];
+      const float ga2 = two ? ra[l + 64] : 0.0f, gb2 = two ? rb[l + 64] : 0.0f;
+      child_genes(l, ga, gb);
+      if (two) child_genes(l + 64, ga2, gb2);
     }
   }
   // The last workgroup to arrive advances the generation.  The barrier waits
