@@ -280,7 +280,7 @@ FitnessGeom fitness_geometry(const Plan& p, int task, int dtype, int P_eval) {
     g.grid = (g.n_items + 7) / 8 * 8;
     // 32-row range blocks where they balance the SIMDs better; FP32 tiles
     // only: the 16-bit classification kernels, bound by the VALU epilogue,
-    // measured 2 % slower with them at 100 000 x 1000 (FP32 1.7 % faster)
+    // measured no faster with them at 100 000 x 1000 (FP32 1.7 % faster)
     g.ub = dtype == GAME_F32 ? fitness_range_block(p.N, R, g.n_pt, slots) : 4;
     return g;
   }
