@@ -165,8 +165,9 @@ __device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, i
   const int64_t b = seg * chunk, e = min(n_rg, b + chunk);
   double sum = 0.0;
   uint64_t cnt = 0;
-  // 16 rows in flight per thread: these device-scope loads go past the
-  // XCD's L2, so each batch is a full memory round trip
+  // 16 rows in flight per thread, the rest of a segment 4 at a time: these
+  // device-scope loads go past the XCD's L2, so each batch is a full memory
+  // round trip
   int64_t r = b;
   for (; r + 16 <= e; r += 16) {
     double v[16];
@@ -182,9 +183,20 @@ __device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, i
       cnt += m[q];
     }
   }
-  for (; r < e; ++r) {
-    sum += ld_agent(psse + r * part_ld + p);
-    cnt += ld_agent(pmiss + r * part_ld + p);
+  for (; r < e; r += 4) {
+    double v[4];
+    uint32_t m[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = r + q < e ? ld_agent(psse + (r + q) * part_ld + p) : 0.0;
+      m[q] = r + q < e ? ld_agent(pmiss + (r + q) * part_ld + p) : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (r + q < e) {
+        sum += v[q];
+        cnt += m[q];
+      }
   }
   s_red[threadIdx.x] = sum;
   s_redm[threadIdx.x] = cnt;
@@ -1011,6 +1023,13 @@ hipError_t launch_fitness_batch(int dtype, const BatchFitRun* runs, int n_runs, 
 int fitness_range_block(int64_t N, int64_t n_rg, int n_pt, int slots) {
   const int64_t n_items = n_rg * n_pt;
   if (slots <= 0 || n_items > slots || n_rg < 1) return 4;
+  // a context asks again for every launch it enqueues: keep the last answer
+  struct Memo {
+    int64_t N, n_rg;
+    int n_pt, slots, ub;
+  };
+  static thread_local Memo memo{-1, -1, -1, -1, 4};
+  if (memo.N == N && memo.n_rg == n_rg && memo.n_pt == n_pt && memo.slots == slots) return memo.ub;
   const int cpx = cus_per_xcd();
   const int64_t n_units = (N + 31) / 32, per = (n_items + 7) / 8;
   int64_t worst[2] = {0, 0};
@@ -1031,7 +1050,8 @@ int fitness_range_block(int64_t N, int64_t n_rg, int n_pt, int slots) {
     }
     worst[m] = *std::max_element(load.begin(), load.end());
   }
-  return worst[1] < worst[0] ? 1 : 4;
+  memo = Memo{N, n_rg, n_pt, slots, worst[1] < worst[0] ? 1 : 4};
+  return memo.ub;
 }
 
 int fitness_persistent_slots(const Plan& p, int task, int dtype) {
