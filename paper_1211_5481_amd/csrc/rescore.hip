@@ -46,6 +46,10 @@ struct RescoreArgs {
   float* best;           // best genes (tracking mode)
 };
 
+// NS = a.n chromosomes (1..kMaxRescore) as a template parameter: the
+// per-basis-value loop over chromosomes then has no runtime guards, which
+// cost more than the arithmetic they guarded.
+template <int NS>
 __global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
   if (run_halted(a.st)) return;
   extern __shared__ float g_lds[];  // n x L genes
@@ -63,10 +67,10 @@ __global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
   }
   __syncthreads();
 
-  double sse[kMaxRescore];
-  double mis[kMaxRescore];
+  double sse[NS];
+  double mis[NS];
 #pragma unroll
-  for (int e = 0; e < kMaxRescore; ++e) {
+  for (int e = 0; e < NS; ++e) {
     sse[e] = 0.0;
     mis[e] = 0.0;
   }
@@ -74,9 +78,9 @@ __global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
   const bool shared = a.M == a.K && a.F > 1;
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   for (int64_t nrow = (int64_t)blockIdx.x * kThreads + tid; nrow < a.N; nrow += stride) {
-    float z[kMaxRescore];
+    float z[NS];
 #pragma unroll
-    for (int e = 0; e < kMaxRescore; ++e) z[e] = 0.0f;
+    for (int e = 0; e < NS; ++e) z[e] = 0.0f;
     for (int k = 0; shared && k < a.K; ++k) {
       double sum = 0.0;
       for (int i = 0; i < a.F; ++i) {
@@ -88,23 +92,20 @@ __global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
       }
       const float vf = (float)sum;
 #pragma unroll
-      for (int e = 0; e < kMaxRescore; ++e)
-        if (e < a.n) z[e] = fmaf(vf, g_lds[e * a.L + k], z[e]);
+      for (int e = 0; e < NS; ++e) z[e] = fmaf(vf, g_lds[e * a.L + k], z[e]);
     }
     for (int i = 0; !shared && i < a.F; ++i) {
       const float* gi = g_lds + i * a.K;
       expand_feature(a.basis, a.D, (double)a.X[nrow * a.F + i], [&](int k, double val) {
         const float vf = (float)val;
 #pragma unroll
-        for (int e = 0; e < kMaxRescore; ++e)
-          if (e < a.n) z[e] = fmaf(vf, gi[e * a.L + k], z[e]);
+        for (int e = 0; e < NS; ++e) z[e] = fmaf(vf, gi[e * a.L + k], z[e]);
       });
     }
     const float tn = a.t[nrow];
     const float lab = tn >= 0.5f ? 1.0f : 0.0f;
 #pragma unroll
-    for (int e = 0; e < kMaxRescore; ++e) {
-      if (e >= a.n) continue;
+    for (int e = 0; e < NS; ++e) {
       const float ze = a.bias ? z[e] + g_lds[e * a.L + a.M] : z[e];
       float d;
       if (a.task == GAME_CLASSIFICATION) {
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
   // fixed-order block reduction: wave shuffle tree, then waves in order
   const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
-  for (int e = 0; e < kMaxRescore; ++e) {
+  for (int e = 0; e < NS; ++e) {
     for (int off = 32; off > 0; off >>= 1) {
       sse[e] += __shfl_xor(sse[e], off);
       mis[e] += __shfl_xor(mis[e], off);
@@ -130,10 +131,13 @@ __global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
     }
   }
   __syncthreads();
-  if (tid < 2 * kMaxRescore) {
+  // value v of a block: sse of chromosome v (v < kMaxRescore), misses of
+  // chromosome v - kMaxRescore; only the first NS of each are used
+  const int v_me = tid < NS ? tid : kMaxRescore + tid - NS;
+  if (tid < 2 * NS) {
     double s = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) s += s_red[w][tid];
-    st_agent(a.part + (int64_t)blockIdx.x * 2 * kMaxRescore + tid, s);
+    for (int w = 0; w < kThreads / 64; ++w) s += s_red[w][v_me];
+    st_agent(a.part + (int64_t)blockIdx.x * 2 * kMaxRescore + v_me, s);
   }
   agent_stores_done();
   __syncthreads();
@@ -145,25 +149,25 @@ __global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
   __shared__ double s_all[kThreads][2 * kMaxRescore];
   __shared__ double s_mse[kMaxRescore], s_mis[kMaxRescore];
   {
-    double acc[2 * kMaxRescore];
+    double acc[2 * NS];
 #pragma unroll
-    for (int v = 0; v < 2 * kMaxRescore; ++v) acc[v] = 0.0;
+    for (int v = 0; v < 2 * NS; ++v) acc[v] = 0.0;
     for (unsigned b = tid; b < gridDim.x; b += kThreads) {
 #pragma unroll
-      for (int v = 0; v < 2 * kMaxRescore; ++v)
-        acc[v] += ld_agent(a.part + (int64_t)b * 2 * kMaxRescore + v);
+      for (int v = 0; v < 2 * NS; ++v)
+        acc[v] += ld_agent(a.part + (int64_t)b * 2 * kMaxRescore + (v < NS ? v : kMaxRescore + v - NS));
     }
 #pragma unroll
-    for (int v = 0; v < 2 * kMaxRescore; ++v) s_all[tid][v] = acc[v];
+    for (int v = 0; v < 2 * NS; ++v) s_all[tid][v < NS ? v : kMaxRescore + v - NS] = acc[v];
   }
   __syncthreads();
-  if (tid < 2 * kMaxRescore) {
+  if (tid < 2 * NS) {
     double s = 0.0;
-    for (int q = 0; q < kThreads; ++q) s += s_all[q][tid];
-    if (tid < kMaxRescore)
+    for (int q = 0; q < kThreads; ++q) s += s_all[q][v_me];
+    if (tid < NS)
       s_mse[tid] = s / (double)a.N;
     else
-      s_mis[tid - kMaxRescore] = s / (double)a.N;
+      s_mis[tid - NS] = s / (double)a.N;
   }
   __syncthreads();
   if (tid < a.n) {
@@ -221,7 +225,21 @@ hipError_t launch_rescore(const float* X, const float* t, int64_t N, int F, int 
   if (n < 1 || n > kMaxRescore) return hipErrorInvalidValue;
   const size_t lds = (size_t)n * L * sizeof(float);
   if (lds > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rescore_kernel, dim3(rescore_grid()), dim3(kThreads), lds, s, a);
+  switch (n) {
+#define GAME_RESCORE_N(NS)                                                                   \
+  case NS:                                                                                   \
+    hipLaunchKernelGGL(rescore_kernel<NS>, dim3(rescore_grid()), dim3(kThreads), lds, s, a); \
+    break;
+    GAME_RESCORE_N(1)
+    GAME_RESCORE_N(2)
+    GAME_RESCORE_N(3)
+    GAME_RESCORE_N(4)
+    GAME_RESCORE_N(5)
+    GAME_RESCORE_N(6)
+    GAME_RESCORE_N(7)
+    GAME_RESCORE_N(8)
+#undef GAME_RESCORE_N
+  }
   return hipGetLastError();
 }
 
