@@ -60,6 +60,15 @@ def workload(name: str, dtype: str):
         return dict(workload="classification N=1000000 F=16 legendre D=8 P=2048",
                     N=N, F=F, D=D, P=P, basis="legendre", task="classification",
                     ga_seed=synth.ga_seed(3)), X, t
+    if name == "c3-shard8":
+        # one GPU's share of the 1M-pattern workload row-sharded over 8 GPUs:
+        # its first 125 000 rows, the whole population
+        N, F, D, P = 125_000, 16, 8, 2048
+        X, t = synth.classification_dataset(1_000_000, F, seed=synth.data_seed(3))
+        return dict(workload="classification N=1000000 F=16 legendre D=8 P=2048, row shard 0 of 8 "
+                             "(N=125000)",
+                    N=N, F=F, D=D, P=P, basis="legendre", task="classification",
+                    ga_seed=synth.ga_seed(3)), X[:N].copy(), t[:N].copy()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -310,8 +319,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16", "f64"])
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c3-shard8", "c4"],
                     help="c2: 100k-pattern trig classification; c3: 1M-pattern Legendre; "
+                         "c3-shard8: one GPU's row shard of c3 over 8 GPUs; "
                          "c4: 64 batched runs of uneven size")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
