@@ -1317,7 +1317,6 @@ game_status batch_tables(game_batch* b) {
     f.st = c->state;
     f.tail = make_tail(c, p.P, true, nullptr, nullptr, nullptr);
     f.N = p.N;
-    f.n_rt = p.n_rt;
     f.M_pad = p.M_pad;
     f.ldsw = fitness_lds_stride(c->cfg.dtype, p.M_pad);
     f.n_pt = g.n_pt;

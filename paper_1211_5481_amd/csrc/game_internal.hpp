@@ -309,7 +309,7 @@ struct BatchFitRun {
   uint32_t* pmiss;
   const DevState* st;
   FitTail tail;
-  int64_t N, n_rt;
+  int64_t N;
   int64_t item0;      // queue position of this context's first item
   int M_pad, ldsw, n_pt, n_ranges, part_ld, task, tile_p, ub;
 };
