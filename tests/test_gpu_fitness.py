@@ -111,6 +111,37 @@ def test_fitness_matches_oracle(case):
     g.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_alternating_populations_never_mix(dtype):
+    """Two populations evaluated in turn, twelve times each: every evaluation
+    equals that population's first bit for bit, so a launch's tail reads the
+    partial rows of its own launch only (values the previous launch left in
+    the same buffers would change the sums), and the first ones match the
+    oracle."""
+    torch = require_gpu()
+    from paper_1211_5481_amd import Config, Game
+    N, F, D, P = 20_000, 10, 6, 1000
+    X, t = synth.classification_dataset(N, F, seed=41)
+    cfg = Config(n_patterns=N, n_features=F, degree=D, basis="trig", task="classification",
+                 dtype=dtype, pop_size=P, seed=43)
+    announce(f"alternating populations {dtype} N={N} P={P}")
+    g = Game(cfg, dev(X, torch.float32), dev(t, torch.float32))
+    pops = [synth.random_population(P, g.L, seed=s) for s in (1, 2)]
+    first = []
+    for G in pops:
+        mse, miscls, fit = (host(a) for a in g.eval_fitness(dev(G, torch.float32)))
+        first.append((mse.copy(), miscls.copy()))
+    check_against_oracle(X, t, pops[0], "trig", D, "classification", bool(cfg.bias), dtype,
+                         first[0][0], first[0][1], 1.0 - first[0][0], label="population A")
+    assert not np.array_equal(first[0][0], first[1][0])
+    for _ in range(12):
+        for G, (mse0, mis0) in zip(pops, first):
+            mse, miscls, _ = (host(a) for a in g.eval_fitness(dev(G, torch.float32)))
+            assert np.array_equal(mse.view(np.uint64), mse0.view(np.uint64))
+            assert np.array_equal(miscls.view(np.uint64), mis0.view(np.uint64))
+    g.close()
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
 def test_special_chromosomes(dtype):
     torch = require_gpu()
