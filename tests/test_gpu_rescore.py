@@ -45,6 +45,33 @@ def test_rescore_explicit_genes(dtype, basis, task, bias):
     g.close()
 
 
+def test_rescore_counts_one_to_eight_agree():
+    """The re-score kernel is compiled per chromosome count (1..8): a set of
+    eight scored together gives, bit for bit, what each scored alone gives
+    (a chromosome's sums do not depend on its neighbours), and matches the
+    oracle."""
+    torch = require_gpu()
+    from paper_1211_5481_amd import Config, Game
+    N, F, D, P = 9000, 5, 6, 32
+    X, t = synth.classification_dataset(N, F, seed=13)
+    cfg = Config(n_patterns=N, n_features=F, degree=D, basis="legendre", task="classification",
+                 dtype="bf16", bias=1, pop_size=P)
+    g = Game(cfg, dev(X, torch.float32), dev(t, torch.float32))
+    G = synth.random_population(8, g.L, seed=17)
+    announce("rescore counts 1..8")
+    all_mse, all_mis = (host(a) for a in g.rescore(dev(G, torch.float32)))
+    ref = oracle_mse(X, t, G, "legendre", D, "classification", 1)
+    np.testing.assert_allclose(all_mse, ref["mse"], rtol=1e-5)
+    for n in range(1, 8):
+        mse, mis = (host(a) for a in g.rescore(dev(G[:n], torch.float32)))
+        assert np.array_equal(mse, all_mse[:n]), n
+        assert np.array_equal(mis, all_mis[:n]), n
+    for i in range(8):
+        mse, _ = (host(a) for a in g.rescore(dev(G[i:i + 1], torch.float32)))
+        assert np.array_equal(mse, all_mse[i:i + 1]), i
+    g.close()
+
+
 def test_bf16_run_tracks_float32_mse_of_elites():
     torch = require_gpu()
     from paper_1211_5481_amd import Config, Game
