@@ -48,6 +48,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fitness_c2_traffic.txt")
 
 def workload(name: str, dtype: str):
     import synth
+    if name == "c1":
+        # the small regression case: launch latency bound (run in FP64)
+        N, F, D, P = 1000, 8, 4, 20
+        X, t, _ = synth.regression_dataset(N, F, 4, 0.05, seed=synth.data_seed(1))
+        return dict(workload="regression N=1000 F=8 chebyshev D=4 P=20",
+                    N=N, F=F, D=D, P=P, basis="chebyshev", task="regression",
+                    ga_seed=synth.ga_seed(1)), X, t
     if name == "c2":
         N, F, D, P = 100_000, 10, 6, 1000
         X, t = synth.classification_dataset(N, F, seed=synth.data_seed(2))
@@ -319,8 +326,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16", "f64"])
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c3-shard8", "c4"],
-                    help="c2: 100k-pattern trig classification; c3: 1M-pattern Legendre; "
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c3-shard8", "c4"],
+                    help="c1: 1000-pattern Chebyshev regression (FP64: --dtype f64); "
+                         "c2: 100k-pattern trig classification; c3: 1M-pattern Legendre; "
                          "c3-shard8: one GPU's row shard of c3 over 8 GPUs; "
                          "c4: 64 batched runs of uneven size")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
