@@ -538,6 +538,10 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
   __syncthreads();
 
   for (int64_t u = u_first; u < u_end; u += 4) {
+    // a wave in its K loop issues before one in its epilogue: the other wave
+    // on the SIMD then fills the MFMA gaps with epilogue VALU work, not the
+    // reverse (FP32 about 1 % faster, 16-bit unchanged)
+    __builtin_amdgcn_s_setprio(1);
     AccV acc[WM][WN];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
@@ -653,6 +657,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
       loadA(a0, u + 4, 0);
     }
 
+    __builtin_amdgcn_s_setprio(0);
     // epilogue: element r of block (i, j) is pattern nw0 + 16 i + row_in_block(r),
     // chromosome p0 + 16 j + lrow
     auto epilogue = [&](auto full_tag) {
