@@ -537,11 +537,16 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
   }
   __syncthreads();
 
+  // Wave priorities of the two phases.  Where the matrix cores bind (FP32,
+  // regression), a wave in its K loop issues ahead of the other wave on the
+  // SIMD in its epilogue, whose VALU work then fills the MFMA gaps (workload
+  // 2 FP32 1 % faster); where the classification epilogue's VALU work binds
+  // (16-bit tiles), the epilogue goes first and the MFMAs fill its gaps
+  // (BF16 10 % faster at 100 000 x 1000, 17 % at 10^6 x 2048).
+  constexpr bool kValuBound = kCls && sizeof(T) == 2;
+  constexpr int kPrioK = kValuBound ? 0 : 1, kPrioEpi = kValuBound ? 1 : 0;
   for (int64_t u = u_first; u < u_end; u += 4) {
-    // a wave in its K loop issues before one in its epilogue: the other wave
-    // on the SIMD then fills the MFMA gaps with epilogue VALU work, not the
-    // reverse (FP32 about 1 % faster, 16-bit unchanged)
-    __builtin_amdgcn_s_setprio(1);
+    __builtin_amdgcn_s_setprio(kPrioK);
     AccV acc[WM][WN];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
@@ -657,7 +662,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
       loadA(a0, u + 4, 0);
     }
 
-    __builtin_amdgcn_s_setprio(0);
+    __builtin_amdgcn_s_setprio(kPrioEpi);
     // epilogue: element r of block (i, j) is pattern nw0 + 16 i + row_in_block(r),
     // chromosome p0 + 16 j + lrow
     auto epilogue = [&](auto full_tag) {
@@ -691,6 +696,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
     else epilogue(std::false_type{});
   }
 
+  __builtin_amdgcn_s_setprio(0);
 #pragma unroll
   for (int j = 0; j < WN; ++j) {
     sse[j] += __shfl_xor(sse[j], 16);
