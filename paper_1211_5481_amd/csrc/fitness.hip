@@ -6,9 +6,13 @@
 //           = (l_n - 1/(1+exp(-z)))^2        (classification, label l_n = [t_n >= 0.5])
 //   miss    = [(z >= 0) != l_n]              (classification)
 // and per chromosome sse = sum_n e, misses = sum_n miss, reduced to
-// mse = sse / N and fitness = 1 - mse by reduce_kernel.
+// mse = sse / N and fitness = 1 - mse by the kernels' tail (fitness_tail).
 //
-// Work decomposition (one workgroup = 4 waves of 64 lanes, 2 x 2):
+// Two kernels share that definition: fitness_lds_kernel (the gene tile
+// staged in LDS, persistent; described with lds_item below) and the
+// streaming fitness_kernel (FP64, and gene counts whose tile does not fit
+// in LDS), whose decomposition is this (one workgroup = 4 waves of 64
+// lanes, 2 x 2):
 //   * a workgroup owns one tile of tile_p chromosomes and a group of
 //     consecutive row tiles of tile_n patterns; Z never leaves registers;
 //   * each wave computes a (16*WM) x (16*WN) block of Z with 16x16 MFMAs,
@@ -20,8 +24,8 @@
 //     tile in the accumulation type, adds that into a double per column, and
 //     after the last row tile reduces the four 16-lane groups by shuffles and
 //     the two row-waves through LDS in a fixed order.  Partial sums go to
-//     part_sse[row_group][p] (double) and part_miss (uint32); no atomics, so
-//     every run is bit-reproducible;
+//     part_sse[row_group][p] (double) and part_miss (uint32); no floating-
+//     point atomics (only arrival counts), so every run is bit-reproducible;
 //   * workgroups sharing a row group run back to back on one XCD (the
 //     dispatcher deals workgroups round-robin over the 8 XCDs; the logical
 //     tile index is remapped so each XCD gets a contiguous range), so the
