@@ -9,8 +9,10 @@ elite chromosomes per generation, MSE threshold 0.001).  The operator
 variants used here: selection by tournament, by fitness-proportionate
 roulette, or by rank-based roulette (linear ranking weights); one-point
 crossover producing two complementary children; per-gene Gaussian mutation
-with clamping to [-1, 1]; optionally the last n_imm children of a generation
-replaced by random immigrants.
+with clamping to [-1, 1] (a mutated gene always lands in the gene range of
+Sec. 3: a NaN sum goes to -1, as the IEEE 754 maxNum/minNum operations
+give); optionally the last n_imm children of a generation replaced by random
+immigrants.
 
 Every random decision is a pure function of a Philox4x32-10 block
 (``oracle.philox``) addressed by a counter (a, b, generation, tag) under the
@@ -194,12 +196,18 @@ def gaussian_ih12(words) -> np.float32:
     return np.float32(s) * np.float32(2.0 ** -25)
 
 
+def clamp_gene(v):
+    """Clamp to [-1, 1] with IEEE 754 maxNum/minNum: a NaN operand yields the
+    other one, so a NaN sum becomes -1 and the result is always a gene value."""
+    return np.fmin(np.fmax(v, np.float32(-1.0)), np.float32(1.0))
+
+
 def mutate_gene(gene: np.float32, words12, sigma32: np.float32) -> np.float32:
     """g' = clamp(fl(g + fl(sigma * z)), -1, 1), float32, no fused multiply-add."""
     z = gaussian_ih12(words12)
     delta = np.float32(sigma32 * z)
     v = np.float32(np.float32(gene) + delta)
-    return np.float32(min(max(v, np.float32(-1.0)), np.float32(1.0)))
+    return np.float32(clamp_gene(v))
 
 
 def _mutation_words(c, l, g: int, seed: int):
@@ -240,7 +248,7 @@ def mutate(children: np.ndarray, g: int, seed: int, p_mutation: float,
     z = s.astype(np.float32) * np.float32(2.0 ** -25)
     delta = np.float32(sigma) * z
     v = children[ci, li] + delta
-    children[ci, li] = np.minimum(np.maximum(v, np.float32(-1.0)), np.float32(1.0))
+    children[ci, li] = clamp_gene(v)
     return children
 
 

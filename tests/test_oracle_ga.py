@@ -95,6 +95,57 @@ def test_vectorised_mutation_equals_scalar_definition():
     assert n_mut > 0
 
 
+def _f32(hexbits: str) -> np.float32:
+    return np.array([int(hexbits, 16)], dtype=np.uint32).view(np.float32)[0]
+
+
+def _hex(v) -> str:
+    return "%08x" % int(np.array([v], dtype=np.float32).view(np.uint32)[0])
+
+
+def test_mutation_hand_derived_float32_bits(golden_dir):
+    """Bits derived by hand with exact arithmetic (tests/golden/mutation_bits.json):
+    float32 rounding of the integer sum S, of sigma * z and of g + delta, each
+    on its own.  A fused multiply-add, a float64 delta or an unrounded S give
+    the other bit patterns the fixture lists."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(golden_dir, "mutation_bits.json")))
+    sigma = _f32(gold["sigma_bits"])
+    assert sigma == np.float32(0.1)
+    cases = gold["cases"]
+    for case in cases:
+        words = [int(w, 16) for w in case["words"]]
+        assert sum(2 * (w >> 8) + 1 for w in words) - 12 * (1 << 24) == case["S"]
+        z = ga.gaussian_ih12(words)
+        assert z == np.float32(case["float32_S"] / 2.0 ** 25)
+        got = ga.mutate_gene(_f32(case["gene_bits"]), words, sigma)
+        assert _hex(got) == case["want_bits"]
+        assert case["want_bits"] not in case["not_bits"].values()
+        # the vectorised path computes the same delta and sum
+        delta = np.float32(sigma * z)
+        assert _hex(delta) == case["delta_bits"]
+    for cc in gold["clamp_cases"]:
+        words = [int(w, 16) for w in cases[cc.get("words_of_case", 0)]["words"]]
+        got = ga.mutate_gene(_f32(cc["gene_bits"]), words, sigma)
+        assert _hex(got) == cc["want_bits"], cc["why"]
+
+
+def test_vectorised_mutation_clamps_nan_and_inf_like_the_scalar_rule():
+    pop = synth.random_population(6, 5, seed=4)
+    pop[0, 0] = np.nan
+    pop[1, 1] = np.inf
+    pop[2, 2] = -np.inf
+    pop[3, 3] = np.array([0x7fa00001], dtype=np.uint32).view(np.float32)[0]   # signalling NaN
+    with np.errstate(invalid="ignore"):          # the signalling NaN raises 'invalid'
+        out = ga.mutate(pop, g=2, seed=9, p_mutation=1.0, sigma=0.1)
+    assert out[0, 0] == -1.0 and out[1, 1] == 1.0 and out[2, 2] == -1.0 and out[3, 3] == -1.0
+    assert np.isfinite(out).all() and out.min() >= -1.0 and out.max() <= 1.0
+    # without mutation a NaN gene is copied bit for bit
+    same = ga.mutate(pop, g=2, seed=9, p_mutation=0.0, sigma=0.1)
+    np.testing.assert_array_equal(same.view(np.uint32), pop.view(np.uint32))
+
+
 def test_mutation_statistics():
     n, L = 400, 64
     pop = np.zeros((n, L), dtype=np.float32)

@@ -118,6 +118,29 @@ def test_minibatch_recent_rows_come_from_latest_append():
     assert mlp.recent_rows(3, 0.5) == 2           # halves round up
 
 
+def test_standardise_is_the_population_standard_deviation():
+    import statistics
+    v = np.random.default_rng(8).normal(-3.0, 0.7, 501)
+    mu, sd = mlp.standardise(v)
+    assert abs(mu - statistics.fmean(v)) <= 1e-12 * abs(mu)
+    assert abs(sd - statistics.pstdev(v)) <= 1e-12 * sd
+    assert abs(sd - statistics.stdev(v)) > 1e-6 * sd          # not the sample (n - 1) form
+    # two values a, b: population std |a - b| / 2
+    assert mlp.standardise([1.0, 4.0]) == (2.5, 1.5)
+    assert mlp.standardise([2.0, 2.0, 2.0]) == (2.0, 1.0)      # constant: unit scale
+
+
+def test_random_keys_are_word_zero_of_the_counter_blocks():
+    from oracle import philox
+    keys = rank.random_keys(37, g=5, tag=rank.TAG_AUDIT, seed=12345)
+    for i in (0, 1, 17, 36):
+        assert keys[i] == philox.philox_block((i, 0, 5, rank.TAG_AUDIT), 12345)[0]
+    other = rank.random_keys(37, g=5, tag=rank.TAG_PRESCREEN, seed=12345)
+    assert other[3] == philox.philox_block((3, 0, 5, rank.TAG_PRESCREEN), 12345)[0]
+    assert not np.array_equal(keys, other)
+    assert keys.min() >= 0 and keys.max() < 2 ** 32 and np.array_equal(keys, np.floor(keys))
+
+
 def test_merge_survivors_keeps_elites_and_best_candidates():
     pop = synth.random_population(10, 4, seed=1)
     fit_pop = synth.random_fitness(10, seed=2)
