@@ -1,6 +1,7 @@
 """Build libgame.so in-tree with hipcc for gfx950.
 
-    python -m paper_1211_5481_amd.build
+    python -m paper_1211_5481_amd.build              # libgame.so
+    python -m paper_1211_5481_amd.build --sanitize   # _build/san/libgame_san.so (host ASan/UBSan)
 
 Compiles every source under csrc/ in parallel and links them into
 paper_1211_5481_amd/libgame.so next to this file.  Always rebuilds.
@@ -29,6 +30,20 @@ HIP_FLAGS = [
 ]
 
 
+# Host-code sanitizers (AddressSanitizer, UndefinedBehaviorSanitizer) for a
+# CPU-side check of the library's host code: every -fsanitize= applies to the
+# host pass only (-Xarch_host), the device code is built as usual.
+SANITIZE_FLAGS = [
+    "-O1", "-g", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+    "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+    f"-I{INCLUDE}", f"-I{CSRC}",
+]
+SAN_BUILD = os.path.join(BUILD, "san")
+SAN_LIB = os.path.join(SAN_BUILD, "libgame_san.so")
+
+
 def hipcc() -> str:
     exe = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(exe):
@@ -41,9 +56,9 @@ def sources():
                   if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), "-x", "hip", *HIP_FLAGS, "-c", src, "-o", obj]
+def _compile(src: str, flags=None, out_dir=None) -> str:
+    obj = os.path.join(out_dir or BUILD, os.path.basename(src) + ".o")
+    cmd = [hipcc(), "-x", "hip", *(flags or HIP_FLAGS), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     err = "\n".join(l for l in r.stderr.splitlines() if noise not in l)
@@ -70,5 +85,39 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+def build_sanitized(verbose: bool = True) -> str:
+    """libgame_san.so under _build/san: the same sources with the host code
+    instrumented by ASan and UBSan (load it with the ASan runtime preloaded,
+    see sanitizer_runtime())."""
+    os.makedirs(SAN_BUILD, exist_ok=True)
+    srcs = sources()
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(lambda f: _compile(f, SANITIZE_FLAGS, SAN_BUILD), srcs))
+    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", *objs, "-o", SAN_LIB]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    if verbose:
+        print(f"built {SAN_LIB}")
+    return SAN_LIB
+
+
+def sanitizer_runtime() -> str:
+    """Path of the ASan runtime shared library of the ROCm clang that built it."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = shutil.which("clang") or "/opt/rocm/llvm/bin/clang"
+    r = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True,
+                       text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("ASan runtime not found")
+    return path
+
+
 if __name__ == "__main__":
-    build()
+    if "--sanitize" in sys.argv[1:]:
+        build_sanitized()
+    else:
+        build()
