@@ -7,8 +7,16 @@ Tolerances (relative, on the MSE of every chromosome):
   bf16/f16   2e-5 against the oracle evaluated on the same rounded Phi and
              genes (isolates accumulation error); the total error against
              the unrounded oracle is reported and only bounded loosely.
-Misclassification counts must agree except on patterns whose oracle output
-is within 1e-4 * sum|Phi G| of the decision boundary z = 0.
+Misclassification counts: a pattern whose oracle output z lies within the
+accumulation bound of the decision boundary z = 0 may fall either way; every
+other pattern must be classified as the oracle does.  The bound, relative to
+sum_m |Phi[n, m] G[m]|, is 1e-12 for f64 (double everywhere; the oracle's
+closed-form basis and the device's recurrences differ by a few ulp of double)
+and (M + 4) 2^-24 for the float32-accumulated forms (M rounded products added
+in float32, plus the rounding of Phi to float32 for f32; for bf16/f16 the
+reference already holds the rounded Phi and genes).  So the device's count
+must lie between the oracle's misses among the far patterns and that number
+plus the count of near ones.
 """
 import numpy as np
 import pytest
@@ -20,6 +28,12 @@ from tests.gpu_util import announce, dev, host, require_gpu
 pytestmark = pytest.mark.gpu
 
 RTOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-5, "f16": 2e-5}
+
+
+def miss_window(dtype, M):
+    """Relative distance to z = 0 within which the device may classify a
+    pattern either way (see the module docstring)."""
+    return 1e-12 if dtype == "f64" else (M + 4) * 2.0 ** -24
 
 
 def make_data(task, N, F, seed):
@@ -61,11 +75,17 @@ def check_against_oracle(X, t, G, basis, D, task, bias, dtype, mse, miscls, fit,
     N = len(t)
     if task == "classification":
         z = ref["z"]
-        scale = np.abs(Phi) @ np.abs(G_r[:, :M] if dtype in ("bf16", "f16") else Go[:, :M]).T
-        near = np.abs(z) <= 1e-4 * np.maximum(scale, 1e-300)
-        cnt_ref = np.round(ref["miscls"] * N)
+        Gm = G_r[:, :M] if dtype in ("bf16", "f16") else Go[:, :M]
+        scale = np.abs(Phi_r if dtype in ("bf16", "f16") else Phi) @ np.abs(Gm).T
+        window = miss_window(dtype, M)
+        near = np.abs(z) <= window * scale
+        label1 = (to >= 0.5)[:, None]
+        miss = (z >= 0.0) != label1
+        far_miss = np.sum(miss & ~near, axis=0)
         cnt_got = np.round(miscls * N)
-        assert np.all(np.abs(cnt_got - cnt_ref) <= near.sum(axis=0)), label
+        n_near = near.sum(axis=0)
+        assert np.all(cnt_got >= far_miss) and np.all(cnt_got <= far_miss + n_near), (
+            label, window, int(np.max(n_near)))
     else:
         assert np.all(miscls == 0.0)
 
@@ -191,10 +211,55 @@ def test_workload_c3_full_size_sampled(dtype):
     g = Game(cfg, dev(X, torch.float32), dev(t, torch.float32))
     mse, miscls, fit = (host(a) for a in g.eval_fitness())
     pop = host(g.population)
-    idx = np.array([0, 1, 777, P - 1])
+    idx = np.concatenate([[0, 1, P - 1], np.random.default_rng(3).choice(
+        np.arange(2, P - 1), 61, replace=False)])
     check_against_oracle(X, t, pop[idx], "legendre", D, "classification", 0, dtype, mse[idx],
                          miscls[idx], fit[idx], label="c3")
     g.close()
+
+
+def test_workload_c3_first_10k_rows_precision():
+    """The precision forms against the float64 oracle on the first 10 000
+    rows of the 1M-pattern Legendre workload (whole population of 2048): the
+    relative MSE error of FP32, BF16 and FP16 against the unrounded oracle is
+    printed (max and median) and bounded; FP16, whose 11-bit significand
+    holds every Phi and gene value in [-1, 1] more finely than BF16's 8, must
+    be the closer of the two; and the FP32 re-score of the 16-bit runs'
+    elites meets the FP32 tolerance."""
+    torch = require_gpu()
+    import json
+    from paper_1211_5481_amd import Config, Game
+    N_all, N, F, D, P = 1_000_000, 10_000, 16, 8, 2048
+    X, t = synth.classification_dataset(N_all, F, seed=synth.data_seed(3))
+    X, t = X[:N].copy(), t[:N].copy()
+    Xo = X.astype(np.float32).astype(np.float64)
+    to = t.astype(np.float32).astype(np.float64)
+    stats = {}
+    ref = None
+    for dtype in ("f32", "bf16", "f16"):
+        cfg = Config(n_patterns=N, n_features=F, degree=D, basis="legendre",
+                     task="classification", dtype=dtype, pop_size=P, seed=synth.ga_seed(3))
+        announce(f"c3 first 10k rows, {dtype}")
+        g = Game(cfg, dev(X, torch.float32), dev(t, torch.float32))
+        pop = host(g.population)
+        mse_t, _, fit_t = g.eval_fitness()
+        mse, fit = host(mse_t), host(fit_t)
+        if ref is None:
+            ref = model.evaluate(Xo, to, pop.astype(np.float64), "legendre", D,
+                                 "classification")["mse"]
+        rel = np.abs(mse - ref) / ref
+        stats[dtype] = {"max": float(rel.max()), "median": float(np.median(rel))}
+        if dtype != "f32":
+            # the elites re-scored in float32 meet the float32 tolerance
+            r_mse = host(g.rescore(None, 2)[0])
+            order = np.lexsort((np.arange(P), -fit))   # fitness desc, index asc
+            np.testing.assert_allclose(r_mse, ref[order[:2]], rtol=1e-5)
+        g.close()
+    print("precision c3 first 10k rows, relative MSE error vs float64 oracle: "
+          + json.dumps(stats))
+    assert stats["f32"]["max"] <= 1e-5
+    assert stats["f16"]["max"] <= 1e-3 and stats["bf16"]["max"] <= 1e-2
+    assert stats["f16"]["median"] < stats["bf16"]["median"]
 
 
 TILE_CASES = [

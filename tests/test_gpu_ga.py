@@ -148,3 +148,35 @@ def test_wheel_selection_and_immigrants_bit_exact(case):
         assert bad.size == 0, f"generation {gen}: first mismatches {bad[:5].tolist()}"
         pop = want
     g.close()
+
+
+@pytest.mark.parametrize("pm", [1.0, 0.3])
+def test_non_finite_and_out_of_range_genes_bit_exact(pm):
+    """Genes the library accepts through set_population but the operators
+    never produce: NaN, +-inf and values outside [-1, 1].  A mutated gene is
+    clamped with IEEE maxNum/minNum (a NaN sum lands on -1, +-inf on +-1), an
+    unmutated one is copied bit for bit, NaN included; the device and the
+    oracle agree bit for bit over three generations."""
+    torch = require_gpu()
+    P, L, seed = 24, 12, 31415
+    g, cfg = make_game(P, L, pm=pm, sigma=0.5, seed=seed)
+    pop = synth.random_population(P, L, seed=9)
+    rng = np.random.default_rng(10)
+    specials = np.array([np.nan, np.inf, -np.inf, 3.5, -7.25, 1e30, -0.0], dtype=np.float32)
+    cells = rng.choice(P * L, 60, replace=False)
+    pop.reshape(-1)[cells] = specials[np.arange(60) % specials.size]
+    g.population = dev(pop, torch.float32)
+    assert np.array_equal(bits(host(g.population)), bits(pop))
+    for gen in range(3):
+        fit = synth.random_fitness(P, seed=gen + 50, n_ties=4, n_nan=1)
+        announce(f"non-finite genes p_m={pm} generation {gen}")
+        g.step(dev(fit, torch.float64))
+        got = host(g.population)
+        want = ga.ga_step(pop, fit, gen, seed, p_mutation=pm, sigma=0.5)
+        bad = np.argwhere(bits(got) != bits(want))
+        assert bad.size == 0, f"generation {gen}: first mismatches {bad[:5].tolist()}"
+        if pm == 1.0:
+            # every child gene went through the clamp
+            assert np.all(np.abs(want[2:]) <= 1.0)
+        pop = want
+    g.close()

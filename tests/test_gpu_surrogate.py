@@ -124,6 +124,52 @@ def test_mlp_forward_grads_adam(H, B, F, D, bias):
     g.close()
 
 
+@pytest.mark.parametrize("B", [2048, 2000])
+def test_mlp_training_at_benchmarked_shape(B):
+    """The surrogate's training products at the benchmarked shape: 128 genes
+    (16 features, Legendre D = 8), two hidden layers of 256 units, minibatches
+    of 2048 rows and a ragged 2000.  Every tile product then runs several
+    16-wide contraction groups per wave (the next group's operands are loaded
+    while the current one multiplies), which the small cases above never
+    reach.  Forward scores, the loss, every gradient element and two Adam
+    steps against the float64 oracle."""
+    torch = require_gpu()
+    H = 256
+    g, cfg = make("mlp", H=H, batch=2048, n_off=2048, F=16, D=8, N=3000)
+    L = g.L
+    assert L == 128
+    rng = np.random.default_rng(B)
+    Xh = rng.uniform(-1, 1, (B, L)).astype(np.float32)
+    th = rng.normal(0, 1, B).astype(np.float32)
+    announce(f"mlp forward at the benchmarked shape H={H} B={B} L={L}")
+    p0 = split_params(host(g.mlp_params()), L, H)
+    y = host(g.mlp_forward(dev(Xh, torch.float32)))
+    ref = mlp.forward(p0, Xh)
+    assert np.abs(y - ref["y"]).max() <= 1e-5 * max(1.0, np.abs(ref["y"]).max())
+    announce(f"mlp grads at the benchmarked shape B={B}")
+    gr, loss = g.mlp_grads(dev(Xh, torch.float32), dev(th, torch.float32))
+    gr = host(gr)
+    ref_loss, ref_g = mlp.loss_and_grads(p0, Xh, th)
+    assert abs(float(host(loss)[0]) - ref_loss) <= 1e-5 * ref_loss
+    got = split_params(gr, L, H)
+    for k in ref_g:
+        tol = 1e-4 * np.abs(ref_g[k]).max() + 1e-9
+        err = np.abs(got[k] - ref_g[k])
+        assert err.max() <= tol, (k, float(err.max()), tol)
+    announce(f"mlp adam at the benchmarked shape B={B}, two steps")
+    m = {k: np.zeros_like(v, dtype=np.float64) for k, v in p0.items()}
+    v = {k: np.zeros_like(v, dtype=np.float64) for k, v in p0.items()}
+    pref = {k: np.asarray(x, np.float64) for k, x in p0.items()}
+    for t in (1, 2):
+        gflat = gr if t == 1 else host(g.mlp_grads(dev(Xh, torch.float32),
+                                                    dev(th, torch.float32))[0])
+        g.mlp_adam(dev(gflat, torch.float32))
+        pref, m, v = mlp.adam_step(pref, split_params(gflat.astype(np.float64), L, H), m, v, t,
+                                   lr=cfg.surrogate_lr)
+        assert np.abs(host(g.mlp_params()) - join_params(pref)).max() <= 2e-6
+    g.close()
+
+
 # ----------------------------------------------------- offspring generations
 def test_offspring_plain_bit_exact():
     torch = require_gpu()
@@ -260,6 +306,47 @@ def test_replay_buffer_and_training():
     diff = np.abs(got - join_params(p))
     # an update at step 1 is +-lr times the sign of each gradient, so an element
     # whose gradient is zero to rounding may move the other way
+    assert np.mean(diff <= 1e-5) >= 0.995
+    assert diff.max() <= 4.0 * cfg.surrogate_lr + 1e-5
+    log = g.surrogate_log()
+    assert abs(log[0, 2] - loss) <= 1e-3 * loss
+    g.close()
+
+
+def test_replay_training_at_benchmarked_shape():
+    """One generation of the learned prescreen with the benchmarked network
+    and minibatch (128 genes, 256-256 hidden, 2048 rows drawn from the
+    replay ring, three quarters of them from the latest generation): the
+    parameters after the set-up step and the generation's step equal the
+    oracle's two Adam steps on the same ring slots and standardised targets."""
+    torch = require_gpu()
+    P, E, n_off, A, B, H, seed = 256, 2, 2048, 256, 2048, 256, 9001
+    g, cfg = make("mlp", P=P, E=E, n_off=n_off, frac=0.25, steps=1, audit=A, batch=B, H=H,
+                  buffer=50000, F=16, D=8, N=3000, seed=seed)
+    k, L = 512, g.L
+    assert L == 128
+    announce("replay training at the benchmarked shape: one generation")
+    g.step()
+    genes, y, count, head, mu, sigma = g.surrogate_buffer()
+    genes, y = host(genes), host(y)
+    n = P + k + A
+    assert count == n and head == n
+    p = {kk: np.asarray(val, np.float64) for kk, val in mlp.init_params(L, H, H, seed).items()}
+    m = {kk: np.zeros_like(val) for kk, val in p.items()}
+    v = {kk: np.zeros_like(val) for kk, val in p.items()}
+    n_rec = mlp.recent_rows(B, cfg.surrogate_recent)
+    loss = None
+    for step, cnt, hd, last in ((0, P, P, P), (1, n, n, k + A)):
+        mu_s, sd_s = mlp.standardise(y[:cnt])
+        slots = mlp.minibatch_slots(step, B, cnt, seed, n_recent=n_rec, head=hd, last=last,
+                                    cap=cfg.surrogate_buffer)
+        loss, gr = mlp.loss_and_grads(p, genes[slots], (y[slots] - mu_s) / sd_s)
+        p, m, v = mlp.adam_step(p, gr, m, v, step + 1, lr=cfg.surrogate_lr)
+    got = host(g.mlp_params())
+    diff = np.abs(got - join_params(p))
+    # Adam's first steps move each parameter by about lr times the sign of its
+    # gradient, so an element whose gradient is zero to rounding may move the
+    # other way
     assert np.mean(diff <= 1e-5) >= 0.995
     assert diff.max() <= 4.0 * cfg.surrogate_lr + 1e-5
     log = g.surrogate_log()

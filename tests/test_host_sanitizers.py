@@ -34,7 +34,8 @@ def test_abi_checks_clean_under_host_asan_and_ubsan():
     except RuntimeError as e:     # no ROCm toolchain here
         pytest.skip(f"sanitized build unavailable: {e}")
     env = dict(os.environ)
-    env["LD_PRELOAD"] = runtime
+    # the ASan runtime must come first; anything already preloaded stays
+    env["LD_PRELOAD"] = os.pathsep.join(x for x in (runtime, env.get("LD_PRELOAD", "")) if x)
     env["ASAN_OPTIONS"] = "detect_leaks=0:halt_on_error=1:abort_on_error=0"
     env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
     env["PYTHONPATH"] = ROOT + os.pathsep + env.get("PYTHONPATH", "")
