@@ -280,6 +280,32 @@ game_status game_rescore(game_ctx* ctx, const float* genes_dev, int32_t n, doubl
                          double* miscls_dev);
 
 /*
+ * For callers that cannot allocate device memory and hold no context: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The float32 re-score of game_rescore computed straight from the
+ * patterns, async on `stream`; it allocates nothing (no hipMalloc, no
+ * workspace) and needs no game_init.
+ *   cfg:        a configuration as for game_init (validated as by game_query);
+ *               F32, BF16 or F16 (F64: GAME_E_UNSUPPORTED).  The basis, degree,
+ *               bias, shared and task fields define the model.
+ *   X_dev:      N x F float patterns, row-major (device); t_dev: N float targets.
+ *   genes_dev:  n x L float chromosomes (device), required.
+ *   n:          1 <= n <= 8 (GAME_E_INVALID beyond: the scratch below holds the
+ *               partial sums of at most 8 chromosomes), and n * L <= 16384.
+ *   mse_dev, miscls_dev: n doubles each (device) or NULL.
+ * Scratch: one fixed array of 131 328 bytes inside the library per GPU (1024
+ * workgroup partials of 16 doubles and an arrival counter), held until the
+ * process ends.  Every call on a GPU shares it, so calls that overlap on one
+ * GPU (several streams or host threads) race: the caller serialises them.
+ * The first call on a device also enqueues a one-thread kernel that clears
+ * the counter.  Results equal game_rescore's bit for bit on a context built
+ * from the same cfg, X and t.
+ */
+game_status game_rescore_noalloc(const game_config* cfg, const void* X_dev, const void* t_dev,
+                                 const float* genes_dev, int32_t n, double* mse_dev,
+                                 double* miscls_dev, void* stream);
+
+/*
  * Offspring form, per generation, blocking: the Spearman rank correlation of
  * the surrogate's scores with the exact log MSE on the audit sample
  * (rho_audit) and on the children evaluated exactly (rho_selected), and the

@@ -7,5 +7,5 @@ selection, crossover and mutation.  All of it runs in hand-written HIP
 kernels behind the C ABI in include/game.h; this package only marshals
 arguments and borrows device memory and streams from PyTorch.
 """
-from .game import Batch, Config, Game, build_basis, query, workspace_size  # noqa: F401
+from .game import Batch, Config, Game, build_basis, query, rescore_noalloc, workspace_size  # noqa: F401
 from . import _lib  # noqa: F401

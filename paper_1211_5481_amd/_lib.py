@@ -113,6 +113,8 @@ SIGNATURES = {
     "game_advance": (C.c_int, [_VP, C.c_int32]),
     "game_run": (C.c_int, [_VP, C.POINTER(GameResult)]),
     "game_rescore": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP]),
+    "game_rescore_noalloc": (C.c_int, [C.POINTER(GameConfig), _VP, _VP, _VP, C.c_int32, _VP, _VP,
+                                       _VP]),
     "game_surrogate_log": (C.c_int, [_VP, _VP, C.c_int32, C.POINTER(C.c_int32)]),
     "game_surrogate_buffer": (C.c_int, [_VP, _VP, _VP, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "game_mlp_params": (C.c_int, [_VP, _VP, C.c_int32]),

@@ -896,6 +896,32 @@ game_status game_rescore(game_ctx* c, const float* genes, int32_t n, double* mse
   return enqueue_rescore(c, genes, n, mse, miscls, false, c->stream);
 }
 
+game_status game_rescore_noalloc(const game_config* cfg, const void* X, const void* t,
+                                 const float* genes, int32_t n, double* mse, double* miscls,
+                                 void* stream) {
+  Plan p{};
+  char err[256] = "";
+  const game_status st = make_plan(cfg, &p, err, sizeof(err));
+  if (st != GAME_OK) return fail(st, "%s", err);
+  if (cfg->dtype == GAME_F64)
+    return fail(GAME_E_UNSUPPORTED, "game_rescore_noalloc scores in float32: F64 configurations are not accepted");
+  if (!X || !t || !genes) return fail(GAME_E_INVALID, "X, t and genes are required");
+  if (n < 1 || n > kMaxRescore)
+    return fail(GAME_E_INVALID, "n must be in [1, %d]: the fixed scratch holds the partial sums of at most %d "
+                "chromosomes", kMaxRescore, kMaxRescore);
+  if ((int64_t)n * p.L > 16384) return fail(GAME_E_INVALID, "n * L must be <= 16384");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  double* part = nullptr;
+  uint32_t* counter = nullptr;
+  hipError_t e = rescore_scratch(s, &part, &counter);
+  if (e != hipSuccess) return fail(GAME_E_DEVICE, "re-score scratch: %s", hipGetErrorString(e));
+  e = launch_rescore(static_cast<const float*>(X), static_cast<const float*>(t), p.N, cfg->n_features,
+                     cfg->degree, p.K, cfg->basis, p.M, p.L, cfg->bias, cfg->task, genes, n, nullptr,
+                     nullptr, nullptr, part, counter, mse, miscls, nullptr, nullptr, nullptr, s);
+  if (e != hipSuccess) return fail(GAME_E_DEVICE, "rescore: %s", hipGetErrorString(e));
+  return GAME_OK;
+}
+
 game_status game_surrogate_log(game_ctx* c, float* out, int32_t n_max, int32_t* n_out) {
   GAME_TRY(check_ctx(c));
   if (!out || !n_out || n_max < 0) return fail(GAME_E_INVALID, "log buffer and count are required");

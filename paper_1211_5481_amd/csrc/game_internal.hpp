@@ -215,6 +215,10 @@ hipError_t launch_pop_copy(float* pop0, float* pop1, const DevState* st, float* 
                            int dir, hipStream_t s);
 
 int rescore_grid();
+// The allocation-free re-score's scratch on the current device (block
+// partials and arrival counter; set up on the first call per device).
+size_t rescore_scratch_bytes();
+hipError_t rescore_scratch(hipStream_t s, double** part, uint32_t** counter);
 hipError_t launch_rescore(const float* X, const float* t, int64_t N, int F, int D, int K, int basis,
                           int M, int L, int bias, int task, const float* genes, int n,
                           const float* pop0, const float* pop1, const int* top, double* part,

@@ -18,6 +18,9 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <vector>
+
 #include "expand.hpp"
 #include "game_internal.hpp"
 #include "select.hpp"
@@ -210,9 +213,50 @@ __global__ __launch_bounds__(kThreads) void rescore_kernel(RescoreArgs a) {
   }
 }
 
+constexpr int kGrid = 1024;  // workgroups of every re-score launch
+
+// Scratch of the allocation-free entry point (game_rescore_noalloc): the
+// kGrid x 2 kMaxRescore block partials, then the arrival counter (a uint32 in
+// the first word of the last 256 bytes).  One copy per GPU, held until the
+// process ends; every call on a GPU shares it.  The partials are written in
+// full by each launch before they are read; the counter is zero when the code
+// object is loaded, is cleared once more by a small kernel at the first call
+// on each device, and every launch returns it to zero.
+constexpr size_t kScratchPartDoubles = (size_t)kGrid * 2 * kMaxRescore;
+static __device__ __align__(256) double scratch[kScratchPartDoubles + 32];
+
+__global__ void clear_counter_kernel(uint32_t* counter) { *counter = 0u; }
+
 }  // namespace
 
-int rescore_grid() { return 1024; }
+int rescore_grid() { return kGrid; }
+
+size_t rescore_scratch_bytes() { return sizeof(double) * (kScratchPartDoubles + 32); }
+
+hipError_t rescore_scratch(hipStream_t s, double** part, uint32_t** counter) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  static std::mutex mu;
+  static std::vector<double*> ptrs;  // per device: the array's device address
+  std::lock_guard<std::mutex> lock(mu);
+  if (dev < 0) return hipErrorInvalidDevice;
+  if ((size_t)dev >= ptrs.size()) ptrs.resize((size_t)dev + 1, nullptr);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    hipLaunchKernelGGL(clear_counter_kernel, dim3(1), dim3(1), 0, s,
+                       reinterpret_cast<uint32_t*>(static_cast<double*>(p) + kScratchPartDoubles));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ptrs[dev] = static_cast<double*>(p);
+  }
+  *part = ptrs[dev];
+  *counter = reinterpret_cast<uint32_t*>(ptrs[dev] + kScratchPartDoubles);
+  return hipSuccess;
+}
 
 hipError_t launch_rescore(const float* X, const float* t, int64_t N, int F, int D, int K, int basis,
                           int M, int L, int bias, int task, const float* genes, int n,

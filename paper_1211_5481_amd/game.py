@@ -139,6 +139,23 @@ def build_basis(cfg: Config, X, ld: Optional[int] = None, stream=None):
     return phi
 
 
+def rescore_noalloc(cfg: Config, X, t, genes, stream=None):
+    """Float32 (mse, miscls) of n <= 8 chromosomes (n x L) on device patterns
+    X (N x F) and targets t, with no context and no allocation inside the
+    library (game_rescore_noalloc; the outputs are allocated here)."""
+    torch = _torch()
+    d = query(cfg)
+    X, t, genes = X.contiguous(), t.contiguous(), genes.contiguous()
+    if genes.dtype != torch.float32 or genes.dim() != 2 or genes.shape[1] != d.L:
+        raise ValueError("genes must be a float32 n x L CUDA tensor")
+    n = genes.shape[0]
+    out = torch.empty((2, n), dtype=torch.float64, device=genes.device)
+    L.check(L.lib().game_rescore_noalloc(C.byref(cfg.to_c()), _ptr(X), _ptr(t), _ptr(genes), int(n),
+                                         _ptr(out[0]), _ptr(out[1]), _stream_handle(stream)),
+            "game_rescore_noalloc")
+    return out[0], out[1]
+
+
 class Game:
     """A GAME training context (game_init ... game_destroy)."""
 
