@@ -15,7 +15,12 @@ mixture (30/70, min-max scaled to [-1, 1]), trigonometric expansion of
 degree 6 (120 genes), population 1000, sigmoid output, FP32.
 
 Prints one JSON line.  Metric: chromosome x pattern fitness evaluations per
-second over the whole step.
+second over the whole step.  The default line also carries the metric's
+comparison at equal quality ("equal_mse"): on the 1M-pattern, 16-feature
+Legendre D=8 workload, the wall time of BF16 and FP16 runs (elites
+re-scored in FP32) to reach the final best MSE of a 100-generation FP32 run,
+and of the MLP and random 25 % prescreens (8192 offspring per generation) to
+reach that of a run evaluating every offspring exactly.
 """
 from __future__ import annotations
 
@@ -120,22 +125,44 @@ def cpu_baseline(meta, X, t, dtype, seconds: float, threads_limit=None):
         el = time.perf_counter() - t0
         if el >= seconds or gens >= 50:
             break
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    avail = len(os.sched_getaffinity(0))
+    threads = min(max([i.get("num_threads", 1) for i in threadpool_info()] + [1]), avail)
     return {"value": meta["P"] * meta["N"] * gens / el, "unit": "evals/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{gens} full generations (all {meta['N']} patterns x {meta['P']} "
                       f"chromosomes, then the GA step) of the float64 numpy oracle, Phi "
                       f"precomputed, {el:.1f} s; BLAS threads {threads}, elementwise work "
-                      f"single-threaded"}
+                      f"single-threaded",
+            "host_cores_available": avail, "cpu_model": cpu_model()}
 
 
-def time_to_mse(args):
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo, else lscpu)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return "unknown"
+
+
+def time_to_mse(args, wl=None):
     """Plain FP32 run for G generations -> its final best MSE; then BF16 and
     FP16 runs (top-2 re-scored in FP32 every generation) until their FP32
     best MSE reaches that value."""
     import torch
     from paper_1211_5481_amd import Config, Game
-    meta, X, t = workload(args.workload, "f32")
+    meta, X, t = workload(wl or args.workload, "f32")
     Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
     td = torch.tensor(t, dtype=torch.float32, device="cuda")
     base = dict(n_patterns=meta["N"], n_features=meta["F"], degree=meta["D"], basis=meta["basis"],
@@ -333,6 +360,9 @@ def main():
                          "c4: 64 batched runs of uneven size")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-equal-mse", action="store_true",
+                    help="skip the time-to-equal-MSE comparisons (precision and surrogate forms) "
+                         "that the default workload's line carries")
     ap.add_argument("--time-to-mse", action="store_true",
                     help="precision forms: generations and wall time of BF16/FP16 runs (elites "
                          "re-scored in FP32) to reach the final best MSE of a plain FP32 run")
@@ -448,14 +478,50 @@ def main():
         "basis_ms_once": basis_ms,
         "best_mse_after": st["best_mse"],
     }
+    g.close()
+    if not args.no_equal_mse and args.workload == "c2" and args.dtype == "f32":
+        out["equal_mse"] = equal_mse(args)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(meta, X, t, args.dtype, args.cpu_seconds)
         # the same oracle on one core (the paper's serial CPU comparison point)
         out["cpu_baseline_one_core"] = cpu_baseline(meta, X, t, args.dtype, args.cpu_seconds / 3,
                                                     threads_limit=1)
-    g.close()
     print(json.dumps(out), flush=True)
+
+
+def equal_mse(args):
+    """The metric's comparison at equal quality: (a) the 1M-pattern Legendre
+    workload in FP32 for G generations, then BF16 and FP16 (elites re-scored
+    in FP32) until their FP32 best MSE reaches the FP32 run's final one; (b)
+    the surrogate form on the same data (8192 offspring per generation): all
+    offspring evaluated exactly for G generations, then the MLP and the random
+    25 % prescreens until they reach that run's final best MSE (one GA seed).
+    Wall times of whole runs, generations, and speed-ups."""
+    print("[bench] equal MSE: precision forms, 1M patterns", file=sys.stderr, flush=True)
+    tt = time_to_mse(args, wl="c3")
+    prec = {"workload": tt["workload"], "target_mse": tt["f32"]["best_mse"],
+            "f32": {k: tt["f32"][k] for k in ("generations", "seconds", "evals_per_s")}}
+    for d in ("bf16", "f16"):
+        prec[d] = {k: tt[d][k] for k in ("generations", "seconds", "reached", "evals_per_s",
+                                         "speedup_vs_f32", "best_mse_fp32")}
+    print("[bench] equal MSE: surrogate form, 1M patterns, 8192 offspring", file=sys.stderr,
+          flush=True)
+    sc = surrogate_compare(args)
+    run = sc["runs"][0]
+    sur = {"workload": sc["workload"], "ga_seed": run["ga_seed"],
+           "target_mse": run["plain"]["best_mse"],
+           "plain": {k: run["plain"][k] for k in ("generations", "seconds", "evals_per_s")}}
+    for mode in ("mlp", "random"):
+        sur[mode] = {k: v for k, v in run[mode].items()
+                     if k in ("generations", "seconds", "reached", "speedup_vs_plain",
+                              "evals_per_s", "screened_per_s", "spearman_audit_mean",
+                              "spearman_audit_last10", "spearman_selected_mean")}
+    return {"precision": prec, "surrogate": sur,
+            "speedup_at_equal_mse": {"bf16_vs_f32": prec["bf16"]["speedup_vs_f32"],
+                                     "f16_vs_f32": prec["f16"]["speedup_vs_f32"],
+                                     "mlp_vs_plain": sur["mlp"]["speedup_vs_plain"],
+                                     "random_vs_plain": sur["random"]["speedup_vs_plain"]}}
 
 
 if __name__ == "__main__":

@@ -238,10 +238,14 @@ game_status game_eval_fitness(game_ctx* ctx, const float* genes_dev, int32_t P,
                               double* mse_dev, double* miscls_dev, double* fitness_dev);
 
 /*
- * One generation of the genetic operators on the current population, async:
+ * One generation of the genetic operators on the current population, async
+ * (the operators Sec. 3 lists, applied at the rates and elitism of the
+ * experiments of Sec. 5; genes stay in the [-1, 1] range of Sec. 3):
  * elitism (the E best, fitness descending, ties to the lower index, NaN worst,
- * copied unchanged), then P - E children from size-k tournaments, one-point
- * crossover and per-gene Gaussian mutation clamped to [-1, 1].
+ * copied unchanged), then P - E children from the configured selection
+ * (size-k tournaments, roulette or ranking), one-point crossover and per-gene
+ * Gaussian mutation clamped to [-1, 1] (IEEE maxNum/minNum: a NaN sum becomes
+ * -1), the last n_immigrants children replaced by random chromosomes (Sec. 4).
  *   fitness_dev: P doubles of the current population (device), or NULL to use
  *                the last game_eval_fitness(NULL) result (GAME_E_STATE if none).
  * Increments the generation counter that keys the random draws.
