@@ -260,9 +260,22 @@ game_status game_step(game_ctx* ctx, const double* fitness_dev);
 
 /*
  * n generations of (evaluate current population, rank, evolve), async,
- * replayed from a captured HIP graph; no stop test.
+ * replayed from captured HIP graphs (n / 8 launches of an 8-generation graph,
+ * then one graph of the n mod 8 remaining generations; graphs are captured on
+ * first use, see game_advance_prepare); no stop test.
  */
 game_status game_advance(game_ctx* ctx, int32_t n_generations);
+
+/*
+ * Capture, without running anything, the HIP graphs game_advance(ctx, n)
+ * replays (a graph of 8 generations when n >= 8 and one of the n mod 8
+ * remaining generations), so that a later game_advance(ctx, n) only launches
+ * them: a caller with a latency-critical loop pays the capture beforehand.
+ * Blocking (host-side capture; may wait for the context's stream when it
+ * replaces a remainder graph of another length).  Only the last remainder
+ * length is kept.
+ */
+game_status game_advance_prepare(game_ctx* ctx, int32_t n_generations);
 
 /*
  * Train until best MSE <= mse_threshold or max_generations generations have

@@ -111,6 +111,7 @@ SIGNATURES = {
     "game_eval_fitness": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP]),
     "game_step": (C.c_int, [_VP, _VP]),
     "game_advance": (C.c_int, [_VP, C.c_int32]),
+    "game_advance_prepare": (C.c_int, [_VP, C.c_int32]),
     "game_run": (C.c_int, [_VP, C.POINTER(GameResult)]),
     "game_rescore": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP]),
     "game_rescore_noalloc": (C.c_int, [C.POINTER(GameConfig), _VP, _VP, _VP, C.c_int32, _VP, _VP,

@@ -42,8 +42,9 @@ struct game_ctx {
   Plan plan;
   hipStream_t stream = nullptr;      // caller's stream
   hipStream_t cap = nullptr;         // private stream used only for graph capture
-  hipGraphExec_t exec1 = nullptr, execC = nullptr;
-  hipGraph_t graph1 = nullptr, graphC = nullptr;
+  hipGraphExec_t execR = nullptr, execC = nullptr;
+  hipGraph_t graphR = nullptr, graphC = nullptr;
+  int nR = 0;                        // generations in graphR (game_advance's remainder)
   unsigned char* ws = nullptr;
   void *phi, *tvec, *tile, *biasv;
   float *pop0, *pop1, *best;  // generation g lives in pop[g & 1]
@@ -820,17 +821,44 @@ game_status game_step(game_ctx* c, const double* fit) {
   return GAME_OK;
 }
 
+// The graphs game_advance(n) replays: chunks of kChunk generations and one
+// graph of the n mod kChunk remaining ones (kept until another remainder is
+// asked for).
+static game_status prepare_advance(game_ctx* c, int32_t n) {
+  if (n >= kChunk) GAME_TRY(build_graph(c, kChunk, &c->graphC, &c->execC));
+  const int rem = n % kChunk;
+  if (rem && c->nR != rem) {
+    if (c->execR) {
+      // the old remainder graph may still be running on the stream
+      GAME_TRY(dev(c, hipStreamSynchronize(c->stream), "synchronize"));
+      (void)hipGraphExecDestroy(c->execR);
+      c->execR = nullptr;
+    }
+    if (c->graphR) (void)hipGraphDestroy(c->graphR);
+    c->graphR = nullptr;
+    c->nR = 0;
+    GAME_TRY(build_graph(c, rem, &c->graphR, &c->execR));
+    c->nR = rem;
+  }
+  return GAME_OK;
+}
+
+game_status game_advance_prepare(game_ctx* c, int32_t n) {
+  GAME_TRY(check_ctx(c));
+  if (n < 0) return fail(GAME_E_INVALID, "n_generations must be >= 0");
+  return prepare_advance(c, n);
+}
+
 game_status game_advance(game_ctx* c, int32_t n) {
   GAME_TRY(check_ctx(c));
   if (n < 0) return fail(GAME_E_INVALID, "n_generations must be >= 0");
   if (n == 0) return GAME_OK;
   if (c->plan.offspring && !c->sur_warm) GAME_TRY(enqueue_offspring_warmup(c, c->stream));
-  if (n >= kChunk) GAME_TRY(build_graph(c, kChunk, &c->graphC, &c->execC));
-  if (n % kChunk) GAME_TRY(build_graph(c, 1, &c->graph1, &c->exec1));
+  GAME_TRY(prepare_advance(c, n));
   if (!c->plan.offspring) GAME_TRY(enqueue_pack_population(c, c->stream));
   for (int i = 0; i + kChunk <= n; i += kChunk)
     GAME_TRY(dev(c, hipGraphLaunch(c->execC, c->stream), "graph launch"));
-  for (int i = 0; i < n % kChunk; ++i) GAME_TRY(dev(c, hipGraphLaunch(c->exec1, c->stream), "graph launch"));
+  if (n % kChunk) GAME_TRY(dev(c, hipGraphLaunch(c->execR, c->stream), "graph launch"));
   c->have_eval = c->plan.offspring;
   return GAME_OK;
 }
@@ -1214,9 +1242,9 @@ game_status game_time_fitness(game_ctx* c, int32_t reps, float* ms) {
 
 void game_destroy(game_ctx* c) {
   if (!c) return;
-  if (c->exec1) (void)hipGraphExecDestroy(c->exec1);
+  if (c->execR) (void)hipGraphExecDestroy(c->execR);
   if (c->execC) (void)hipGraphExecDestroy(c->execC);
-  if (c->graph1) (void)hipGraphDestroy(c->graph1);
+  if (c->graphR) (void)hipGraphDestroy(c->graphR);
   if (c->graphC) (void)hipGraphDestroy(c->graphC);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;

@@ -123,6 +123,11 @@ __device__ __forceinline__ float sig_pos(float cz) {
 }
 __device__ __forceinline__ double sig_pos(double cz) { return 1.0 / (1.0 + exp2(cz)); }
 
+// loc + q^2 as one fused multiply-add: written out, so that every kernel
+// that shares the error arithmetic rounds it the same way (left to the
+// compiler, a sum of two squares may be fused around either product).
+__device__ __forceinline__ float sq_acc(float q, float loc) { return __builtin_fmaf(q, q, loc); }
+
 // Misclassification test by floating-point class: for label 0 a pattern is
 // missed when z >= 0 (+-0, positive denormal/normal/inf), for label 1 when
 // z < 0 or z is NaN; padding rows use an empty class mask.
@@ -688,7 +693,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
               q = tcur[i][r] - z;
             }
             if constexpr (!kFull) q = (nw0 + i * 16 + row_in_block(r) < N) ? q : Acc(0);
-            loc += q * q;
+            loc = sq_acc(q, loc);
           }
         sse[j] += (double)loc;
         miss[j] += ms;

@@ -215,6 +215,11 @@ class Game:
     def advance(self, n_generations: int):
         L.check(L.lib().game_advance(self._ctx, int(n_generations)), "game_advance")
 
+    def prepare(self, n_generations: int):
+        """Capture the graphs advance(n_generations) replays, running nothing."""
+        L.check(L.lib().game_advance_prepare(self._ctx, int(n_generations)),
+                "game_advance_prepare")
+
     def run(self) -> dict:
         genes = (C.c_float * self.L)()
         r = L.GameResult()

@@ -51,13 +51,17 @@ def test_graph_replay_equals_eager_steps_and_oracle():
     a, cfg, X, t = c1_game(dtype="f32", pop_size=64)
     b, _, _, _ = c1_game(dtype="f32", pop_size=64)
     pop0 = host(a.population)
-    a.advance(11)                          # one 8-generation graph + 3 single-generation graphs
-    for _ in range(11):
+    a.advance(11)                          # one 8-generation graph + a 3-generation graph
+    a.prepare(5)                           # replaces the remainder graph, runs nothing
+    assert a.state()["generation"] == 11
+    a.advance(5)                           # a 5-generation remainder graph
+    a.advance(3)                           # a 3-generation one again
+    for _ in range(19):
         b.eval_fitness()
         b.step()
     pa, pb = host(a.population), host(b.population)
     assert np.array_equal(pa.view(np.uint32), pb.view(np.uint32))
-    assert a.state()["generation"] == 11
+    assert a.state()["generation"] == 19
     # replay the first generation on the oracle from the device's own fitness vector
     c, _, _, _ = c1_game(dtype="f32", pop_size=64)
     _, _, fit = c.eval_fitness()

@@ -404,7 +404,7 @@ def test_advance_equals_steps_in_offspring_form():
     kw = dict(P=32, n_off=160, frac=0.5, steps=1, audit=8, batch=32, H=16, seed=99)
     a, _ = make("mlp", **kw)
     b, _ = make("mlp", **kw)
-    a.advance(11)          # one chunk of 8 and three single generations
+    a.advance(11)          # one chunk of 8 and a 3-generation graph
     for _ in range(11):
         b.step()
     assert np.array_equal(bits(host(a.population)), bits(host(b.population)))
