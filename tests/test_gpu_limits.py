@@ -8,11 +8,11 @@ import pytest
 
 from oracle import ga, model
 import synth
-from tests.gpu_util import announce, dev, host, require_gpu
+from tests.gpu_util import accumulation_bound, announce, dev, host, require_gpu
 
 pytestmark = pytest.mark.gpu
 
-RTOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-5}
+RTOL = {"f64": 1e-12, "f32": 1e-5}
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
@@ -36,7 +36,11 @@ def test_largest_chromosome(dtype):
         Phi = model.quantize(Phi, "bf16")
         Go = model.quantize(Go, "bf16")
     ref = model.evaluate(Xo, to, Go, "trig", D, "classification", Phi=Phi)
-    np.testing.assert_allclose(mse, ref["mse"], rtol=RTOL[dtype], atol=0)
+    if dtype == "bf16":
+        bound = accumulation_bound(Phi, Go, ref, to, "classification", Phi.shape[1])
+        assert np.all(np.abs(mse - ref["mse"]) <= bound)
+    else:
+        np.testing.assert_allclose(mse, ref["mse"], rtol=RTOL[dtype], atol=0)
     assert np.array_equal(fit, 1.0 - mse)
     # one GA step on the widest rows is bit-exact with the oracle's
     pop = host(g.population)
