@@ -401,8 +401,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
 // Persistent decomposition, used when the gene tile fits in LDS.  The grid
 // holds as many workgroups as can be resident; a work item (row range wr,
-// chromosome tile pt) stages its gene tile in LDS once (row stride padded so
-// the 16 rows a quarter-wave reads sit in distinct banks) and walks its
+// chromosome tile pt) stages its gene tile in LDS once (K-block-major, in
+// the order the MFMA operand fragments are read) and walks its
 // contiguous range of 32-pattern row units.  The four waves of an item take
 // the range's units round-robin, each computing 32 patterns x TP chromosomes
 // (2 x WN blocks of 16 x 16) per unit, so every Phi row is read by exactly
@@ -450,8 +450,13 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
   using Ld = typename Tr::Ld;
   constexpr int WM = 2, TU = 32, TP = 16 * WN;
   constexpr int kLdWords = (int)(sizeof(Ld) / 4);
-  constexpr int kBlkWords = Tr::kBlk * (int)sizeof(T) / 4;
-  // LDS: the gene tile (TP rows of ldsw words), then the per-wave column sums
+  static_assert(Tr::kBlk / Tr::kPerLane == 4, "a K-block is four lane groups of one Ld unit");
+  // LDS: the gene tile (TP x M_pad elements = TP ldsw words), then the
+  // per-wave column sums.  The tile is stored K-block-major in MFMA operand
+  // order: the fragment lane l of block column j reads for K-block kb sits at
+  // Ld unit (kb WN + j) 64 + l, so a wave's read of a fragment is 64
+  // consecutive Ld units (no bank conflicts) and every address is one
+  // lane-constant base plus a compile-time or per-K-block offset.
   double (*s_sse)[TP] = reinterpret_cast<double (*)[TP]>(lds + TP * ldsw);
   uint32_t (*s_miss)[TP] = reinterpret_cast<uint32_t (*)[TP]>(lds + TP * ldsw + 8 * TP);
 
@@ -471,7 +476,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
   Acc bias_j[WN];
 #pragma unroll
   for (int j = 0; j < WN; ++j) bias_j[j] = biasv ? biasv[p0 + j * 16 + lrow] : Acc(0);
-  const int bofs0 = lrow * ldsw + lgrp * kLdWords;  // + 16 j ldsw for block j
+  const int bofs0 = lane * kLdWords;  // + ((kb WN + j) 64) kLdWords
 
   auto row_in_block = [&](int r) { return Tr::kRowInterleave ? lgrp + 4 * r : 4 * lgrp + r; };
 
@@ -502,7 +507,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
   auto loadB = [&](Ld* b, int kb) {
 #pragma unroll
     for (int j = 0; j < WN; ++j)
-      b[j] = *reinterpret_cast<const Ld*>(&lds[bofs0 + j * 16 * ldsw + kb * kBlkWords]);
+      b[j] = *reinterpret_cast<const Ld*>(&lds[bofs0 + (kb * WN + j) * 64 * kLdWords]);
   };
 
   if (u_first < u_end) {
@@ -526,8 +531,11 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
     };
     auto st = [&](int v, const Ld& x) {
       if (v < total) {
+        // global unit c of gene row r: K-block c / 4, lane group c % 4;
+        // block column r / 16, lane row r % 16
         const int r = v / units, c = v - r * units;
-        *reinterpret_cast<Ld*>(&lds[r * ldsw + c * kLdWords]) = x;
+        const int slot = ((c >> 2) * WN + (r >> 4)) * 64 + (c & 3) * 16 + (r & 15);
+        *reinterpret_cast<Ld*>(&lds[slot * kLdWords]) = x;
       }
     };
     if constexpr (sizeof(Ld) == 8) {
@@ -833,15 +841,11 @@ hipError_t launch_tr(int task, const FitnessGeom& g, const Plan& p, const void* 
   return hipGetLastError();
 }
 
-// LDS row stride (4-byte words) for the staged gene tile: a multiple of the
-// per-lane load unit, congruent to it modulo 64 words, so the 16 rows read by
-// a quarter-wave fall in distinct banks.
+// LDS words per staged gene row: the tile is stored dense (K-block-major,
+// see lds_item), so a row is its M_pad elements.
 template <class Tr>
 int lds_stride_words(int M_pad) {
-  const int unit = (int)(sizeof(typename Tr::Ld) / 4);
-  const int row = M_pad * (int)sizeof(typename Tr::T) / 4;
-  int s = row + ((unit - row) % 64 + 64) % 64;
-  return s;
+  return M_pad * (int)sizeof(typename Tr::T) / 4;
 }
 
 // Dynamic LDS of one LDS-kernel workgroup: gene tile plus column sums.
