@@ -637,7 +637,7 @@ void game_config_default(game_config* c) {
   c->surrogate_batch = 2048;
   c->audit = 256;
   c->prescreen_frac = 0.25;
-  c->surrogate_lr = 3e-3;
+  c->surrogate_lr = 3e-4;
   c->surrogate_recent = 0.75;
 }
 
@@ -768,6 +768,7 @@ game_status game_init(const game_config* cfg, const void* X, const void* t, void
     if (r == GAME_OK) r = dev(c, hipMemsetAsync(c->loss, 0, 16, st), "surrogate state");
     if (r == GAME_OK && p.sur == GAME_SURROGATE_MLP) {
       r = dev(c, mlp_init(MlpDims{p.L, p.H, p.H}, c->prm, c->am, c->av, c->WT, cfg->seed, st), "mlp init");
+      if (r == GAME_OK) r = dev(c, mlp_scratch_init(MlpDims{p.L, p.H, p.H}, c->mscr, st), "mlp init");
       if (r == GAME_OK) r = dev(c, hipMemsetAsync(c->step, 0, 16, st), "mlp init");
     }
   }

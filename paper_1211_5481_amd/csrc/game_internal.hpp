@@ -268,6 +268,8 @@ MlpLayout mlp_layout(int L, int H1, int H2);
 // activation scratch (floats) for training steps of `batch` rows and forward
 // passes of up to `rows_max` rows
 int64_t mlp_scratch_floats(const MlpDims& d, int batch, int rows_max);
+// Zero the gradient products' arrival counters in the scratch (once per context).
+hipError_t mlp_scratch_init(const MlpDims& d, float* scratch, hipStream_t s);
 // W2T: transposed copy of W2 (H1 x H2), kept in step with the parameters
 hipError_t mlp_transpose(const MlpDims& d, const float* params, float* W2T, hipStream_t s);
 hipError_t mlp_init(const MlpDims& d, float* params, float* m, float* v, float* W2T, uint64_t seed,

@@ -62,9 +62,13 @@ constexpr int64_t round4(int64_t n) { return (n + 3) & ~int64_t(3); }
 // (ld B4): XT (L), G1T = gelu'(A1), Hd1T, D1T (H1), Hd2T, D2T (H2), dyres (dy
 // then squared residuals).  tv: standardised targets; ones: 1 for rows < B.
 struct Scratch {
+  uint32_t* gcnt;  // per parameter tile: arrival count of its split products (zero between launches)
+  float* gpart;    // per parameter tile and split: the 32 x 32 partial product
   float *Hd1, *ypart, *XT, *tv, *ones, *G1T, *Hd1T, *G2, *Hd2T, *dyres, *D2T, *D1T;
   int B4, ld1, ld2, nT2;
 };
+int grad_tiles(const MlpDims& d);
+constexpr int kSplit = 4;  // row ranges each parameter tile's product is split into
 
 // Lays the scratch out from `base` (null: sizes only); returns the floats
 // used.  A forward pass needs only Hd1 and ypart, which come first.
@@ -81,6 +85,11 @@ int64_t scratch_layout(const MlpDims& d, int B, bool train, float* base, Scratch
     return p;
   };
   const int64_t B4 = z.B4;
+  // the gradient products' counters and partials come first in every layout,
+  // so that no other scratch use overwrites the counters
+  const int64_t nt = grad_tiles(d);
+  z.gcnt = reinterpret_cast<uint32_t*>(take(nt));
+  z.gpart = take(nt * kSplit * kT * kT);
   z.Hd1 = take(B4 * z.ld1);
   z.ypart = take(B4 * z.nT2);
   if (train) {
@@ -98,6 +107,16 @@ int64_t scratch_layout(const MlpDims& d, int B, bool train, float* base, Scratch
   if (s) *s = z;
   return o;
 }
+
+__device__ __forceinline__ void st_agent(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ld_agent(const float* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until this thread's device-scope stores are acknowledged (they are
+// then visible to the workgroup that counts the arrival after them).
+__device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Four consecutive k of one operand row, zero past K or for a missing row.
 __device__ __forceinline__ v4f load4(const float* row, int k, int K, bool vec) {
@@ -467,9 +486,13 @@ __device__ bool find_job(const GradArgs& g, int wg, Job& job, int& tm, int& tn) 
   return false;
 }
 
-// The gradient products contract over all B rows: 16 waves per tile keep
-// more loads in flight than 4.
-constexpr int kGradWaves = 16;
+// The gradient products contract over all B rows.  Each parameter tile's
+// product is split into kSplit consecutive row ranges, one workgroup each
+// (4 waves interleaving 16-row groups), so that the products cover the whole
+// device; a workgroup stores its 32 x 32 partial at device scope, and the
+// last of a tile's workgroups to arrive adds the partials in range order and
+// applies Adam to the tile (or writes the gradient).
+constexpr int kGradWaves = 4;
 
 int grad_tiles(const MlpDims& d) {
   auto t = [](int M, int N) { return ((M + kT - 1) / kT) * ((N + kT - 1) / kT); };
@@ -480,37 +503,56 @@ __global__ __launch_bounds__(64 * kGradWaves) void grads_kernel(GradArgs g, cons
   if (run_halted(halt)) return;
   __shared__ v4f red[kGradWaves * 4 * 64];
   __shared__ int s_last;
-  const int B4 = g.s.B4, K = g.B;
+  const int B4 = g.s.B4;
   const int t = g.grads ? 0 : *g.step + 1;
+  const int tile = (int)blockIdx.x / kSplit, split = (int)blockIdx.x - tile * kSplit;
   Job job{};
   int tm = 0, tn = 0;
-  const bool have = find_job(g, blockIdx.x, job, tm, tn);
+  const bool have = find_job(g, tile, job, tm, tn);
+  // rows of this split: [k0, k1), ranges of a multiple of 16 rows
+  const int kc = ((g.B + kSplit - 1) / kSplit + 15) & ~15;
+  const int k0 = min(split * kc, g.B), k1 = min(g.B, k0 + kc);
   const int m0 = tm * kT, n0 = tn * kT;
   auto fa = [&](int m, int k) {
-    return load4(have && m0 + m < job.M ? job.A + (int64_t)(m0 + m) * B4 : nullptr, k, K, true);
+    return load4(have && m0 + m < job.M ? job.A + (int64_t)(m0 + m) * B4 + k0 : nullptr, k, k1 - k0, true);
   };
   auto fb = [&](int n, int k) {
-    return load4(have && n0 + n < job.N ? job.Bt + (int64_t)(n0 + n) * B4 : nullptr, k, K, true);
+    return load4(have && n0 + n < job.N ? job.Bt + (int64_t)(n0 + n) * B4 + k0 : nullptr, k, k1 - k0, true);
   };
-  tile_product<kGradWaves>(K, fa, fb, red);
+  tile_product<kGradWaves>(k1 - k0, fa, fb, red);
   const TileOut o = tile_sum<kGradWaves>(red);
-  const int n = n0 + o.n;
-  if (have && threadIdx.x < 256 && n < job.N) {
+  const int64_t tsz = kT * kT;
+  float* part = g.s.gpart + ((int64_t)tile * kSplit + split) * tsz;
+  if (have) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int m = m0 + o.m0 + q;
-      if (m >= job.M) continue;
-      const float val = o.v[q];
-      if (job.scalars && m == 1) {
-        if (g.loss) *g.loss = val / (float)g.B;
-        continue;
+    for (int q = 0; q < 4; ++q) st_agent(part + (o.m0 + q) * kT + o.n, o.v[q]);
+  }
+  stores_done();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = atomicAdd(&g.s.gcnt[tile], 1u) == (uint32_t)(kSplit - 1);
+  __syncthreads();
+  if (s_last) {
+    const int n = n0 + o.n;
+    if (have && n < job.N) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + o.m0 + q;
+        if (m >= job.M) continue;
+        const float* pt = g.s.gpart + (int64_t)tile * kSplit * tsz + (o.m0 + q) * kT + o.n;
+        float val = 0.0f;
+        for (int sp = 0; sp < kSplit; ++sp) val += ld_agent(pt + sp * tsz);
+        if (job.scalars && m == 1) {
+          if (g.loss) *g.loss = val / (float)g.B;
+          continue;
+        }
+        const int64_t p = job.p0 + (int64_t)m * job.ldp + n;
+        if (g.grads)
+          g.grads[p] = val;
+        else
+          adam_update(g.params, g.m, g.v, g.W2T, p, val, t, g.lr, g.L, g.H1, g.H2);
       }
-      const int64_t p = job.p0 + (int64_t)m * job.ldp + n;
-      if (g.grads)
-        g.grads[p] = val;
-      else
-        adam_update(g.params, g.m, g.v, g.W2T, p, val, t, g.lr, g.L, g.H1, g.H2);
     }
+    if (threadIdx.x == 0) g.s.gcnt[tile] = 0u;
   }
   if (g.grads) return;
   __syncthreads();
@@ -626,8 +668,14 @@ GradArgs grad_args(const MlpDims& d, const Args& a) {
 }
 
 hipError_t launch_grads(const MlpDims& d, const GradArgs& g, const DevState* halt, hipStream_t s) {
-  hipLaunchKernelGGL(grads_kernel, dim3((unsigned)grad_tiles(d)), dim3(64 * kGradWaves), 0, s, g, halt);
+  hipLaunchKernelGGL(grads_kernel, dim3((unsigned)(grad_tiles(d) * kSplit)), dim3(64 * kGradWaves), 0, s,
+                     g, halt);
   return hipGetLastError();
+}
+
+__global__ void clear_counts_kernel(uint32_t* c, int n) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) c[i] = 0u;
 }
 
 }  // namespace
@@ -653,6 +701,14 @@ hipError_t mlp_transpose(const MlpDims& d, const float* params, float* W2T, hipS
   const int64_t n = (int64_t)d.H2 * d.H1;
   hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params, W2T,
                      d.L, d.H1, d.H2);
+  return hipGetLastError();
+}
+
+hipError_t mlp_scratch_init(const MlpDims& d, float* scratch, hipStream_t s) {
+  Scratch z{};
+  scratch_layout(d, 4, true, scratch, &z);
+  const int n = grad_tiles(d);
+  hipLaunchKernelGGL(clear_counts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z.gcnt, n);
   return hipGetLastError();
 }
 

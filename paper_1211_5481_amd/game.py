@@ -43,7 +43,7 @@ class Config:
     surrogate_batch: int = 2048
     audit: int = 256
     prescreen_frac: float = 0.25
-    surrogate_lr: float = 3e-3
+    surrogate_lr: float = 3e-4
     surrogate_recent: float = 0.75
     p_crossover: float = 0.9
     p_mutation: float = 0.05
