@@ -279,7 +279,8 @@ def batched(args):
     classification), 100 generations each, advanced together; tile widths and
     row ranges picked by the library's tuner.  Value: aggregate chromosome x
     pattern evaluations per second over the whole run; per-run generation
-    latency percentiles."""
+    latency percentiles (over all runs' generations, and each run's median
+    against its generation's work)."""
     import numpy as np
     import torch
     import synth
@@ -312,9 +313,21 @@ def batched(args):
     run_s = time.perf_counter() - t0
     gens = [r["generations"] for r in results]
     evals = sum(float(sp["n"]) * sp["pop"] * g for sp, g in zip(specs, gens))
-    kernel_ms = b.time_fitness(reps=10)
+    run_flops = 0.0
+    work = []
+    for sp, g in zip(specs, gens):
+        B = 2 if sp["basis"] == "trig" else 1
+        w = 2.0 * sp["n"] * sp["f"] * B * sp["degree"] * sp["pop"]
+        work.append(w)
+        run_flops += w * g
+    eval_ms = b.time_fitness(reps=10)
     v = lat[lat >= 0.0]
-    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    # one scheduler launch runs every generation of every run: the whole run's
+    # contraction flop over its duration
+    achieved = run_flops / run_s / 1e12
+    p50 = np.array([np.median(row[row >= 0.0]) for row in lat])
+    order = np.argsort(work)
+    from scipy.stats import spearmanr
     out = {
         "metric": METRIC,
         "value": evals / run_s,
@@ -335,11 +348,17 @@ def batched(args):
                    "evals_per_generation": evals_per_gen},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK["f32"], "traffic": None,
-                     "kernel": "fitness_batch_kernel", "kernel_ms": kernel_ms,
-                     "flops_per_launch": flops},
+                     "kernel": "flow_kernel", "kernel_ms": run_s * 1e3,
+                     "flops_per_launch": run_flops},
+        "evaluation_only_ms": eval_ms,
+        "evaluation_only_tflops": flops / (eval_ms * 1e-3) / 1e12,
         "generation_latency_us": {"p50": float(np.percentile(v, 50)),
                                   "p99": float(np.percentile(v, 99)),
-                                  "max": float(v.max()), "samples": int(v.size)},
+                                  "max": float(v.max()), "samples": int(v.size),
+                                  "per_run_p50_smallest_run": float(p50[order[0]]),
+                                  "per_run_p50_median_run": float(p50[order[len(order) // 2]]),
+                                  "per_run_p50_largest_run": float(p50[order[-1]]),
+                                  "spearman_run_work_vs_p50": float(spearmanr(work, p50)[0])},
         "init_and_tune_s": init_s,
         "tiles": {"tile_p": tiles[0], "row_groups": tiles[1]},
     }

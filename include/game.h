@@ -431,16 +431,20 @@ void game_destroy(game_ctx* ctx);
 
 /*
  * Batched form: many independent GA runs (each one context with its own
- * configuration, patterns, population and stop rule) advanced together.
- * Every generation is one persistent fitness launch in which workgroups take
- * (run, chromosome tile, row range) items from a device queue, followed by
- * the wheel or rank order of each roulette / ranking run and one breed
- * launch over all runs; chunks of generations are replayed from a
- * captured HIP graph.  Requirements: 1..4096 runs, one dtype for all (F32,
- * BF16 or F16), the generational GA (no offspring form, no re-score), gene
- * counts whose tiles fit the LDS-staged kernel.  Each run computes exactly
- * what game_run would on a context created with the same configuration and
- * the tile_p / row_groups the batch uses (game_batch_tiles).
+ * configuration, patterns, population and stop rule) advanced together by
+ * one persistent scheduler launch per up to 128 generations.  Each run moves
+ * through its own phases (fitness items of chromosome tile x row range, the
+ * wheel or rank order for roulette / ranking selection, the breed) as soon
+ * as its previous phase ends, so runs progress independently: a small run's
+ * generation takes about its own work, not the largest run's.  Workgroups
+ * take open items from the runs in order of increasing generation cost.
+ * Requirements: 1..4096 runs, one dtype for all (F32, BF16 or F16), the
+ * generational GA (no offspring form, no re-score), gene counts whose tiles
+ * fit the LDS-staged kernel.  Each run computes exactly what game_run would
+ * on a context created with the same configuration and the tile_p /
+ * row_groups the batch uses (game_batch_tiles).  A workgroup that finds no
+ * open item for far longer than any phase takes (at least 2 s) ends the
+ * launch with GAME_E_DEVICE and poisons the batch.
  */
 typedef struct game_batch game_batch;
 
@@ -451,8 +455,8 @@ game_status game_batch_workspace_size(const game_config* cfgs, int32_t n_runs, s
  * Create the runs (as game_init: basis, targets, initial population) in one
  * workspace, then pick each run's tile width and row ranges: configurations
  * with tile_p and row_groups both set keep them when every run sets them;
- * otherwise the tuner times candidate assignments of the batched fitness
- * launch on the device and keeps the fastest.  Blocking.
+ * otherwise the tuner times candidate assignments with evaluation-only
+ * scheduler launches on the device and keeps the fastest.  Blocking.
  *   X_devs[i], t_devs[i]: run i's patterns and targets, as for game_init.
  */
 game_status game_batch_init(const game_config* cfgs, int32_t n_runs, const void* const* X_devs,
@@ -465,16 +469,18 @@ game_status game_batch_tiles(game_batch* batch, int32_t* tile_p_host, int32_t* r
 /* Run i's context, for inspection (population, state, fitness); owned by the batch. */
 game_status game_batch_context(game_batch* batch, int32_t i, game_ctx** out);
 
-/* Mean duration (ms) of one batched fitness launch over the current populations; blocking. */
+/* Mean duration (ms) of one scheduler launch that evaluates every run's current
+ * population once (fitness phase only, each run's ranking and best tracking
+ * included); blocking. */
 game_status game_batch_time_fitness(game_batch* batch, int32_t reps, float* ms);
 
 /*
  * Run every run until its own stop rule holds (as game_run), blocking.
  *   results: n_runs records (best_genes may be NULL or L_i host floats).
  *   latency_us: NULL, or n_runs x G doubles (G = largest max_generations):
- *     entry [i][g] = microseconds from the start of batched generation g's
- *     fitness launch to the end of run i's breed in it, -1 where run i did
- *     not breed in generation g.
+ *     entry [i][g] = microseconds from the opening of run i's g-th
+ *     generation of this call (its fitness phase) to the end of its breed,
+ *     -1 where run i did not breed a g-th generation.
  */
 game_status game_batch_run(game_batch* batch, game_result* results, double* latency_us);
 

@@ -1268,28 +1268,24 @@ const char* game_last_error(void) { return g_err; }
 }  // extern "C"
 
 // ====================================================== batched form
-// Many independent contexts advanced in lockstep: each generation is one
-// persistent fitness launch over a queue of (context, chromosome tile, row
-// range) items and one breed launch over every context's workgroups, both
-// replayed from a captured graph.  Each context keeps its own workspace,
-// state and stop rule; a stopped context's items and workgroups are skipped.
+// Many independent contexts advanced by one persistent scheduler launch
+// (flow_kernel): each run moves through its own fitness, wheel / ranking and
+// breed phases, so a run's generation takes about its own work.  Each
+// context keeps its own workspace, state and stop rule.
 struct game_batch {
   std::vector<game_ctx*> ctx;
   std::vector<size_t> ws_off;
   int n = 0, dtype = 0;
-  hipStream_t stream = nullptr, cap = nullptr;
-  unsigned char* tab = nullptr;  // device tables
-  BatchFitRun* dfit = nullptr;
-  BatchBreedRun* dbreed = nullptr;
-  DevState** dstates = nullptr;
-  BatchQueue* q = nullptr;
-  uint64_t *t_start = nullptr, *t_done = nullptr;
+  hipStream_t stream = nullptr;
+  FlowRun* druns = nullptr;  // device table, cheapest generation first
+  FlowCtl* ctl = nullptr;
+  FlowQueue* q = nullptr;
+  uint64_t *t_start = nullptr, *t_done = nullptr;  // per context: G slots each
   int G = 0;  // timestamp slots per context
-  int64_t n_items = 0;
-  int fit_grid = 0, breed_grid = 0;
-  size_t fit_lds = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  int grid = 0;
+  size_t lds = 0;
+  uint64_t idle_ticks = 0;
+  double gen_flop = 0.0;  // one generation of every run (2 N M P summed)
   bool poisoned = false;
   std::vector<int> tile_p, row_groups;  // per context, as tuned
   float tune_ms = 0.0f;
@@ -1297,11 +1293,16 @@ struct game_batch {
 
 namespace {
 
-constexpr int kBatchChunk = 8;
+// Generations each run may breed per scheduler launch: a launch of the
+// workload of 64 runs of up to 5e5 patterns lasts about 2.5 s at this size.
+constexpr int kFlowChunk = 128;
+// FP32 contraction rate (flop/s) the fair-share deadlines assume; only the
+// runs' relative shares depend on it.
+constexpr double kFlowRate = 80e12;
 
 struct BatchLayout {
   std::vector<size_t> ws_off;
-  size_t tab_off, fit_off, breed_off, states_off, q_off, ts_off, td_off, total;
+  size_t tab_off, runs_off, ctl_off, q_off, ts_off, td_off, total;
   int G;
 };
 
@@ -1332,11 +1333,10 @@ game_status batch_layout(const game_config* cfgs, int n, BatchLayout* L, int* dt
     off = align256(off + bytes);
     return o;
   };
-  L->fit_off = take(sizeof(BatchFitRun) * n);
-  L->breed_off = take(sizeof(BatchBreedRun) * n);
-  L->states_off = take(sizeof(DevState*) * n);
-  L->q_off = take(sizeof(BatchQueue));
-  L->ts_off = take(sizeof(uint64_t) * G);
+  L->runs_off = take(sizeof(FlowRun) * n);
+  L->ctl_off = take(sizeof(FlowCtl) * n);
+  L->q_off = take(sizeof(FlowQueue));
+  L->ts_off = take(sizeof(uint64_t) * (size_t)G * n);
   L->td_off = take(sizeof(uint64_t) * (size_t)G * n);
   L->total = off;
   return GAME_OK;
@@ -1348,21 +1348,24 @@ game_status bdev(game_batch* b, hipError_t e, const char* what) {
   return fail(GAME_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Device tables for the contexts' current tile widths and row ranges: items
-// of the contexts with the largest items first, so the queue ends on small
-// ones.
+// The scheduler's table for the contexts' current tile widths and row
+// ranges, with each run's fair-share generation span, its dynamic LDS (the widest gene tile, or a ranking's sort) and
+// the resident grid.
 game_status batch_tables(game_batch* b) {
-  std::vector<BatchFitRun> fit(b->n);
-  std::vector<BatchBreedRun> br(b->n);
-  std::vector<DevState*> states(b->n);
+  std::vector<FlowRun> runs(b->n);
   std::vector<double> cost(b->n);
   std::vector<int> order(b->n);
-  b->fit_lds = 0;
+  b->lds = 0;
+  b->gen_flop = 0.0;
+  int dev_id = 0, rate_khz = 0;
+  GAME_TRY(bdev(b, hipGetDevice(&dev_id), "device"));
+  GAME_TRY(bdev(b, hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev_id), "clock rate"));
+  const double ticks_per_s = 1e3 * (rate_khz > 0 ? rate_khz : 100000);
   for (int i = 0; i < b->n; ++i) {
     game_ctx* c = b->ctx[i];
     const Plan& p = c->plan;
     const FitnessGeom g = fitness_geometry(p, c->cfg.task, c->cfg.dtype, p.P);
-    BatchFitRun& f = fit[i];
+    FlowRun& f = runs[i];
     f.phi = c->phi;
     f.tile = c->tile;
     f.biasv = c->cfg.bias ? c->biasv : nullptr;
@@ -1371,6 +1374,12 @@ game_status batch_tables(game_batch* b) {
     f.pmiss = c->pmiss;
     f.st = c->state;
     f.tail = make_tail(c, p.P, true, nullptr, nullptr, nullptr);
+    f.breed = evolve_args(c, c->fit);
+    f.breed.counter = nullptr;
+    f.wheel = c->wheel;
+    f.t_start = b->t_start + (size_t)i * b->G;
+    f.t_done = b->t_done + (size_t)i * b->G;
+    f.t_cap = b->G;
     f.N = p.N;
     f.M_pad = p.M_pad;
     f.ldsw = fitness_lds_stride(c->cfg.dtype, p.M_pad);
@@ -1380,46 +1389,52 @@ game_status batch_tables(game_batch* b) {
     f.task = c->cfg.task;
     f.tile_p = p.tile_p;
     f.ub = g.ub;
-    cost[i] = (double)((p.n_rt + g.n_rg - 1) / g.n_rg) * p.tile_p * p.M_pad;
+    f.n_fit = g.n_pt * (int)g.n_rg;
+    f.n_breed = breed_blocks(f.breed);
+    f.sel = c->cfg.selection;
+    f.rank_pow2 = 1;
+    while (f.rank_pow2 < p.P) f.rank_pow2 <<= 1;
+    cost[i] = (double)p.N * p.M_pad * p.P;
+    b->gen_flop += 2.0 * (double)p.N * p.M * p.P;
+    // fair share: the generation (its contraction at kFlowRate, plus about
+    // 20 us of tail and breed) with 1/n of the device
+    f.span = (uint64_t)(b->n * (2.0 * cost[i] / kFlowRate + 20e-6) * ticks_per_s);
     order[i] = i;
-    b->fit_lds = std::max(b->fit_lds, fitness_lds_bytes(c->cfg.dtype, p.M_pad, p.tile_p));
-    states[i] = c->state;
+    b->lds = std::max(b->lds, fitness_lds_bytes(c->cfg.dtype, p.M_pad, p.tile_p));
+    if (f.sel == GAME_SEL_RANKING) b->lds = std::max(b->lds, (size_t)f.rank_pow2 * 12);
   }
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-  std::vector<BatchFitRun> sorted(b->n);
-  int64_t item = 0;
-  for (int k = 0; k < b->n; ++k) {
-    sorted[k] = fit[order[k]];
-    sorted[k].item0 = item;
-    item += (int64_t)sorted[k].n_pt * sorted[k].n_ranges;
-  }
-  b->n_items = item;
-  int block = 0;
-  for (int i = 0; i < b->n; ++i) {
-    br[i].a = evolve_args(b->ctx[i], b->ctx[i]->fit);
-    br[i].st = b->ctx[i]->state;
-    br[i].t_done = b->t_done + (size_t)i * b->G;
-    br[i].block0 = block;
-    br[i].n_blocks = breed_blocks(br[i].a);
-    br[i].gen0 = 0;
-    block += br[i].n_blocks;
-  }
-  b->breed_grid = block;
-  const int slots = fitness_batch_slots(b->dtype, b->fit_lds);
-  if (slots <= 0) return fail(GAME_E_DEVICE, "batched fitness kernel cannot be resident");
-  b->fit_grid = (int)std::min<int64_t>(slots, std::max<int64_t>(b->n_items, 1));
-  GAME_TRY(bdev(b, hipMemcpyAsync(b->dfit, sorted.data(), sizeof(BatchFitRun) * b->n, hipMemcpyHostToDevice, b->stream), "batch tables"));
-  GAME_TRY(bdev(b, hipMemcpyAsync(b->dbreed, br.data(), sizeof(BatchBreedRun) * b->n, hipMemcpyHostToDevice, b->stream), "batch tables"));
-  GAME_TRY(bdev(b, hipMemcpyAsync(b->dstates, states.data(), sizeof(DevState*) * b->n, hipMemcpyHostToDevice, b->stream), "batch tables"));
+  // the table lists the cheapest generation first: of runs with equal
+  // deadlines the cheaper one is served first
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] < cost[y]; });
+  std::vector<FlowRun> sorted(b->n);
+  for (int k = 0; k < b->n; ++k) sorted[k] = runs[order[k]];
+  const int slots = flow_slots(b->dtype, b->lds);
+  if (slots <= 0) return fail(GAME_E_DEVICE, "batched scheduler cannot be resident");
+  b->grid = slots;
+  // a workgroup that finds no open item for this long gives up (a phase of
+  // one run never takes nearly this long: 20x one generation of every run
+  // at 50 TFLOP/s, at least 2 s)
+  const double idle_s = std::max(2.0, 20.0 * b->gen_flop / 50e12);
+  b->idle_ticks = (uint64_t)(idle_s * ticks_per_s);
+  GAME_TRY(bdev(b, hipMemcpyAsync(b->druns, sorted.data(), sizeof(FlowRun) * b->n, hipMemcpyHostToDevice, b->stream), "batch tables"));
   GAME_TRY(bdev(b, hipStreamSynchronize(b->stream), "synchronize"));
   return GAME_OK;
 }
 
-game_status batch_fitness(game_batch* b, hipStream_t s, bool stamps) {
-  return bdev(b,
-              launch_fitness_batch(b->dtype, b->dfit, b->n, b->n_items, b->fit_grid, b->fit_lds, b->q,
-                                   stamps ? b->t_start : nullptr, b->G, s),
-              "batched fitness");
+// One scheduler launch (arm, scheduler, status) and its queue afterwards.
+game_status batch_launch(game_batch* b, int chunk, int first, int eval_only, FlowQueue* hq) {
+  GAME_TRY(bdev(b,
+                launch_flow(b->dtype, b->druns, b->n, b->ctl, b->q, b->grid, b->lds, chunk, first,
+                            eval_only, b->idle_ticks, b->stream),
+                "batched scheduler"));
+  if (!hq) return GAME_OK;
+  GAME_TRY(bdev(b, hipMemcpyAsync(hq, b->q, sizeof(FlowQueue), hipMemcpyDeviceToHost, b->stream), "status copy"));
+  GAME_TRY(bdev(b, hipStreamSynchronize(b->stream), "synchronize"));
+  if (hq->error) {
+    b->poisoned = true;
+    return fail(GAME_E_DEVICE, "batched scheduler: a workgroup found no open item for too long");
+  }
+  return GAME_OK;
 }
 
 // Apply per-context tile widths and row ranges (each must fit), rebuild tables.
@@ -1435,28 +1450,38 @@ game_status batch_apply(game_batch* b, const std::vector<int>& tp, const std::ve
   return batch_tables(b);
 }
 
-// Mean duration (ms) of one batched fitness launch over the current populations.
+// Mean duration (ms) of one scheduler launch that evaluates every run's
+// current population once (the fitness phase only).
 game_status batch_time(game_batch* b, int reps, float* ms) {
+  for (game_ctx* c : b->ctx)
+    if (!c->tile_fresh) GAME_TRY(enqueue_pack_population(c, b->stream));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   GAME_TRY(bdev(b, hipEventCreate(&e0), "event"));
   game_status st = bdev(b, hipEventCreate(&e1), "event");
-  if (st == GAME_OK) st = batch_fitness(b, b->stream, false);  // warm
+  if (st == GAME_OK) st = batch_launch(b, 0, 0, 1, nullptr);  // warm
   if (st == GAME_OK) st = bdev(b, hipEventRecord(e0, b->stream), "event");
-  for (int r = 0; r < reps && st == GAME_OK; ++r) st = batch_fitness(b, b->stream, false);
+  for (int r = 0; r < reps && st == GAME_OK; ++r) st = batch_launch(b, 0, 0, 1, nullptr);
   if (st == GAME_OK) st = bdev(b, hipEventRecord(e1, b->stream), "event");
   if (st == GAME_OK) st = bdev(b, hipEventSynchronize(e1), "event");
   float t = 0.0f;
   if (st == GAME_OK) st = bdev(b, hipEventElapsedTime(&t, e0, e1), "event");
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
+  FlowQueue hq{};
+  if (st == GAME_OK) st = bdev(b, hipMemcpy(&hq, b->q, sizeof(hq), hipMemcpyDeviceToHost), "status copy");
+  if (st == GAME_OK && hq.error) {
+    b->poisoned = true;
+    st = fail(GAME_E_DEVICE, "batched scheduler: a workgroup found no open item for too long");
+  }
   if (st == GAME_OK) *ms = t / (float)reps;
+  for (game_ctx* c : b->ctx) c->evaluated = true;
   return st;
 }
 
 // The tuner: every context takes the widest tile that fits the LDS budget of
 // the candidate, and as many row ranges as give items of about W row-tile x
 // chromosome x gene units; the (budget, W) pair with the fastest batched
-// fitness launch wins.  Contexts whose configuration fixes tile_p and
+// evaluation wins.  Contexts whose configuration fixes tile_p and
 // row_groups keep them.
 game_status batch_tune(game_batch* b) {
   const size_t budgets[] = {98304, 49152};
@@ -1504,39 +1529,6 @@ game_status batch_tune(game_batch* b) {
   return batch_apply(b, best_tp, best_rg);
 }
 
-game_status batch_graph(game_batch* b) {
-  if (b->exec) return GAME_OK;
-  if (!b->cap) GAME_TRY(bdev(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "stream create"));
-  GAME_TRY(bdev(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture"));
-  game_status st = GAME_OK;
-  for (int i = 0; i < kBatchChunk && st == GAME_OK; ++i) {
-    st = batch_fitness(b, b->cap, true);
-    // roulette / ranking runs build their wheel or rank order first
-    for (int r = 0; r < b->n && st == GAME_OK; ++r)
-      if (b->ctx[r]->cfg.selection != GAME_SEL_TOURNAMENT)
-        st = enqueue_select_prep(b->ctx[r], b->ctx[r]->fit, b->cap);
-    if (st == GAME_OK)
-      st = bdev(b, launch_breed_batch(b->dtype, b->dbreed, b->n, b->breed_grid, b->q, b->G, b->cap), "batched breed");
-  }
-  if (st == GAME_OK) st = bdev(b, launch_batch_status(b->dstates, b->dbreed, b->n, b->q, 0, b->cap), "status");
-  hipGraph_t g = nullptr;
-  const hipError_t e = hipStreamEndCapture(b->cap, &g);
-  if (st != GAME_OK) {
-    if (g) (void)hipGraphDestroy(g);
-    return st;
-  }
-  GAME_TRY(bdev(b, e, "end capture"));
-  hipGraphExec_t x = nullptr;
-  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-  if (ei != hipSuccess) {
-    (void)hipGraphDestroy(g);
-    return bdev(b, ei, "graph instantiate");
-  }
-  b->graph = g;
-  b->exec = x;
-  return GAME_OK;
-}
-
 game_status check_batch(game_batch* b) {
   if (!b) return fail(GAME_E_INVALID, "batch is NULL");
   if (b->poisoned) return fail(GAME_E_STATE, "batch poisoned by an earlier device error");
@@ -1560,9 +1552,6 @@ game_status game_batch_workspace_size(const game_config* cfgs, int32_t n_runs, s
 
 void game_batch_destroy(game_batch* b) {
   if (!b) return;
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  if (b->cap) (void)hipStreamDestroy(b->cap);
   for (game_ctx* c : b->ctx) game_destroy(c);
   delete b;
 }
@@ -1599,14 +1588,12 @@ game_status game_batch_init(const game_config* cfgs, int32_t n_runs, const void*
     }
     b->ctx.push_back(c);
   }
-  b->tab = base + L.tab_off;
-  b->dfit = reinterpret_cast<BatchFitRun*>(base + L.fit_off);
-  b->dbreed = reinterpret_cast<BatchBreedRun*>(base + L.breed_off);
-  b->dstates = reinterpret_cast<DevState**>(base + L.states_off);
-  b->q = reinterpret_cast<BatchQueue*>(base + L.q_off);
+  b->druns = reinterpret_cast<FlowRun*>(base + L.runs_off);
+  b->ctl = reinterpret_cast<FlowCtl*>(base + L.ctl_off);
+  b->q = reinterpret_cast<FlowQueue*>(base + L.q_off);
   b->t_start = reinterpret_cast<uint64_t*>(base + L.ts_off);
   b->t_done = reinterpret_cast<uint64_t*>(base + L.td_off);
-  game_status s = bdev(b, hipMemsetAsync(b->q, 0, sizeof(BatchQueue), b->stream), "batch init");
+  game_status s = bdev(b, hipMemsetAsync(b->q, 0, sizeof(FlowQueue), b->stream), "batch init");
   if (s == GAME_OK) {
     bool fixed = true;
     for (int i = 0; i < n_runs; ++i) fixed = fixed && cfgs[i].tile_p > 0 && cfgs[i].row_groups > 0;
@@ -1654,7 +1641,6 @@ game_status game_batch_time_fitness(game_batch* b, int32_t reps, float* ms) {
 game_status game_batch_run(game_batch* b, game_result* results, double* latency_us) {
   GAME_TRY(check_batch(b));
   if (!results) return fail(GAME_E_INVALID, "results is NULL");
-  GAME_TRY(batch_graph(b));
   std::vector<game_state> s0(b->n);
   for (int i = 0; i < b->n; ++i) {
     game_ctx* c = b->ctx[i];
@@ -1662,24 +1648,23 @@ game_status game_batch_run(game_batch* b, game_result* results, double* latency_
     GAME_TRY(game_get_state(c, &s0[i], nullptr));
     GAME_TRY(dev(c, launch_run_arm(c->state, c->cfg.max_generations, c->cfg.mse_threshold, b->stream), "arm"));
   }
-  GAME_TRY(bdev(b, launch_batch_status(b->dstates, b->dbreed, b->n, b->q, 1, b->stream), "arm"));
-  BatchQueue hq{};
-  for (int launched = 0; launched < b->G + kBatchChunk; launched += kBatchChunk) {
-    GAME_TRY(bdev(b, hipGraphLaunch(b->exec, b->stream), "graph launch"));
-    GAME_TRY(bdev(b, hipMemcpyAsync(&hq, b->q, sizeof(hq), hipMemcpyDeviceToHost, b->stream), "status copy"));
-    GAME_TRY(bdev(b, hipStreamSynchronize(b->stream), "synchronize"));
-    if (hq.active == 0) break;
+  // each launch breeds up to kFlowChunk generations of every run; the last
+  // one finds every run stopped
+  FlowQueue hq{};
+  const int launches = b->G / kFlowChunk + 2;
+  for (int k = 0;; ++k) {
+    if (k == launches) return fail(GAME_E_STATE, "batch did not reach its stop conditions");
+    GAME_TRY(batch_launch(b, kFlowChunk, k == 0, 0, &hq));
+    if (hq.running == 0) break;
   }
-  if (hq.active != 0) return fail(GAME_E_STATE, "batch did not reach its stop conditions");
   std::vector<uint64_t> ts, td;
+  int dev_id = 0, rate_khz = 0;
   if (latency_us) {
-    ts.resize(b->G);
+    ts.resize((size_t)b->G * b->n);
     td.resize((size_t)b->G * b->n);
     GAME_TRY(bdev(b, hipMemcpyAsync(ts.data(), b->t_start, ts.size() * 8, hipMemcpyDeviceToHost, b->stream), "stamps"));
     GAME_TRY(bdev(b, hipMemcpyAsync(td.data(), b->t_done, td.size() * 8, hipMemcpyDeviceToHost, b->stream), "stamps"));
-  }
-  int dev_id = 0, rate_khz = 0;
-  if (latency_us) {
+    GAME_TRY(bdev(b, hipStreamSynchronize(b->stream), "synchronize"));
     GAME_TRY(bdev(b, hipGetDevice(&dev_id), "device"));
     GAME_TRY(bdev(b, hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev_id), "clock rate"));
   }
@@ -1697,11 +1682,11 @@ game_status game_batch_run(game_batch* b, game_result* results, double* latency_
     c->tile_fresh = true;
     c->evaluated = true;
     if (latency_us) {
-      // generation g of context i: from the start of the batched fitness
-      // launch to the end of its breed (bred generations only)
+      // generation g of run i: from the opening of its fitness phase to the
+      // end of its breed (bred generations only)
       for (int g = 0; g < b->G; ++g) {
         double v = -1.0;
-        const uint64_t a = ts[g], e = td[(size_t)i * b->G + g];
+        const uint64_t a = ts[(size_t)i * b->G + g], e = td[(size_t)i * b->G + g];
         if (g + 1 < results[i].generations && e > a && rate_khz > 0) v = (double)(e - a) * 1e3 / rate_khz;
         latency_us[(size_t)i * b->G + g] = v;
       }

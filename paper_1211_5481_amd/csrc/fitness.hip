@@ -37,6 +37,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "breed.hpp"
 #include "game_internal.hpp"
 #include "select.hpp"
 
@@ -154,7 +155,9 @@ __device__ __forceinline__ TailLds& tail_lds() {
   return s;
 }
 
-template <int TP>
+// kFlow: the batched scheduler runs every phase of a run inside one launch,
+// so the counters, the ranking and the state are also written at device scope.
+template <int TP, bool kFlow = false>
 __device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, int part_ld,
                              const double* psse, const uint32_t* pmiss) {
   constexpr int S = 256 / TP;
@@ -229,7 +232,7 @@ __device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, i
   agent_stores_done();
   __syncthreads();
   if (threadIdx.x == 0) {
-    t.counters[pt] = 0u;
+    stc<kFlow>(&t.counters[pt], 0u);
     s_flag = t.n_top > 0 && atomicAdd(&t.counters[t.n_pt_cap], 1u) == (uint32_t)(n_pt - 1);
   }
   __syncthreads();
@@ -237,10 +240,10 @@ __device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, i
   block_topk<256, true>(t.fit, t.P, t.n_top, t.top);
   __syncthreads();
   if (t.track) {
-    const float* pop = (t.st->generation & 1) ? t.pop1 : t.pop0;
-    track_best(t.st, t.top, t.mse, t.miscls, pop, t.L, t.best);
+    const float* pop = (ldc<kFlow>(&t.st->generation) & 1) ? t.pop1 : t.pop0;
+    track_best<kFlow>(t.st, t.top, t.mse, t.miscls, pop, t.L, t.best);
   }
-  if (threadIdx.x == 0) t.counters[t.n_pt_cap] = 0u;
+  if (threadIdx.x == 0) stc<kFlow>(&t.counters[t.n_pt_cap], 0u);
 }
 
 template <class Tr, int WM, int WN, bool kCls>
@@ -435,7 +438,25 @@ __device__ __forceinline__ int item_rot(int64_t lt, int64_t n_items, int cpx, in
   return ub == 1 ? 2 * (int)(((lt % per) / cpx) & 1) : 0;
 }
 
-template <class Tr, bool kCls, int WN, int kDepth>
+// A gene-tile load unit: plain, or at device scope (kAgent: the tile was
+// written by the breed phase of the same launch).
+template <bool kAgent, class Ld>
+__device__ __forceinline__ Ld ld_unit(const Ld* p) {
+  if constexpr (!kAgent) {
+    return *p;
+  } else if constexpr (sizeof(Ld) == 8) {
+    return __builtin_bit_cast(Ld, ld_agent(reinterpret_cast<const uint64_t*>(p)));
+  } else {
+    static_assert(sizeof(Ld) == 16, "gene-tile units are 8 or 16 bytes");
+    const uint64_t* q = reinterpret_cast<const uint64_t*>(p);
+    struct Pair {
+      uint64_t lo, hi;
+    };
+    return __builtin_bit_cast(Ld, Pair{ld_agent(q), ld_agent(q + 1)});
+  }
+}
+
+template <class Tr, bool kCls, int WN, int kDepth, bool kFlow = false>
 __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
                                          const typename Tr::T* __restrict__ tile,
                                          const typename Tr::Acc* __restrict__ biasv,
@@ -475,7 +496,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
   const int p0 = pt * TP;
   Acc bias_j[WN];
 #pragma unroll
-  for (int j = 0; j < WN; ++j) bias_j[j] = biasv ? biasv[p0 + j * 16 + lrow] : Acc(0);
+  for (int j = 0; j < WN; ++j) bias_j[j] = biasv ? ldc<kFlow>(biasv + p0 + j * 16 + lrow) : Acc(0);
   const int bofs0 = lane * kLdWords;  // + ((kb WN + j) 64) kLdWords
 
   auto row_in_block = [&](int r) { return Tr::kRowInterleave ? lgrp + 4 * r : 4 * lgrp + r; };
@@ -526,7 +547,7 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
     const Ld* src = reinterpret_cast<const Ld*>(tile + (int64_t)pt * TP * M_pad);
     auto ld = [&](int v) {
       Ld x{};
-      if (v < total) x = src[v];
+      if (v < total) x = ld_unit<kFlow>(src + v);
       return x;
     };
     auto st = [&](int v, const Ld& x) {
@@ -757,68 +778,239 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   fitness_tail<16 * WN>(tail, pt, n_pt, n_ranges, part_ld, part_sse, part_miss);
 }
 
-// Batched form: one persistent launch evaluates the populations of many
-// contexts.  Workgroups take (context, chromosome tile, row range) items from
-// a device queue in order; an item is the single-context kernel's work item
-// and tail, so each context's sums are those its own kernel would produce
-// with the same tile width and row ranges.  The last workgroup to leave
-// resets the queue for the next launch.
-template <class Tr>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fitness_batch_kernel(
-    const BatchFitRun* __restrict__ runs, int n_runs, int64_t n_items, int cpx, BatchQueue* q,
-    uint64_t* t_start, int t_cap) {
+// Batched form: one persistent launch advances many independent runs, each
+// at its own pace.  A run moves through three phases per generation:
+// fitness (its chromosome tile x row range items, each with the tail above,
+// so the last item ranks the population, tracks the best and applies the
+// stop rule), the roulette wheel or full ranking (one item, wheel selections
+// only) and the breed (its breed workgroups).  Per run, a 64-bit word holds
+// the phase epoch and the count of items claimed in it; a workgroup claims
+// an item by an atomic add on the word and takes the epoch the add returns,
+// so a claim is always for the phase it names.  Items of a phase never wait
+// for anything: the workgroup that finishes a phase's last item opens the
+// run's next phase (or parks the run: stopped, evaluation only, or its
+// generations for this launch bred).  A workgroup takes an item of the run
+// with the earliest deadline among those with open items; a generation's
+// deadline is the time it opened plus the time the run's generation would
+// take with 1/n of the device (earliest-deadline-first on fair-share
+// deadlines: runs share the device in proportion to their work, so a run's
+// generation takes about its own work times the runs in flight, and no run
+// starves).  Every value
+// one phase hands to the next (population, gene tile, fitness, ranking,
+// wheel, state, counters) is written and read at device scope, since the
+// phases of a run land on workgroups of different XCDs.  An item is the
+// single-context kernels' work, so a run's results equal its results alone
+// with the same tile width and row ranges.  Exit: every run parked, or no
+// open item for idle_ticks of the wall clock (error flag; bounds a lost
+// hand-off).
+constexpr uint32_t kParked = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t flow_count(const FlowRun& r, uint32_t e) {
+  if (e == kParked) return 0u;
+  const uint32_t ph = e % 3u;
+  return ph == 0u ? (uint32_t)r.n_fit : ph == 1u ? 1u : (uint32_t)r.n_breed;
+}
+
+// Run r finished epoch e: open its next phase or park it (thread 0 of the
+// workgroup that finished the epoch's last item).
+__device__ void flow_advance(const FlowRun& r, FlowCtl* c, FlowQueue* q, uint32_t e, int eval_only) {
+  const uint32_t ph = e % 3u;
+  uint32_t next;
+  if (ph == 0u) {
+    const bool halted = ld_agent(&r.st->run_active) != 0 && ld_agent(&r.st->stopped) != 0;
+    next = (eval_only || halted) ? kParked : e + (r.sel != GAME_SEL_TOURNAMENT ? 1u : 2u);
+  } else if (ph == 1u) {
+    next = e + 1u;
+  } else {
+    const int32_t g = ld_agent(&c->gen) + 1, rel = ld_agent(&c->rel), left = ld_agent(&c->left) - 1;
+    st_agent(&r.st->generation, g);
+    st_agent(&c->gen, g);
+    st_agent(&c->rel, rel + 1);
+    st_agent(&c->left, left);
+    const uint64_t now = wall_clock64();
+    if (rel < r.t_cap) st_agent(r.t_done + rel, now);
+    if (left > 0) {
+      next = e + 1u;
+      st_agent(&c->deadline, now + r.span);
+      if (rel + 1 < r.t_cap) st_agent(r.t_start + rel + 1, now);
+    } else {
+      next = kParked;  // this launch's generations are bred; the next launch resumes
+    }
+  }
+  st_agent(&c->done, 0u);
+  agent_stores_done();
+  __hip_atomic_exchange(&c->word, (uint64_t)next << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (next == kParked) atomicSub(&q->active, 1u);
+}
+
+template <class Tr, class O>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void flow_kernel(
+    const FlowRun* __restrict__ runs, int n_runs, FlowCtl* ctl, FlowQueue* q, int eval_only, int cpx,
+    uint64_t idle_ticks) {
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
   extern __shared__ __align__(16) uint32_t lds[];
-  __shared__ int64_t s_item;
+  __shared__ int s_state, s_run, s_gen;  // s_state: 0 item claimed, 1 none open, 2 leave
+  __shared__ uint32_t s_epoch, s_idx;
+  __shared__ int s_last;
+  uint64_t idle_since = 0;
   for (;;) {
     __syncthreads();  // the previous item's LDS is no longer read
-    if (threadIdx.x == 0) {
-      s_item = (int64_t)atomicAdd(&q->next, 1u);
-      if (s_item == 0 && t_start) {
-        const int g = q->gen - q->base;
-        if (g >= 0 && g < t_cap) t_start[g] = wall_clock64();
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      // the open run with the earliest deadline (ties to the lower index)
+      uint64_t best_dl = ~0ull;
+      int found = -1;
+      for (int base = 0; base < n_runs; base += 64) {
+        const int r = base + lane;
+        uint64_t dl = ~0ull;
+        int idx = -1;
+        if (r < n_runs) {
+          const uint64_t w = ld_agent(&ctl[r].word);
+          if ((uint32_t)w < flow_count(runs[r], (uint32_t)(w >> 32))) {
+            dl = ld_agent(&ctl[r].deadline);
+            idx = r;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const uint64_t odl = __shfl_xor(dl, off);
+          const int oidx = __shfl_xor(idx, off);
+          if (oidx >= 0 && (idx < 0 || odl < dl || (odl == dl && oidx < idx))) {
+            dl = odl;
+            idx = oidx;
+          }
+        }
+        if (idx >= 0 && (found < 0 || dl < best_dl)) {
+          best_dl = dl;
+          found = idx;
+        }
+      }
+      if (lane == 0) {
+        int state = 1;
+        if (found >= 0) {
+          const uint64_t old = __hip_atomic_fetch_add(&ctl[found].word, 1ull, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+          const uint32_t e = (uint32_t)(old >> 32), i = (uint32_t)old;
+          if (i < flow_count(runs[found], e)) {
+            state = 0;
+            s_run = found;
+            s_epoch = e;
+            s_idx = i;
+            s_gen = ld_agent(&ctl[found].gen);
+          }
+        } else if (ld_agent(&q->active) == 0u || ld_agent(&q->error) != 0u) {
+          state = 2;
+        }
+        // the idle clock is thread 0's alone, so the whole workgroup leaves together
+        if (state == 1) {
+          const uint64_t now = wall_clock64();
+          if (idle_since == 0) {
+            idle_since = now;
+          } else if (now - idle_since > idle_ticks) {
+            atomicOr(&q->error, 1u);
+            state = 2;
+          }
+        } else {
+          idle_since = 0;
+        }
+        s_state = state;
       }
     }
     __syncthreads();
-    const int64_t item = s_item;
-    if (item >= n_items) break;
-    int lo = 0, hi = n_runs - 1;  // last run whose first item is <= item
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (runs[mid].item0 <= item) lo = mid;
-      else hi = mid - 1;
+    const int state = s_state;
+    if (state == 2) break;
+    if (state == 1) {
+      __builtin_amdgcn_s_sleep(8);
+      continue;
     }
-    const BatchFitRun& r = runs[lo];
-    if (run_halted(r.st)) continue;
-    const int64_t local = item - r.item0;
-    const int pt = (int)(local % r.n_pt);
-    const int wr = (int)(local / r.n_pt);
-    const T* phi = static_cast<const T*>(r.phi);
-    const T* tile = static_cast<const T*>(r.tile);
-    const Acc* biasv = static_cast<const Acc*>(r.biasv);
-    const Acc* tvec = static_cast<const Acc*>(r.tvec);
-#define GAME_BATCH_ITEM(CLS, WN)                                                                 \
-  do {                                                                                           \
-    lds_item<Tr, CLS, WN, 1>(phi, tile, biasv, tvec, r.N, r.M_pad, r.ldsw, r.n_ranges, pt, wr,   \
-                             r.ub, item_rot(local, (int64_t)r.n_pt * r.n_ranges, cpx, r.ub), \
-                             r.part_ld, r.psse, r.pmiss, lds);                                   \
-    fitness_tail<16 * WN>(r.tail, pt, r.n_pt, r.n_ranges, r.part_ld, r.psse, r.pmiss);           \
+    const FlowRun& r = runs[s_run];
+    const uint32_t e = s_epoch, item = s_idx;
+    const uint32_t ph = e % 3u;
+    if (ph == 0u) {
+      const int pt = (int)(item % (uint32_t)r.n_pt);
+      const int wr = (int)(item / (uint32_t)r.n_pt);
+      const T* phi = static_cast<const T*>(r.phi);
+      const T* tile = static_cast<const T*>(r.tile);
+      const Acc* biasv = static_cast<const Acc*>(r.biasv);
+      const Acc* tvec = static_cast<const Acc*>(r.tvec);
+#define GAME_FLOW_ITEM(CLS, WN)                                                                   \
+  do {                                                                                            \
+    lds_item<Tr, CLS, WN, 1, true>(phi, tile, biasv, tvec, r.N, r.M_pad, r.ldsw, r.n_ranges, pt,  \
+                                   wr, r.ub, item_rot(item, r.n_fit, cpx, r.ub), r.part_ld,       \
+                                   r.psse, r.pmiss, lds);                                         \
+    fitness_tail<16 * WN, true>(r.tail, pt, r.n_pt, r.n_ranges, r.part_ld, r.psse, r.pmiss);      \
   } while (0)
-    if (r.task == GAME_CLASSIFICATION) {
-      if (r.tile_p == 128) GAME_BATCH_ITEM(true, 8);
-      else if (r.tile_p == 64) GAME_BATCH_ITEM(true, 4);
-      else GAME_BATCH_ITEM(true, 2);
+      if (r.task == GAME_CLASSIFICATION) {
+        if (r.tile_p == 128) GAME_FLOW_ITEM(true, 8);
+        else if (r.tile_p == 64) GAME_FLOW_ITEM(true, 4);
+        else GAME_FLOW_ITEM(true, 2);
+      } else {
+        if (r.tile_p == 128) GAME_FLOW_ITEM(false, 8);
+        else if (r.tile_p == 64) GAME_FLOW_ITEM(false, 4);
+        else GAME_FLOW_ITEM(false, 2);
+      }
+#undef GAME_FLOW_ITEM
+    } else if (ph == 1u) {
+      if (r.sel == GAME_SEL_ROULETTE)
+        wheel_block<256, true>(r.tail.fit, r.tail.P, r.wheel);
+      else
+        rank_block<256, true>(r.tail.fit, r.tail.P, r.rank_pow2, reinterpret_cast<int*>(r.wheel),
+                              reinterpret_cast<unsigned char*>(lds));
     } else {
-      if (r.tile_p == 128) GAME_BATCH_ITEM(false, 8);
-      else if (r.tile_p == 64) GAME_BATCH_ITEM(false, 4);
-      else GAME_BATCH_ITEM(false, 2);
+      breed_work<O, float, true>(r.breed, (int)item, (uint32_t)s_gen);
     }
-#undef GAME_BATCH_ITEM
+    // every store of the item is acknowledged before its completion counts
+    agent_stores_done();
+    __syncthreads();
+    if (threadIdx.x == 0)
+      s_last = atomicAdd(&ctl[s_run].done, 1u) + 1u == flow_count(r, e);
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) flow_advance(r, &ctl[s_run], q, e, eval_only);
   }
-  if (threadIdx.x == 0 && atomicAdd(&q->done, 1u) == gridDim.x - 1) {
-    q->next = 0u;
-    q->done = 0u;
+}
+
+// Before a launch: open the fitness phase of every run that has not stopped
+// (park the others), note the generation and the start time, count the runs
+// with work.  first: the start of a batch run (timestamp slots restart).
+__global__ void flow_arm_kernel(const FlowRun* __restrict__ runs, int n_runs, FlowCtl* ctl, FlowQueue* q,
+                                int chunk, int first, int eval_only) {
+  __shared__ uint32_t s_active[256];
+  uint32_t act = 0;
+  const uint64_t now = wall_clock64();
+  for (int i = threadIdx.x; i < n_runs; i += 256) {
+    const FlowRun& r = runs[i];
+    const bool halted = run_halted(r.st);
+    FlowCtl& c = ctl[i];
+    c.word = halted ? (uint64_t)kParked << 32 : 0ull;
+    c.deadline = now + r.span;
+    c.done = 0u;
+    c.gen = r.st->generation;
+    c.left = chunk;
+    if (first) c.rel = 0;
+    if (!halted && !eval_only && c.rel < r.t_cap) r.t_start[c.rel] = now;
+    act += halted ? 0u : 1u;
+  }
+  s_active[threadIdx.x] = act;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int i = 0; i < 256; ++i) tot += s_active[i];
+    q->active = tot;
+    q->error = 0u;
+  }
+}
+
+// After a launch: how many runs have not stopped.
+__global__ void flow_status_kernel(const FlowRun* __restrict__ runs, int n_runs, FlowQueue* q) {
+  __shared__ uint32_t s_run[256];
+  uint32_t n = 0;
+  for (int i = threadIdx.x; i < n_runs; i += 256) n += run_halted(runs[i].st) ? 0u : 1u;
+  s_run[threadIdx.x] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int i = 0; i < 256; ++i) tot += s_run[i];
+    q->running = tot;
   }
 }
 
@@ -987,53 +1179,62 @@ int fitness_lds_fits(int dtype, int M_pad, int tp) {
 }
 
 namespace {
-template <class Tr>
-hipError_t batch_prepare() {
+template <class Tr, class O>
+hipError_t flow_prepare() {
   static bool done = false;
   if (done) return hipSuccess;
-  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fitness_batch_kernel<Tr>),
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(flow_kernel<Tr, O>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
   if (e == hipSuccess) done = true;
   return e;
 }
 
-template <class Tr>
-int batch_slots(size_t lds) {
-  if (batch_prepare<Tr>() != hipSuccess) return 0;
+template <class Tr, class O>
+int flow_slots_tr(size_t lds) {
+  if (flow_prepare<Tr, O>() != hipSuccess) return 0;
   int blocks = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &blocks, reinterpret_cast<const void*>(fitness_batch_kernel<Tr>), 256, lds) != hipSuccess)
+          &blocks, reinterpret_cast<const void*>(flow_kernel<Tr, O>), 256, lds) != hipSuccess)
     return 0;
   return blocks * device_cus();
 }
 
-template <class Tr>
-hipError_t batch_launch(const BatchFitRun* runs, int n_runs, int64_t n_items, int grid, size_t lds,
-                        BatchQueue* q, uint64_t* t_start, int t_cap, hipStream_t s) {
-  const hipError_t e = batch_prepare<Tr>();
+template <class Tr, class O>
+hipError_t flow_launch(const FlowRun* runs, int n_runs, FlowCtl* ctl, FlowQueue* q, int grid, size_t lds,
+                       int chunk, int first, int eval_only, uint64_t idle_ticks, hipStream_t s) {
+  const hipError_t e = flow_prepare<Tr, O>();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fitness_batch_kernel<Tr>, dim3((unsigned)grid), dim3(256), lds, s, runs, n_runs,
-                     n_items, cus_per_xcd(), q, t_start, t_cap);
+  hipLaunchKernelGGL(flow_arm_kernel, dim3(1), dim3(256), 0, s, runs, n_runs, ctl, q, chunk, first,
+                     eval_only);
+  hipLaunchKernelGGL((flow_kernel<Tr, O>), dim3((unsigned)grid), dim3(256), lds, s, runs, n_runs, ctl, q,
+                     eval_only, cus_per_xcd(), idle_ticks);
+  hipLaunchKernelGGL(flow_status_kernel, dim3(1), dim3(256), 0, s, runs, n_runs, q);
   return hipGetLastError();
 }
 }  // namespace
 
-int fitness_batch_slots(int dtype, size_t lds) {
+int flow_slots(int dtype, size_t lds) {
+  if (lds > kLdsMax) return 0;
   switch (dtype) {
-    case GAME_F32: return batch_slots<F32Tr>(lds);
-    case GAME_BF16: return batch_slots<BF16Tr>(lds);
-    case GAME_F16: return batch_slots<F16Tr>(lds);
+    case GAME_F32: return flow_slots_tr<F32Tr, float>(lds);
+    case GAME_BF16: return flow_slots_tr<BF16Tr, uint16_t>(lds);
+    case GAME_F16: return flow_slots_tr<F16Tr, _Float16>(lds);
   }
   return 0;
 }
 
-hipError_t launch_fitness_batch(int dtype, const BatchFitRun* runs, int n_runs, int64_t n_items,
-                                int grid, size_t lds, BatchQueue* q, uint64_t* t_start, int t_cap,
-                                hipStream_t s) {
+hipError_t launch_flow(int dtype, const FlowRun* runs, int n_runs, FlowCtl* ctl, FlowQueue* q,
+                       int grid, size_t lds, int chunk, int first, int eval_only, uint64_t idle_ticks,
+                       hipStream_t s) {
   switch (dtype) {
-    case GAME_F32: return batch_launch<F32Tr>(runs, n_runs, n_items, grid, lds, q, t_start, t_cap, s);
-    case GAME_BF16: return batch_launch<BF16Tr>(runs, n_runs, n_items, grid, lds, q, t_start, t_cap, s);
-    case GAME_F16: return batch_launch<F16Tr>(runs, n_runs, n_items, grid, lds, q, t_start, t_cap, s);
+    case GAME_F32:
+      return flow_launch<F32Tr, float>(runs, n_runs, ctl, q, grid, lds, chunk, first, eval_only, idle_ticks, s);
+    case GAME_BF16:
+      return flow_launch<BF16Tr, uint16_t>(runs, n_runs, ctl, q, grid, lds, chunk, first, eval_only,
+                                           idle_ticks, s);
+    case GAME_F16:
+      return flow_launch<F16Tr, _Float16>(runs, n_runs, ctl, q, grid, lds, chunk, first, eval_only,
+                                          idle_ticks, s);
   }
   return hipErrorInvalidValue;
 }

@@ -305,42 +305,51 @@ hipError_t launch_predict(bool f64, const PredictArgs& a, hipStream_t s);
 hipError_t launch_metrics(bool f64, const PredictArgs& a, double* result, hipStream_t s);
 
 // ------------------------------------------------------ batched form
-// One context's share of a batched fitness launch (device table entry).
-struct BatchFitRun {
+// One run's entry in the batched scheduler's table (written by the host
+// before a launch, read-only during it).  Phases per generation: fitness
+// (n_fit items), the wheel or ranking (wheel selections), the breed
+// (n_breed items).
+struct FlowRun {
   const void* phi;
   const void* tile;
   const void* biasv;  // null without the bias gene
   const void* tvec;
   double* psse;
   uint32_t* pmiss;
-  const DevState* st;
-  FitTail tail;
-  int64_t N;
-  int64_t item0;      // queue position of this context's first item
-  int M_pad, ldsw, n_pt, n_ranges, part_ld, task, tile_p, ub;
-};
-// One context's share of a batched breed launch.
-struct BatchBreedRun {
-  BreedArgs a;
   DevState* st;
-  uint64_t* t_done;   // per generation: when this context's breed finished
-  int block0, n_blocks;
-  int gen0, pad;      // the context's generation when the batch run started
+  FitTail tail;
+  BreedArgs breed;    // counter and out null: the scheduler advances the generation
+  uint64_t* wheel;    // roulette wheel, or the ranking as int
+  uint64_t* t_start;  // per generation of a batch run: its fitness phase opened
+  uint64_t* t_done;   //   and its breed finished (wall clock)
+  uint64_t span;      // wall-clock ticks a generation of the run would take with
+                      // 1/n of the device (its fair share: deadline = opening + span)
+  int64_t N;
+  int M_pad, ldsw, n_pt, n_ranges, part_ld, task, tile_p, ub;
+  int n_fit, n_breed, sel, rank_pow2, t_cap, pad;
 };
-struct BatchQueue {   // device side of a batch
-  uint32_t next, done;  // fitness item queue, workgroups finished (zero between launches)
-  uint32_t bred, pad;   // breed workgroups finished (zero between launches)
-  int32_t gen, base;    // batched generations launched; value at the start of the run
-  int32_t active, pad2; // contexts not yet stopped (written after each chunk)
+struct FlowCtl {      // per run; read and written only at device scope
+  uint64_t word;      // phase epoch << 32 | items claimed in it
+  uint64_t deadline;  // of the run's current generation (wall clock)
+  uint32_t done;      // items finished in the epoch
+  int32_t gen;        // the run's generation
+  int32_t rel;        // generations bred since the batch run began
+  int32_t left;       // generations this launch may still breed
 };
-int fitness_batch_slots(int dtype, size_t lds);
-hipError_t launch_fitness_batch(int dtype, const BatchFitRun* runs, int n_runs, int64_t n_items,
-                                int grid, size_t lds, BatchQueue* q, uint64_t* t_start, int t_cap,
-                                hipStream_t s);
-hipError_t launch_breed_batch(int dtype, const BatchBreedRun* runs, int n_runs, int n_blocks,
-                              BatchQueue* q, int t_cap, hipStream_t s);
-hipError_t launch_batch_status(DevState* const* states, BatchBreedRun* runs, int n_runs,
-                               BatchQueue* q, int arm, hipStream_t s);
+struct FlowQueue {
+  uint32_t active;    // runs with work left in the launch
+  uint32_t error;     // a workgroup found no open item for too long
+  uint32_t running;   // runs not stopped after the launch
+  uint32_t pad;
+};
+// Workgroups of the scheduler that are resident at once with `lds` bytes of
+// dynamic LDS (0: cannot run).
+int flow_slots(int dtype, size_t lds);
+// arm (first: a batch run begins) -> scheduler -> status; chunk: generations
+// each run may breed in this launch; eval_only: the fitness phase only.
+hipError_t launch_flow(int dtype, const FlowRun* runs, int n_runs, FlowCtl* ctl, FlowQueue* q,
+                       int grid, size_t lds, int chunk, int first, int eval_only, uint64_t idle_ticks,
+                       hipStream_t s);
 // a context's workgroups in a breed launch
 int breed_blocks(const BreedArgs& a);
 

@@ -76,6 +76,45 @@ __device__ __forceinline__ void st_agent(double* p, double v) {
 __device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ int32_t ld_agent(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ld_agent(const float* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint16_t* p, uint16_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(_Float16* p, _Float16 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Loads and stores whose flavour a kernel picks at compile time: kAgent for
+// data that other workgroups of the same launch write or read (the batched
+// scheduler hands a run's population, gene tile, ranking and state from one
+// phase to the next inside one launch), plain otherwise.
+template <bool kAgent, class T>
+__device__ __forceinline__ T ldc(const T* p) {
+  if constexpr (kAgent) return ld_agent(p);
+  else return *p;
+}
+template <bool kAgent, class T>
+__device__ __forceinline__ void stc(T* p, T v) {
+  if constexpr (kAgent) st_agent(p, v);
+  else *p = v;
+}
 
 // Order this thread's earlier st_agent stores before an arrival count that
 // follows a barrier.  Every value one workgroup of a launch hands to another
@@ -89,7 +128,8 @@ __device__ __forceinline__ void agent_stores_done() { asm volatile("s_waitcnt vm
 
 // Top n_top indices of fit[0..P) by repeated arg-max, computed by one
 // workgroup of kThreads threads (all of which must call this).  kAgent: fit
-// was written earlier in the same launch by other workgroups.  Up to
+// was written earlier in the same launch by other workgroups, and top is
+// stored for them too.  Up to
 // kCache values per thread are read once into registers (all loads in
 // flight together), so the n_top passes cost no further memory round trips;
 // larger P re-reads fit on every pass.
@@ -117,7 +157,7 @@ __device__ void block_topk(const double* __restrict__ fit, int P, int n_top, int
         if (better(o, b)) b = o;
       }
       chosen[e] = b.idx;
-      top[e] = b.idx;
+      stc<kAgent>(top + e, b.idx);
     }
     __syncthreads();
   };
@@ -160,36 +200,42 @@ __device__ void block_topk(const double* __restrict__ fit, int P, int n_top, int
 // run is active, decide whether the run stops after this generation.  `top`
 // holds the generation's ranking (written by this workgroup); mse and miscls
 // were written by other workgroups of the same launch.  Every thread of the
-// workgroup calls this.
+// workgroup calls this.  kAgent: the state, the population and the best
+// genes are also handed between workgroups of one launch (batched
+// scheduler), so they are read and written at device scope.
+template <bool kAgent = false>
 __device__ inline void track_best(DevState* st, const int* __restrict__ top,
                                   const double* __restrict__ mse, const double* __restrict__ miscls,
                                   const float* __restrict__ pop, int L, float* __restrict__ best) {
-  __shared__ int s_improve;
+  __shared__ int s_improve, s_b;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int b = top[0];
-    s_improve = (!st->have_best || ld_agent(mse + b) < st->best_mse) ? 1 : 0;
+    const int b = ldc<kAgent>(top);
+    s_b = b;
+    s_improve = (!ldc<kAgent>(&st->have_best) || ld_agent(mse + b) < ldc<kAgent>(&st->best_mse)) ? 1 : 0;
   }
   __syncthreads();
-  const int b = top[0];
+  const int b = s_b;
   if (s_improve)
-    for (int l = threadIdx.x; l < L; l += blockDim.x) best[l] = pop[(int64_t)b * L + l];
+    for (int l = threadIdx.x; l < L; l += blockDim.x) stc<kAgent>(best + l, ldc<kAgent>(pop + (int64_t)b * L + l));
   if (threadIdx.x == 0) {
     const double m = ld_agent(mse + b);
-    st->best_index = b;
+    stc<kAgent>(&st->best_index, b);
+    double best_mse = ldc<kAgent>(&st->best_mse);
     if (s_improve) {
-      st->have_best = 1;
-      st->best_mse = m;
-      st->best_fitness = 1.0 - m;
-      st->best_miscls = ld_agent(miscls + b);
+      best_mse = m;
+      stc<kAgent>(&st->have_best, 1);
+      stc<kAgent>(&st->best_mse, m);
+      stc<kAgent>(&st->best_fitness, 1.0 - m);
+      stc<kAgent>(&st->best_miscls, ld_agent(miscls + b));
     }
-    if (st->run_active) {
-      if (st->best_mse <= st->mse_threshold) {
-        st->stopped = 1;
-        st->stop_reason = GAME_STOP_THRESHOLD;
-      } else if (st->generation + 1 >= st->end_generation) {
-        st->stopped = 1;
-        st->stop_reason = GAME_STOP_MAX_GEN;
+    if (ldc<kAgent>(&st->run_active)) {
+      if (best_mse <= ldc<kAgent>(&st->mse_threshold)) {
+        stc<kAgent>(&st->stopped, 1);
+        stc<kAgent>(&st->stop_reason, (int32_t)GAME_STOP_THRESHOLD);
+      } else if (ldc<kAgent>(&st->generation) + 1 >= ldc<kAgent>(&st->end_generation)) {
+        stc<kAgent>(&st->stopped, 1);
+        stc<kAgent>(&st->stop_reason, (int32_t)GAME_STOP_MAX_GEN);
       }
     }
   }

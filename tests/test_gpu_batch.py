@@ -223,3 +223,41 @@ def test_batch_with_wheel_selection_equals_runs_alone():
     results = b.run()
     compare_with_alone(b, runs, results)
     b.close()
+
+
+def test_batch_runs_progress_at_their_own_pace():
+    """A small run next to a large one: each run's generations take about its
+    own work (the small run does not wait for the large one's generation),
+    and both still equal the same runs alone."""
+    from paper_1211_5481_amd import Batch
+    specs = [("classification", 200_000, 12, 6, 1024, 12, 0.0, 41),
+             ("regression", 2000, 5, 4, 64, 12, 0.0, 42)]
+    runs = make_runs(specs)
+    announce("batched large + small run: per-run generation latency")
+    b = Batch(runs)
+    results, lat = b.run(latency=True)
+    compare_with_alone(b, runs, results)
+    big = np.median(lat[0, :11])
+    small = np.median(lat[1, :11])
+    print(f"median generation latency: large {big:.1f} us, small {small:.1f} us")
+    assert small > 0.0 and big > 0.0
+    assert small < 0.5 * big, (small, big)
+    b.close()
+
+
+def test_batch_longer_than_one_launch_equals_alone():
+    """More generations than one scheduler launch breeds (128): the runs
+    resume in the next launch exactly where they stopped."""
+    from paper_1211_5481_amd import Batch
+    specs = [("regression", 1500, 4, 4, 40, 300, 0.0, 51),
+             ("classification", 3000, 6, 4, 96, 170, 0.0, 52),
+             ("regression", 800, 3, 6, 32, 129, 0.0, 53)]
+    runs = make_runs(specs, extra=[dict(selection="ranking"), {}, dict(selection="roulette")])
+    announce("batched runs over three scheduler launches vs alone")
+    b = Batch(runs)
+    results, lat = b.run(latency=True)
+    compare_with_alone(b, runs, results)
+    for i, s in enumerate(specs):
+        assert results[i]["generations"] == s[5]
+        assert np.all(lat[i, :s[5] - 1] > 0.0)
+    b.close()
