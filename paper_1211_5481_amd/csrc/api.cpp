@@ -1421,6 +1421,31 @@ game_status batch_tables(game_batch* b) {
   return GAME_OK;
 }
 
+// A workgroup of the scheduler found no open item for too long: poison the
+// batch and name the first run that had not parked, with its phase state.
+game_status batch_stall(game_batch* b) {
+  b->poisoned = true;
+  std::vector<FlowCtl> c(b->n);
+  std::vector<FlowRun> r(b->n);
+  char what[512] = "";
+  if (hipMemcpy(c.data(), b->ctl, sizeof(FlowCtl) * b->n, hipMemcpyDeviceToHost) == hipSuccess &&
+      hipMemcpy(r.data(), b->druns, sizeof(FlowRun) * b->n, hipMemcpyDeviceToHost) == hipSuccess) {
+    for (int i = 0; i < b->n; ++i) {
+      const uint32_t e = (uint32_t)(c[i].word >> 32);
+      if (e == 0xFFFFFFFFu) continue;
+      int n = snprintf(what, sizeof(what),
+                       "; table run %d: epoch %u (phase %u), word claims %u, done %u, items %d/1/%d "
+                       "(fitness/wheel/breed), ranges %d, gen %d, slices",
+                       i, e, e % 3u, (uint32_t)c[i].word, c[i].done, r[i].n_fit, r[i].n_breed, r[i].n_ranges,
+                       c[i].gen);
+      for (int x = 0; x < kXcds && n > 0 && n < (int)sizeof(what); ++x)
+        n += snprintf(what + n, sizeof(what) - n, " %u:%u", (uint32_t)(c[i].xw[x] >> 32), (uint32_t)c[i].xw[x]);
+      break;
+    }
+  }
+  return fail(GAME_E_DEVICE, "batched scheduler: a workgroup found no open item for too long%s", what);
+}
+
 // One scheduler launch (arm, scheduler, status) and its queue afterwards.
 game_status batch_launch(game_batch* b, int chunk, int first, int eval_only, FlowQueue* hq) {
   GAME_TRY(bdev(b,
@@ -1430,10 +1455,7 @@ game_status batch_launch(game_batch* b, int chunk, int first, int eval_only, Flo
   if (!hq) return GAME_OK;
   GAME_TRY(bdev(b, hipMemcpyAsync(hq, b->q, sizeof(FlowQueue), hipMemcpyDeviceToHost, b->stream), "status copy"));
   GAME_TRY(bdev(b, hipStreamSynchronize(b->stream), "synchronize"));
-  if (hq->error) {
-    b->poisoned = true;
-    return fail(GAME_E_DEVICE, "batched scheduler: a workgroup found no open item for too long");
-  }
+  if (hq->error) return batch_stall(b);
   return GAME_OK;
 }
 
@@ -1469,10 +1491,7 @@ game_status batch_time(game_batch* b, int reps, float* ms) {
   if (e1) (void)hipEventDestroy(e1);
   FlowQueue hq{};
   if (st == GAME_OK) st = bdev(b, hipMemcpy(&hq, b->q, sizeof(hq), hipMemcpyDeviceToHost), "status copy");
-  if (st == GAME_OK && hq.error) {
-    b->poisoned = true;
-    st = fail(GAME_E_DEVICE, "batched scheduler: a workgroup found no open item for too long");
-  }
+  if (st == GAME_OK && hq.error) st = batch_stall(b);
   if (st == GAME_OK) *ms = t / (float)reps;
   for (game_ctx* c : b->ctx) c->evaluated = true;
   return st;

@@ -805,16 +805,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // hand-off).
 constexpr uint32_t kParked = 0xFFFFFFFFu;
 
+// Items of run r in epoch e: all of them (completion count), and those
+// claimed through the run's word (wheel and breed phases) or through XCD
+// slice x (fitness phase: slice x holds the row ranges
+// [x n_ranges / 8, (x + 1) n_ranges / 8), every chromosome tile of each, so
+// the tiles that share a range's Phi rows run on one XCD and share its L2).
 __device__ __forceinline__ uint32_t flow_count(const FlowRun& r, uint32_t e) {
   if (e == kParked) return 0u;
   const uint32_t ph = e % 3u;
   return ph == 0u ? (uint32_t)r.n_fit : ph == 1u ? 1u : (uint32_t)r.n_breed;
+}
+__device__ __forceinline__ uint32_t flow_word_count(const FlowRun& r, uint32_t e) {
+  return e == kParked || e % 3u == 0u ? 0u : flow_count(r, e);
+}
+__device__ __forceinline__ int slice_lo(const FlowRun& r, int x) { return x * r.n_ranges / kXcds; }
+__device__ __forceinline__ uint32_t flow_slice_count(const FlowRun& r, uint32_t e, int x) {
+  if (e == kParked || e % 3u != 0u) return 0u;
+  return (uint32_t)((slice_lo(r, x + 1) - slice_lo(r, x)) * r.n_pt);
 }
 
 // Run r finished epoch e: open its next phase or park it (thread 0 of the
 // workgroup that finished the epoch's last item).
 __device__ void flow_advance(const FlowRun& r, FlowCtl* c, FlowQueue* q, uint32_t e, int eval_only) {
   const uint32_t ph = e % 3u;
+  // every item of epoch e is claimed and finished: the count restarts before
+  // any item of the next phase can be claimed (and counted)
+  st_agent(&c->done, 0u);
+  agent_stores_done();
   uint32_t next;
   if (ph == 0u) {
     const bool halted = ld_agent(&r.st->run_active) != 0 && ld_agent(&r.st->stopped) != 0;
@@ -837,10 +854,110 @@ __device__ void flow_advance(const FlowRun& r, FlowCtl* c, FlowQueue* q, uint32_
       next = kParked;  // this launch's generations are bred; the next launch resumes
     }
   }
-  st_agent(&c->done, 0u);
+  // Everything above is visible before the next phase's items can be
+  // claimed.  Opening them is this thread's last action on the run: once
+  // they are open, the phase may finish and the next transition begin at
+  // any moment, so the word must already name the phase (the fitness
+  // phase's items are claimed through the slices, opened after the word).
   agent_stores_done();
   __hip_atomic_exchange(&c->word, (uint64_t)next << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (next == kParked) atomicSub(&q->active, 1u);
+  if (next == kParked) {
+    atomicSub(&q->active, 1u);
+  } else if (next % 3u == 0u) {
+    agent_stores_done();
+    for (int x = 0; x < kXcds; ++x) st_agent(&c->xw[x], (uint64_t)next << 32);
+  }
+}
+
+// Wave 0's search for an item (lane 0 returns the claim): the run with the
+// earliest deadline among those with an open item in this XCD's slice or in
+// the run's word; failing that, any open slice of the earliest-deadline run
+// (an idle XCD takes over another XCD's ranges).  Claims are atomic adds on
+// the slice or word, valid for the epoch the add returns.
+struct Claim {
+  int run, slice;  // slice -1: the run's word
+  uint32_t epoch, item;
+};
+__device__ __forceinline__ void min_deadline(uint64_t& dl, int& idx, int& sl) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t odl = __shfl_xor(dl, off);
+    const int oidx = __shfl_xor(idx, off), osl = __shfl_xor(sl, off);
+    if (oidx >= 0 && (idx < 0 || odl < dl || (odl == dl && (oidx < idx || (oidx == idx && osl < sl))))) {
+      dl = odl;
+      idx = oidx;
+      sl = osl;
+    }
+  }
+}
+
+__device__ bool flow_claim(const FlowRun* __restrict__ runs, int n_runs, FlowCtl* ctl, int xcd, Claim* out) {
+  const int lane = threadIdx.x & 63;
+  uint64_t best_dl = ~0ull;
+  int found = -1, fslice = -1;
+  for (int base = 0; base < n_runs; base += 64) {
+    const int r = base + lane;
+    uint64_t dl = ~0ull;
+    int idx = -1, sl = -1;
+    if (r < n_runs) {
+      const uint64_t w = ld_agent(&ctl[r].word);
+      const uint32_t e = (uint32_t)(w >> 32);
+      bool open = (uint32_t)w < flow_word_count(runs[r], e);
+      if (!open && e != kParked && e % 3u == 0u) {
+        const uint64_t xw = ld_agent(&ctl[r].xw[xcd]);
+        open = (uint32_t)xw < flow_slice_count(runs[r], (uint32_t)(xw >> 32), xcd);
+        sl = xcd;
+      }
+      if (open) {
+        dl = ld_agent(&ctl[r].deadline);
+        idx = r;
+      }
+    }
+    min_deadline(dl, idx, sl);
+    if (idx >= 0 && (found < 0 || dl < best_dl)) {
+      best_dl = dl;
+      found = idx;
+      fslice = sl;
+    }
+  }
+  if (found < 0) {
+    // steal: every (run, slice) pair of runs in a fitness phase
+    for (int base = 0; base < n_runs * kXcds; base += 64) {
+      const int pidx = base + lane, r = pidx / kXcds, x = pidx % kXcds;
+      uint64_t dl = ~0ull;
+      int idx = -1, sl = -1;
+      if (r < n_runs) {
+        const uint64_t xw = ld_agent(&ctl[r].xw[x]);
+        if ((uint32_t)xw < flow_slice_count(runs[r], (uint32_t)(xw >> 32), x)) {
+          dl = ld_agent(&ctl[r].deadline);
+          idx = r;
+          sl = x;
+        }
+      }
+      min_deadline(dl, idx, sl);
+      if (idx >= 0 && (found < 0 || dl < best_dl)) {
+        best_dl = dl;
+        found = idx;
+        fslice = sl;
+      }
+    }
+  }
+  if (found < 0 || lane != 0) return false;
+  const FlowRun& r = runs[found];
+  if (fslice < 0) {
+    const uint64_t old = __hip_atomic_fetch_add(&ctl[found].word, 1ull, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t e = (uint32_t)(old >> 32), i = (uint32_t)old;
+    if (i >= flow_word_count(r, e)) return false;
+    *out = Claim{found, -1, e, i};
+    return true;
+  }
+  const uint64_t old = __hip_atomic_fetch_add(&ctl[found].xw[fslice], 1ull, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t e = (uint32_t)(old >> 32), i = (uint32_t)old;
+  if (i >= flow_slice_count(r, e, fslice)) return false;
+  // slice-local item -> the run's item number (chromosome tile fastest)
+  *out = Claim{found, fslice, e, (uint32_t)(slice_lo(r, fslice) * r.n_pt) + i};
+  return true;
 }
 
 template <class Tr, class O>
@@ -853,51 +970,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   __shared__ int s_state, s_run, s_gen;  // s_state: 0 item claimed, 1 none open, 2 leave
   __shared__ uint32_t s_epoch, s_idx;
   __shared__ int s_last;
+  const int xcd = (int)(blockIdx.x % kXcds);
   uint64_t idle_since = 0;
   for (;;) {
     __syncthreads();  // the previous item's LDS is no longer read
     if (threadIdx.x < 64) {
-      const int lane = threadIdx.x;
-      // the open run with the earliest deadline (ties to the lower index)
-      uint64_t best_dl = ~0ull;
-      int found = -1;
-      for (int base = 0; base < n_runs; base += 64) {
-        const int r = base + lane;
-        uint64_t dl = ~0ull;
-        int idx = -1;
-        if (r < n_runs) {
-          const uint64_t w = ld_agent(&ctl[r].word);
-          if ((uint32_t)w < flow_count(runs[r], (uint32_t)(w >> 32))) {
-            dl = ld_agent(&ctl[r].deadline);
-            idx = r;
-          }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-          const uint64_t odl = __shfl_xor(dl, off);
-          const int oidx = __shfl_xor(idx, off);
-          if (oidx >= 0 && (idx < 0 || odl < dl || (odl == dl && oidx < idx))) {
-            dl = odl;
-            idx = oidx;
-          }
-        }
-        if (idx >= 0 && (found < 0 || dl < best_dl)) {
-          best_dl = dl;
-          found = idx;
-        }
-      }
-      if (lane == 0) {
+      Claim cl{};
+      const bool got = flow_claim(runs, n_runs, ctl, xcd, &cl);
+      if (threadIdx.x == 0) {
         int state = 1;
-        if (found >= 0) {
-          const uint64_t old = __hip_atomic_fetch_add(&ctl[found].word, 1ull, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-          const uint32_t e = (uint32_t)(old >> 32), i = (uint32_t)old;
-          if (i < flow_count(runs[found], e)) {
-            state = 0;
-            s_run = found;
-            s_epoch = e;
-            s_idx = i;
-            s_gen = ld_agent(&ctl[found].gen);
-          }
+        if (got) {
+          state = 0;
+          s_run = cl.run;
+          s_epoch = cl.epoch;
+          s_idx = cl.item;
+          s_gen = ld_agent(&ctl[cl.run].gen);
         } else if (ld_agent(&q->active) == 0u || ld_agent(&q->error) != 0u) {
           state = 2;
         }
@@ -981,7 +1068,11 @@ __global__ void flow_arm_kernel(const FlowRun* __restrict__ runs, int n_runs, Fl
     const FlowRun& r = runs[i];
     const bool halted = run_halted(r.st);
     FlowCtl& c = ctl[i];
-    c.word = halted ? (uint64_t)kParked << 32 : 0ull;
+    // epoch 0 (the fitness phase) opens in the word and the slices; a
+    // stopped run stays closed in both
+    const uint64_t open = halted ? (uint64_t)kParked << 32 : 0ull;
+    c.word = open;
+    for (int x = 0; x < kXcds; ++x) c.xw[x] = open;
     c.deadline = now + r.span;
     c.done = 0u;
     c.gen = r.st->generation;

@@ -328,8 +328,10 @@ struct FlowRun {
   int M_pad, ldsw, n_pt, n_ranges, part_ld, task, tile_p, ub;
   int n_fit, n_breed, sel, rank_pow2, t_cap, pad;
 };
+constexpr int kXcds = 8;  // XCDs of the device (workgroup b runs on XCD b % 8)
 struct FlowCtl {      // per run; read and written only at device scope
-  uint64_t word;      // phase epoch << 32 | items claimed in it
+  uint64_t word;      // phase epoch << 32 | items claimed (wheel and breed phases)
+  uint64_t xw[kXcds]; // fitness phase: epoch << 32 | items claimed in XCD slice x
   uint64_t deadline;  // of the run's current generation (wall clock)
   uint32_t done;      // items finished in the epoch
   int32_t gen;        // the run's generation
