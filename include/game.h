@@ -456,7 +456,12 @@ game_status game_batch_workspace_size(const game_config* cfgs, int32_t n_runs, s
  * workspace, then pick each run's tile width and row ranges: configurations
  * with tile_p and row_groups both set keep them when every run sets them;
  * otherwise the tuner times candidate assignments with evaluation-only
- * scheduler launches on the device and keeps the fastest.  Blocking.
+ * scheduler launches on the device and keeps the fastest: a sweep of LDS
+ * budget x item size (each run the widest tile within the budget), then one
+ * tile width narrower per class of runs (task x gene count), kept where
+ * faster.  Each run's choice is cached for the process by its shape (dtype,
+ * task, padded gene count, population, log2 patterns); a batch whose runs
+ * all have a cached choice starts from those without a sweep.  Blocking.
  *   X_devs[i], t_devs[i]: run i's patterns and targets, as for game_init.
  */
 game_status game_batch_init(const game_config* cfgs, int32_t n_runs, const void* const* X_devs,

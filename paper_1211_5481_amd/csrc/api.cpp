@@ -8,6 +8,9 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "game.h"
@@ -1497,55 +1500,137 @@ game_status batch_time(game_batch* b, int reps, float* ms) {
   return st;
 }
 
-// The tuner: every context takes the widest tile that fits the LDS budget of
-// the candidate, and as many row ranges as give items of about W row-tile x
-// chromosome x gene units; the (budget, W) pair with the fastest batched
-// evaluation wins.  Contexts whose configuration fixes tile_p and
-// row_groups keep them.
+// Per-run results of the batched tuner, kept for the process and keyed by a
+// run's shape (dtype, task, padded genes, population in 32s, log2 of the
+// patterns): the tile width and the row-range rule (item size) the run had
+// in the fastest batch it was tuned in.  A batch whose runs all have a
+// cached choice starts from it instead of sweeping.
+struct ShapeKey {
+  int dtype, task, M_pad, P32, logN;
+  bool operator<(const ShapeKey& o) const {
+    return std::tie(dtype, task, M_pad, P32, logN) < std::tie(o.dtype, o.task, o.M_pad, o.P32, o.logN);
+  }
+};
+struct ShapeChoice {
+  int tile_p;
+  double work;  // row-tile x chromosome x gene units per item
+};
+std::mutex g_tune_mu;
+std::map<ShapeKey, ShapeChoice>& tune_cache() {
+  static std::map<ShapeKey, ShapeChoice> m;
+  return m;
+}
+ShapeKey shape_key(const game_ctx* c) {
+  const Plan& p = c->plan;
+  int logN = 0;
+  while ((int64_t(1) << (logN + 1)) <= p.N) ++logN;
+  return ShapeKey{c->cfg.dtype, c->cfg.task, p.M_pad, (p.P + 31) / 32, logN};
+}
+
+// Row ranges giving items of about W row-tile x chromosome x gene units.
+int ranges_for(const Plan& p, int tp, double W) {
+  const double per_rt = (double)tp * p.M_pad;
+  const int64_t rts = std::max<int64_t>(1, (int64_t)std::llround(W / per_rt));
+  return (int)std::min<int64_t>(std::max<int64_t>((p.n_rt + rts - 1) / rts, 1), p.n_rg_max);
+}
+
+// Widest tile within an LDS budget that a population of P fills.
+int widest_tile(int dtype, const Plan& p, size_t budget) {
+  for (int cand : {128, 64})
+    if (cand <= round_up(p.P, 32) && fitness_lds_bytes(dtype, p.M_pad, cand) <= budget) return cand;
+  return fitness_lds_fits(dtype, p.M_pad, 32) ? 32 : p.tile_p;
+}
+
+// The tuner, on evaluation-only scheduler launches over the runs' current
+// populations (a configured tile_p / row_groups is always kept):
+//   1. sweep: an LDS budget (the scheduler's dynamic LDS is its widest
+//      tile; above 80 KiB one workgroup fits a CU instead of two) x an item
+//      size W; every run takes the widest tile within the budget and ranges
+//      of about W units per item;
+//   2. refinement per class of runs (task x padded gene count up to 64, 128,
+//      256, more): the class's runs one tile width narrower, each run's
+//      item size kept; kept where the launch is faster;
+//   3. the per-run choices go to the shape cache.
+// With a cached choice for every run, the batch starts from those and
+// steps 1-2 are skipped.
 game_status batch_tune(game_batch* b) {
-  const size_t budgets[] = {98304, 49152};
-  const double works[] = {1.0 * (1 << 20), 2.0 * (1 << 20), 4.0 * (1 << 20), 8.0 * (1 << 20),
-                          16.0 * (1 << 20)};
-  float best = 0.0f;
-  std::vector<int> best_tp, best_rg;
-  for (size_t budget : budgets) {
-    for (double W : works) {
-      std::vector<int> tp(b->n), rg(b->n);
-      for (int i = 0; i < b->n; ++i) {
-        const game_config& cfg = b->ctx[i]->cfg;
-        const Plan& p = b->ctx[i]->plan;
-        int t = cfg.tile_p;
-        if (t == 0) {
-          // widest tile within the budget that a population of P fills
-          t = 32;
-          for (int cand : {128, 64})
-            if (cand <= round_up(p.P, 32) && fitness_lds_bytes(b->dtype, p.M_pad, cand) <= budget) {
-              t = cand;
-              break;
-            }
-          if (!fitness_lds_fits(b->dtype, p.M_pad, t)) t = p.tile_p;
-        }
-        int r = cfg.row_groups;
-        if (r == 0) {
-          const double per_rt = (double)t * p.M_pad;
-          const int64_t rts = std::max<int64_t>(1, (int64_t)std::llround(W / per_rt));
-          r = (int)std::min<int64_t>(std::max<int64_t>((p.n_rt + rts - 1) / rts, 1), p.n_rg_max);
-        }
-        tp[i] = t;
-        rg[i] = r;
+  const int n = b->n;
+  std::vector<int> tp(n), rg(n);
+  std::vector<double> wk(n, 0.0);
+  auto fixed_tp = [&](int i) { return b->ctx[i]->cfg.tile_p; };
+  auto fixed_rg = [&](int i) { return b->ctx[i]->cfg.row_groups; };
+  auto build = [&](int i, int t, double W) {
+    const Plan& p = b->ctx[i]->plan;
+    tp[i] = fixed_tp(i) > 0 ? fixed_tp(i) : t;
+    rg[i] = fixed_rg(i) > 0 ? fixed_rg(i) : ranges_for(p, tp[i], W);
+    wk[i] = W;
+  };
+  bool all_cached = true;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int i = 0; i < n; ++i) {
+      auto it = tune_cache().find(shape_key(b->ctx[i]));
+      if (it == tune_cache().end()) {
+        all_cached = false;
+        break;
       }
-      GAME_TRY(batch_apply(b, tp, rg));
-      float ms = 0.0f;
-      GAME_TRY(batch_time(b, 3, &ms));
-      if (best_tp.empty() || ms < best) {
-        best = ms;
-        best_tp = tp;
-        best_rg = rg;
-      }
+      build(i, it->second.tile_p, it->second.work);
     }
   }
+  float best = 0.0f;
+  if (all_cached) {
+    GAME_TRY(batch_apply(b, tp, rg));
+    GAME_TRY(batch_time(b, 3, &best));
+  } else {
+    const size_t budgets[] = {98304, 49152};
+    const double works[] = {1.0 * (1 << 20), 2.0 * (1 << 20), 4.0 * (1 << 20), 8.0 * (1 << 20),
+                            16.0 * (1 << 20)};
+    std::vector<int> btp, brg;
+    std::vector<double> bwk;
+    for (size_t budget : budgets)
+      for (double W : works) {
+        for (int i = 0; i < n; ++i) build(i, widest_tile(b->dtype, b->ctx[i]->plan, budget), W);
+        GAME_TRY(batch_apply(b, tp, rg));
+        float ms = 0.0f;
+        GAME_TRY(batch_time(b, 3, &ms));
+        if (btp.empty() || ms < best) {
+          best = ms;
+          btp = tp;
+          brg = rg;
+          bwk = wk;
+        }
+      }
+    tp = btp;
+    rg = brg;
+    wk = bwk;
+    auto cls = [&](int i) {
+      const int M = b->ctx[i]->plan.M_pad;
+      return 4 * b->ctx[i]->cfg.task + (M <= 64 ? 0 : M <= 128 ? 1 : M <= 256 ? 2 : 3);
+    };
+    for (int k = 0; k < 8; ++k) {
+      std::vector<int> ctp = tp, crg = rg;
+      bool any = false;
+      for (int i = 0; i < n; ++i) {
+        if (cls(i) != k || fixed_tp(i) > 0 || tp[i] <= 32) continue;
+        ctp[i] = tp[i] / 2;
+        if (fixed_rg(i) == 0) crg[i] = ranges_for(b->ctx[i]->plan, ctp[i], wk[i]);
+        any = true;
+      }
+      if (!any) continue;
+      GAME_TRY(batch_apply(b, ctp, crg));
+      float ms = 0.0f;
+      GAME_TRY(batch_time(b, 3, &ms));
+      if (ms < best) {
+        best = ms;
+        tp = ctp;
+        rg = crg;
+      }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int i = 0; i < n; ++i) tune_cache()[shape_key(b->ctx[i])] = ShapeChoice{tp[i], wk[i]};
+  }
   b->tune_ms = best;
-  return batch_apply(b, best_tp, best_rg);
+  return batch_apply(b, tp, rg);
 }
 
 game_status check_batch(game_batch* b) {

@@ -261,3 +261,29 @@ def test_batch_longer_than_one_launch_equals_alone():
         assert results[i]["generations"] == s[5]
         assert np.all(lat[i, :s[5] - 1] > 0.0)
     b.close()
+
+
+def test_batch_tuner_cache_reuses_choices():
+    """A second batch of runs with the same shapes takes the tuner's cached
+    per-run choices (same tile widths and row ranges) and still equals the
+    runs alone."""
+    import time
+    from paper_1211_5481_amd import Batch
+    specs = [("classification", 30011, 12, 6, 512, 4, 0.0, 61),
+             ("regression", 9000, 7, 4, 256, 4, 0.0, 62),
+             ("classification", 4000, 5, 8, 96, 4, 0.0, 63)]
+    runs = make_runs(specs)
+    announce("batched tuner, then a batch of the same shapes from its cache")
+    t0 = time.perf_counter()
+    b1 = Batch(runs)
+    t1 = time.perf_counter()
+    tiles1 = b1.tiles()
+    b1.close()
+    t2 = time.perf_counter()
+    b2 = Batch(runs)
+    t3 = time.perf_counter()
+    assert b2.tiles() == tiles1
+    print(f"tuned init {t1 - t0:.3f} s, cached init {t3 - t2:.3f} s")
+    results = b2.run()
+    compare_with_alone(b2, runs, results)
+    b2.close()
