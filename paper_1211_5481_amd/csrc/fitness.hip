@@ -438,21 +438,42 @@ __device__ __forceinline__ int item_rot(int64_t lt, int64_t n_items, int cpx, in
   return ub == 1 ? 2 * (int)(((lt % per) / cpx) & 1) : 0;
 }
 
+// Loads through the global address space.  The item's pointers are global
+// memory; said so explicitly, the loads are global ones even where the
+// pointer came from memory (the batched scheduler's table) rather than a
+// kernel argument: a flat load would count against the LDS counter too, so
+// each LDS wait of the K loop would also wait for the Phi loads in flight.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+  typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, *(gptr<uint32_t>)p);
+  else if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, *(gptr<uint64_t>)p);
+  else {
+    static_assert(sizeof(T) == 16, "4, 8 or 16-byte loads");
+    return __builtin_bit_cast(T, *(gptr<u32x4v>)p);
+  }
+}
+__device__ __forceinline__ uint64_t gload_agent(const uint64_t* p) {
+  return __hip_atomic_load((gptr<uint64_t>)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // A gene-tile load unit: plain, or at device scope (kAgent: the tile was
 // written by the breed phase of the same launch).
 template <bool kAgent, class Ld>
 __device__ __forceinline__ Ld ld_unit(const Ld* p) {
   if constexpr (!kAgent) {
-    return *p;
+    return gload(p);
   } else if constexpr (sizeof(Ld) == 8) {
-    return __builtin_bit_cast(Ld, ld_agent(reinterpret_cast<const uint64_t*>(p)));
+    return __builtin_bit_cast(Ld, gload_agent(reinterpret_cast<const uint64_t*>(p)));
   } else {
     static_assert(sizeof(Ld) == 16, "gene-tile units are 8 or 16 bytes");
     const uint64_t* q = reinterpret_cast<const uint64_t*>(p);
     struct Pair {
       uint64_t lo, hi;
     };
-    return __builtin_bit_cast(Ld, Pair{ld_agent(q), ld_agent(q + 1)});
+    return __builtin_bit_cast(Ld, Pair{gload_agent(q), gload_agent(q + 1)});
   }
 }
 
@@ -516,14 +537,14 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) tv[i][r] = tvec[nw0 + i * 16 + row_in_block(r)];
+      for (int r = 0; r < 4; ++r) tv[i][r] = gload(tvec + nw0 + i * 16 + row_in_block(r));
   };
   auto loadA = [&](Ld* a, int64_t u, int kb) {
     const int64_t nw0 = u * TU;
 #pragma unroll
     for (int i = 0; i < WM; ++i)
-      a[i] = *reinterpret_cast<const Ld*>(phi + (nw0 + i * 16 + lrow) * (int64_t)M_pad +
-                                          lgrp * Tr::kPerLane + kb * Tr::kBlk);
+      a[i] = gload(reinterpret_cast<const Ld*>(phi + (nw0 + i * 16 + lrow) * (int64_t)M_pad +
+                                               lgrp * Tr::kPerLane + kb * Tr::kBlk));
   };
   auto loadB = [&](Ld* b, int kb) {
 #pragma unroll
@@ -805,6 +826,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // hand-off).
 constexpr uint32_t kParked = 0xFFFFFFFFu;
 
+
 // Items of run r in epoch e: all of them (completion count), and those
 // claimed through the run's word (wheel and breed phases) or through XCD
 // slice x (fitness phase: slice x holds the row ranges
@@ -1010,8 +1032,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       __builtin_amdgcn_s_sleep(8);
       continue;
     }
-    const FlowRun& r = runs[s_run];
-    const uint32_t e = s_epoch, item = s_idx;
+    // the claim is the same for every lane; saying so keeps the run's
+    // parameters, and the item's loop bounds, in scalar registers
+    const int ri = __builtin_amdgcn_readfirstlane(s_run);
+    const uint32_t e = __builtin_amdgcn_readfirstlane(s_epoch);
+    const uint32_t item = __builtin_amdgcn_readfirstlane(s_idx);
+    const FlowRun& r = runs[ri];
     const uint32_t ph = e % 3u;
     if (ph == 0u) {
       const int pt = (int)(item % (uint32_t)r.n_pt);
@@ -1020,12 +1046,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const T* tile = static_cast<const T*>(r.tile);
       const Acc* biasv = static_cast<const Acc*>(r.biasv);
       const Acc* tvec = static_cast<const Acc*>(r.tvec);
+      double* psse = r.psse;
+      uint32_t* pmiss = r.pmiss;
 #define GAME_FLOW_ITEM(CLS, WN)                                                                   \
   do {                                                                                            \
-    lds_item<Tr, CLS, WN, 1, true>(phi, tile, biasv, tvec, r.N, r.M_pad, r.ldsw, r.n_ranges, pt,  \
+    lds_item<Tr, CLS, WN, 2, true>(phi, tile, biasv, tvec, r.N, r.M_pad, r.ldsw, r.n_ranges, pt,  \
                                    wr, r.ub, item_rot(item, r.n_fit, cpx, r.ub), r.part_ld,       \
-                                   r.psse, r.pmiss, lds);                                         \
-    fitness_tail<16 * WN, true>(r.tail, pt, r.n_pt, r.n_ranges, r.part_ld, r.psse, r.pmiss);      \
+                                   psse, pmiss, lds);                                             \
+    fitness_tail<16 * WN, true>(r.tail, pt, r.n_pt, r.n_ranges, r.part_ld, psse, pmiss);          \
   } while (0)
       if (r.task == GAME_CLASSIFICATION) {
         if (r.tile_p == 128) GAME_FLOW_ITEM(true, 8);
@@ -1044,15 +1072,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         rank_block<256, true>(r.tail.fit, r.tail.P, r.rank_pow2, reinterpret_cast<int*>(r.wheel),
                               reinterpret_cast<unsigned char*>(lds));
     } else {
-      breed_work<O, float, true>(r.breed, (int)item, (uint32_t)s_gen);
+      breed_work<O, float, true>(r.breed, (int)item, (uint32_t)__builtin_amdgcn_readfirstlane(s_gen));
     }
     // every store of the item is acknowledged before its completion counts
     agent_stores_done();
     __syncthreads();
     if (threadIdx.x == 0)
-      s_last = atomicAdd(&ctl[s_run].done, 1u) + 1u == flow_count(r, e);
+      s_last = atomicAdd(&ctl[ri].done, 1u) + 1u == flow_count(r, e);
     __syncthreads();
-    if (s_last && threadIdx.x == 0) flow_advance(r, &ctl[s_run], q, e, eval_only);
+    if (s_last && threadIdx.x == 0) flow_advance(r, &ctl[ri], q, e, eval_only);
   }
 }
 

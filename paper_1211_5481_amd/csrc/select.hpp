@@ -63,43 +63,32 @@ __device__ void block_sort_pairs(uint64_t* sk, int* si, int n_pow2) {
 
 // Loads and stores of values another workgroup of the same launch produces or
 // consumes: agent-scope atomics, which go through to the device-coherent
-// level instead of an XCD's L2 (no cache invalidation needed).
-__device__ __forceinline__ double ld_agent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// level instead of an XCD's L2 (no cache invalidation needed).  They always
+// address global memory, and say so: a pointer read from memory (the
+// batched scheduler's table) would otherwise be accessed with flat
+// instructions, whose completions the LDS counter waits for too.
+template <class T>
+using agent_ptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ T ld_agent_g(const T* p) {
+  return __hip_atomic_load((agent_ptr<const T>)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <class T>
+__device__ __forceinline__ void st_agent_g(T* p, T v) {
+  __hip_atomic_store((agent_ptr<T>)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_agent(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int32_t ld_agent(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ float ld_agent(const float* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(int32_t* p, int32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(float* p, float v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(uint16_t* p, uint16_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(_Float16* p, _Float16 v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ __forceinline__ double ld_agent(const double* p) { return ld_agent_g(p); }
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) { return ld_agent_g(p); }
+__device__ __forceinline__ int32_t ld_agent(const int32_t* p) { return ld_agent_g(p); }
+__device__ __forceinline__ float ld_agent(const float* p) { return ld_agent_g(p); }
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) { return ld_agent_g(p); }
+__device__ __forceinline__ void st_agent(double* p, double v) { st_agent_g(p, v); }
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) { st_agent_g(p, v); }
+__device__ __forceinline__ void st_agent(int32_t* p, int32_t v) { st_agent_g(p, v); }
+__device__ __forceinline__ void st_agent(float* p, float v) { st_agent_g(p, v); }
+__device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) { st_agent_g(p, v); }
+__device__ __forceinline__ void st_agent(uint16_t* p, uint16_t v) { st_agent_g(p, v); }
+__device__ __forceinline__ void st_agent(_Float16* p, _Float16 v) { st_agent_g(p, v); }
 
 // Loads and stores whose flavour a kernel picks at compile time: kAgent for
 // data that other workgroups of the same launch write or read (the batched
