@@ -443,8 +443,11 @@ void game_destroy(game_ctx* ctx);
  * fit the LDS-staged kernel.  Each run computes exactly what game_run would
  * on a context created with the same configuration and the tile_p /
  * row_groups the batch uses (game_batch_tiles).  A workgroup that finds no
- * open item for far longer than any phase takes (at least 2 s) ends the
- * launch with GAME_E_DEVICE and poisons the batch.
+ * open item for far longer than any phase takes (20x one generation of every
+ * run at 50 TFLOP/s, at least 2 s; the environment variable
+ * GAME_FLOW_IDLE_US, read when the batch's tiles are set, overrides it in
+ * microseconds) ends the launch with GAME_E_DEVICE, naming the stuck run's
+ * phase state, and poisons the batch.
  */
 typedef struct game_batch game_batch;
 

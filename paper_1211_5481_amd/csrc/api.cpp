@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <algorithm>
@@ -1417,8 +1418,14 @@ game_status batch_tables(game_batch* b) {
   // a workgroup that finds no open item for this long gives up (a phase of
   // one run never takes nearly this long: 20x one generation of every run
   // at 50 TFLOP/s, at least 2 s)
-  const double idle_s = std::max(2.0, 20.0 * b->gen_flop / 50e12);
-  b->idle_ticks = (uint64_t)(idle_s * ticks_per_s);
+  // (GAME_FLOW_IDLE_US overrides it, in microseconds)
+  double idle_s = std::max(2.0, 20.0 * b->gen_flop / 50e12);
+  if (const char* env = std::getenv("GAME_FLOW_IDLE_US")) {
+    char* end = nullptr;
+    const double us = std::strtod(env, &end);
+    if (end != env && us > 0.0) idle_s = us * 1e-6;
+  }
+  b->idle_ticks = std::max<uint64_t>(1, (uint64_t)(idle_s * ticks_per_s));
   GAME_TRY(bdev(b, hipMemcpyAsync(b->druns, sorted.data(), sizeof(FlowRun) * b->n, hipMemcpyHostToDevice, b->stream), "batch tables"));
   GAME_TRY(bdev(b, hipStreamSynchronize(b->stream), "synchronize"));
   return GAME_OK;

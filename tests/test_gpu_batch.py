@@ -287,3 +287,24 @@ def test_batch_tuner_cache_reuses_choices():
     results = b2.run()
     compare_with_alone(b2, runs, results)
     b2.close()
+
+
+def test_batch_stall_is_reported_and_poisons(monkeypatch):
+    """The scheduler's bounded wait, forced from the host: with a 1 us idle
+    bound the workgroups that find nothing to do give up at once (every
+    kernel still ends normally); the run reports the stall and the batch
+    refuses further work."""
+    from paper_1211_5481_amd import Batch
+    from paper_1211_5481_amd._lib import GameError
+    specs = [("regression", 3000, 4, 4, 64, 40, 0.0, 71)]
+    runs = make_runs(specs)
+    cfg = runs[0][0]
+    runs = [(type(cfg)(**{**cfg.__dict__, "tile_p": 64, "row_groups": 1}), runs[0][1], runs[0][2])]
+    monkeypatch.setenv("GAME_FLOW_IDLE_US", "1")
+    announce("batched scheduler with a 1 us idle bound: stall reported")
+    b = Batch(runs)
+    with pytest.raises(GameError, match="no open item"):
+        b.run()
+    with pytest.raises(GameError, match="poisoned"):
+        b.run()
+    b.close()
