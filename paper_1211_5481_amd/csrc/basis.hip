@@ -10,11 +10,15 @@
 // recurrence seeded by one sincos) and rounded once to the storage type
 // (bf16/f16 round the float32-rounded value).
 //
-// Layout: Phi is row-major N x ld.  A workgroup builds a block of rows in LDS
-// in any order, then the block, which is contiguous in HBM, is written with
-// 16-byte stores by consecutive lanes (fully coalesced).
+// Layout: Phi is row-major N x ld.  Where a feature's K values fill whole
+// 16-byte stores (per-feature layout), one thread per (row, feature) writes
+// them directly (basis_direct_kernel); otherwise a workgroup builds a block
+// of rows in LDS in any order, then the block, which is contiguous in HBM,
+// is written with 16-byte stores by consecutive lanes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "expand.hpp"
 #include "game_internal.hpp"
@@ -117,6 +121,54 @@ __global__ __launch_bounds__(kBasisThreads) void basis_kernel(const XT* __restri
   }
 }
 
+// Direct form, for the per-feature layout when a feature's K values fill
+// whole 16-byte stores: each thread takes kPairs (row, feature) pairs a
+// workgroup-width apart, loads their inputs together (the loads' latency
+// binds otherwise), then expands each in column order and stores its K
+// values with 16-byte stores; the thread of a row's last feature also
+// zeroes the row's pad columns.  No LDS, no barrier.
+constexpr int kPairs = 4;
+template <typename XT, typename O, int kBasis>
+__global__ __launch_bounds__(kBasisThreads) void basis_direct_kernel(const XT* __restrict__ X,
+                                                                     int64_t rows_in, int64_t rows_out,
+                                                                     int F, int D, int K, int M,
+                                                                     int64_t ld, O* __restrict__ phi) {
+  constexpr int kPer = 16 / (int)sizeof(O);  // values per 16-byte store
+  const int64_t total = rows_out * F, in_total = rows_in * F;
+  const int64_t base = (int64_t)blockIdx.x * kBasisThreads * kPairs + threadIdx.x;
+  XT xs[kPairs];
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) {
+    const int64_t idx = base + (int64_t)p * kBasisThreads;
+    // the load address is clamped, its value unused past the input rows
+    xs[p] = X[idx < in_total ? idx : 0];
+  }
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) {
+    const int64_t idx = base + (int64_t)p * kBasisThreads;
+    if (idx >= total) break;
+    // (row, feature) by a 32-bit division where the pair count allows
+    int64_t n;
+    if (total <= 0xFFFFFFFFll) n = (int64_t)((uint32_t)idx / (uint32_t)F);
+    else n = idx / F;
+    const int i = (int)(idx - n * F);
+    const bool valid = idx < in_total;
+    BasisSeq<kBasis> g(D, valid ? (double)xs[p] : 0.0);
+    O* dst = phi + n * ld + (int64_t)i * K;
+    for (int k = 0; k < K; k += kPer) {
+      O v[kPer];
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const double val = g.next();
+        v[j] = to_storage<O>(valid ? val : 0.0);
+      }
+      *reinterpret_cast<uint4*>(dst + k) = __builtin_bit_cast(uint4, v);
+    }
+    if (i == F - 1)
+      for (int64_t c = M; c < ld; ++c) phi[n * ld + c] = to_storage<O>(0.0);
+  }
+}
+
 template <typename XT, typename O>
 hipError_t launch_typed(const game_config* cfg, const void* X, int64_t rows_in, int64_t rows_out,
                         void* phi, int64_t ld, hipStream_t s) {
@@ -124,6 +176,32 @@ hipError_t launch_typed(const game_config* cfg, const void* X, int64_t rows_in, 
   const int K = (cfg->basis == GAME_BASIS_TRIG ? 2 : 1) * D;
   const int shared = cfg->shared;
   const int M = shared ? K : F * K;
+  if (!shared && ((int64_t)K * (int64_t)sizeof(O)) % 16 == 0 && (ld * (int64_t)sizeof(O)) % 16 == 0 &&
+      (reinterpret_cast<uintptr_t>(phi) & 15) == 0) {
+    const int64_t pairs = rows_out * F;
+    if (pairs == 0) return hipSuccess;
+    const int64_t per_wg = (int64_t)kBasisThreads * kPairs;
+    const int64_t grid = (pairs + per_wg - 1) / per_wg;
+    if (grid > 0x7FFFFFFFll) return hipErrorInvalidValue;
+    const dim3 g((unsigned)grid), b(kBasisThreads);
+    const XT* x = static_cast<const XT*>(X);
+    O* out = static_cast<O*>(phi);
+    switch (cfg->basis) {
+      case GAME_BASIS_POWER:
+        hipLaunchKernelGGL((basis_direct_kernel<XT, O, GAME_BASIS_POWER>), g, b, 0, s, x, rows_in, rows_out, F, D, K, M, ld, out);
+        break;
+      case GAME_BASIS_CHEBYSHEV:
+        hipLaunchKernelGGL((basis_direct_kernel<XT, O, GAME_BASIS_CHEBYSHEV>), g, b, 0, s, x, rows_in, rows_out, F, D, K, M, ld, out);
+        break;
+      case GAME_BASIS_LEGENDRE:
+        hipLaunchKernelGGL((basis_direct_kernel<XT, O, GAME_BASIS_LEGENDRE>), g, b, 0, s, x, rows_in, rows_out, F, D, K, M, ld, out);
+        break;
+      default:
+        hipLaunchKernelGGL((basis_direct_kernel<XT, O, GAME_BASIS_TRIG>), g, b, 0, s, x, rows_in, rows_out, F, D, K, M, ld, out);
+        break;
+    }
+    return hipGetLastError();
+  }
   const int64_t row_bytes = ld * (int64_t)sizeof(O);
   // the shared model keeps K double accumulators per row (one thread per row)
   const int64_t acc_bytes = shared ? (int64_t)K * 8 : 0;

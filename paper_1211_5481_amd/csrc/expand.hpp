@@ -70,4 +70,57 @@ __device__ __forceinline__ void expand_feature(int basis, int D, double x, Put p
   }
 }
 
+// The same K values, one at a time in column order (for trig: every cosine,
+// then every sine, each sequence its own recurrence), by the same operations
+// as expand_feature, so each value is the same double.  The basis is a
+// template parameter, so the sequence is branch-free per value.
+template <int kBasis>
+struct BasisSeq {
+  int D, k;
+  double x, prev, cur;  // power / Chebyshev / Legendre state; trig: cosines
+  double c1, sp, sc;    // trig: cos(x), and the sine recurrence
+  __device__ __forceinline__ BasisSeq(int d, double xv) : D(d), k(0), x(xv) {
+    prev = 1.0;
+    cur = x;
+    c1 = sp = sc = 0.0;
+    if constexpr (kBasis == GAME_BASIS_TRIG) {
+      double s1;
+      sincos(x, &s1, &c1);
+      cur = c1;
+      sc = s1;
+    }
+  }
+  __device__ __forceinline__ double next() {
+    double v;
+    if constexpr (kBasis == GAME_BASIS_POWER) {
+      v = cur;
+      cur *= x;
+    } else if constexpr (kBasis == GAME_BASIS_CHEBYSHEV) {
+      v = cur;
+      const double nxt = 2.0 * x * cur - prev;
+      prev = cur;
+      cur = nxt;
+    } else if constexpr (kBasis == GAME_BASIS_LEGENDRE) {
+      v = cur;
+      const double j = (double)(k + 1);
+      const double num = (2.0 * j + 1.0) * x * cur - j * prev;
+      const double nxt = k < kLegInv ? num * kLegInvTab.v[k] : num / (j + 1.0);
+      prev = cur;
+      cur = nxt;
+    } else if (k < D) {
+      v = cur;
+      const double cn = 2.0 * c1 * cur - prev;
+      prev = cur;
+      cur = cn;
+    } else {
+      v = sc;
+      const double sn = 2.0 * c1 * sc - sp;
+      sp = sc;
+      sc = sn;
+    }
+    ++k;
+    return v;
+  }
+};
+
 }  // namespace game
