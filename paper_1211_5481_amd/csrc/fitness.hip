@@ -155,10 +155,15 @@ __device__ __forceinline__ TailLds& tail_lds() {
   return s;
 }
 
+// An arrival count: the counter's previous value (device scope, in global memory).
+__device__ __forceinline__ uint32_t arrive(uint32_t* c) {
+  return __hip_atomic_fetch_add((agent_ptr<uint32_t>)c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // kFlow: the batched scheduler runs every phase of a run inside one launch,
 // so the counters, the ranking and the state are also written at device scope.
 template <int TP, bool kFlow = false>
-__device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, int part_ld,
+__device__ __forceinline__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, int part_ld,
                              const double* psse, const uint32_t* pmiss) {
   constexpr int S = 256 / TP;
   TailLds& sh = tail_lds();
@@ -168,7 +173,7 @@ __device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, i
   // the partial row was stored at agent scope; order it before the arrival
   agent_stores_done();
   __syncthreads();
-  if (threadIdx.x == 0) s_flag = atomicAdd(&t.counters[pt], 1u) == (uint32_t)(n_rg - 1);
+  if (threadIdx.x == 0) s_flag = arrive(&t.counters[pt]) == (uint32_t)(n_rg - 1);
   __syncthreads();
   if (!s_flag) return;
   const int c = threadIdx.x % TP, seg = threadIdx.x / TP;
@@ -233,7 +238,7 @@ __device__ void fitness_tail(const FitTail& t, int pt, int n_pt, int64_t n_rg, i
   __syncthreads();
   if (threadIdx.x == 0) {
     stc<kFlow>(&t.counters[pt], 0u);
-    s_flag = t.n_top > 0 && atomicAdd(&t.counters[t.n_pt_cap], 1u) == (uint32_t)(n_pt - 1);
+    s_flag = t.n_top > 0 && arrive(&t.counters[t.n_pt_cap]) == (uint32_t)(n_pt - 1);
   }
   __syncthreads();
   if (!s_flag) return;
@@ -848,7 +853,7 @@ __device__ __forceinline__ uint32_t flow_slice_count(const FlowRun& r, uint32_t 
 
 // Run r finished epoch e: open its next phase or park it (thread 0 of the
 // workgroup that finished the epoch's last item).
-__device__ void flow_advance(const FlowRun& r, FlowCtl* c, FlowQueue* q, uint32_t e, int eval_only) {
+__device__ __forceinline__ void flow_advance(const FlowRun& r, FlowCtl* c, FlowQueue* q, uint32_t e, int eval_only) {
   const uint32_t ph = e % 3u;
   // every item of epoch e is claimed and finished: the count restarts before
   // any item of the next phase can be claimed (and counted)
@@ -912,7 +917,8 @@ __device__ __forceinline__ void min_deadline(uint64_t& dl, int& idx, int& sl) {
   }
 }
 
-__device__ bool flow_claim(const FlowRun* __restrict__ runs, int n_runs, FlowCtl* ctl, int xcd, Claim* out) {
+__device__ __forceinline__ bool flow_claim(const FlowRun* __restrict__ runs, int n_runs, FlowCtl* ctl, int xcd,
+                                           Claim* out) {
   const int lane = threadIdx.x & 63;
   uint64_t best_dl = ~0ull;
   int found = -1, fslice = -1;
