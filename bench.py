@@ -236,7 +236,8 @@ def surrogate_compare(args):
         print(f"[bench] seed {seed} plain: {res['plain']}", file=sys.stderr, flush=True)
         for mode in ("mlp", "random"):
             cfg = Config(**b, surrogate=mode, prescreen_frac=0.25, audit=256, surrogate_hidden=256,
-                         surrogate_buffer=50000, surrogate_batch=2048, surrogate_steps=16,
+                         surrogate_buffer=50000, surrogate_batch=args.surrogate_batch,
+                         surrogate_steps=args.surrogate_steps,
                          mse_threshold=target,
                          max_generations=4 * args.generations)
             r, el, log = timed_run(cfg)
@@ -390,6 +391,8 @@ def main():
                          "all 8192 offspring, generations and time to the plain run's final MSE")
     ap.add_argument("--generations", type=int, default=100)
     ap.add_argument("--seeds", type=int, default=1, help="surrogate form: GA seeds to compare over")
+    ap.add_argument("--surrogate-steps", type=int, default=16, help="surrogate form: Adam steps per generation")
+    ap.add_argument("--surrogate-batch", type=int, default=2048, help="surrogate form: minibatch rows per step")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
