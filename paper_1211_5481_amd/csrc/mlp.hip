@@ -24,6 +24,9 @@
 // vectors: the layers store activations row-major and also transposed (batch
 // rows contiguous) for the parameter-gradient products, which contract over
 // rows; W2 is kept transposed as well (W2T, H1 x H2) for the product dA2 W2.
+// Where every row holds whole 16-byte groups (activation rows are padded;
+// weight rows when the widths are multiples of 4) the groups are read
+// without branches, four groups per wave at once (tile_product_v).
 // A workgroup's waves (4; 16 for the gradient products, which contract over
 // all B rows) take interleaved 16-wide slices of the contraction and add
 // their 32 x 32 partial tiles in wave order, so every result has a fixed
@@ -46,6 +49,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;  // four waves
 constexpr int kT = 32;         // tile edge
+constexpr int kMaxHidden = 1024;  // widest hidden layer a context accepts
 
 __device__ __forceinline__ float gelu(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float a) {
@@ -131,6 +135,20 @@ __device__ __forceinline__ v4f load4(const float* row, int k, int K, bool vec) {
 
 __device__ __forceinline__ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+// The same four k read without a branch, in two parts: raw4 loads 16 bytes
+// from a row with at least K rounded up to 4 readable floats (16-byte
+// aligned; k clamped into the row, so any k is in bounds), and mask4 keeps
+// the elements below K of a row that exists (ok) and zeroes the rest.
+__device__ __forceinline__ v4f raw4(const float* row, int k, int K) {
+  return *reinterpret_cast<const v4f*>(row + min(k, ((K + 3) & ~3) - 4));
+}
+__device__ __forceinline__ v4f mask4(v4f v, bool ok, int k, int K) {
+  v4f r;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) r[s] = (ok && k + s < K) ? v[s] : 0.0f;
+  return r;
+}
+
 // C (32 x 32) = sum_{k < K} A(m, k) B(n, k) with NW waves.  Wave w takes the
 // 16-wide k groups w, w + NW, ...; in a group, lane (i, q) supplies rows i and
 // 16 + i of both operands at k = 4q .. 4q + 3 (fa / fb return those four
@@ -173,6 +191,62 @@ __device__ __forceinline__ void tile_product(int K, FA fa, FB fb, v4f* red) {
       acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(c1[s], d0[s], acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(c1[s], d1[s], acc[1][1], 0, 0, 0);
     }
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) red[(wave * 4 + bi * 2 + bj) * 64 + lane] = acc[bi][bj];
+  __syncthreads();
+}
+
+// tile_product with branch-free operand reads: la / lb return a group's raw
+// 16 bytes (any k in bounds), ma / mb turn them into the operand where the
+// group is used (masking, and any per-element work).  Each wave issues the
+// loads of kDepth of its groups at once, then runs their MFMAs in the same
+// order as tile_product.  A group past K is all zeros and its products are
+// added too (a branch around them would let the compiler sink each group's
+// loads to their use, one memory latency per group again), so a sum that
+// is exactly -0 in tile_product can come out +0 here; otherwise the result
+// is the same, bit for bit.  A load under a branch, or its value masked as
+// soon as it arrives, makes the compiler wait for it there; here one memory
+// latency is paid per kDepth groups.
+template <int NW, int kDepth, class LA, class MA, class LB, class MB>
+__device__ __forceinline__ void tile_product_v(int K, LA la, MA ma, LB lb, MB mb, v4f* red) {
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int i = lane & 15, q = lane >> 4;
+  v4f acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = wave * 16; k0 < K; k0 += kDepth * 16 * NW) {
+    v4f ra[kDepth][2], rb[kDepth][2];
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+      const int k = k0 + d * 16 * NW + 4 * q;
+      ra[d][0] = la(i, k);
+      ra[d][1] = la(16 + i, k);
+      rb[d][0] = lb(i, k);
+      rb[d][1] = lb(16 + i, k);
+    }
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+      const int k = k0 + d * 16 * NW + 4 * q;
+      const v4f c0 = ma(i, k, ra[d][0]), c1 = ma(16 + i, k, ra[d][1]);
+      const v4f d0 = mb(i, k, rb[d][0]), d1 = mb(16 + i, k, rb[d][1]);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(c0[s], d0[s], acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(c0[s], d1[s], acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(c1[s], d0[s], acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(c1[s], d1[s], acc[1][1], 0, 0, 0);
+      }
+    }
+    // the chunk's order: every group's loads ahead of the products (left
+    // alone, the scheduler reuses one group's registers and so waits for
+    // each group in turn)
+    __builtin_amdgcn_sched_group_barrier(0x0020, 4 * kDepth, 0);   // vector memory reads
+    __builtin_amdgcn_sched_group_barrier(0x0008, 16 * kDepth, 0);  // MFMAs
   }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -232,7 +306,7 @@ __host__ __device__ __forceinline__ Offs offs(int L, int H1, int H2) {
 
 // Layer 1: tile (row tile blockIdx.y, unit tile blockIdx.x).  The first unit
 // tile also stores the rows' transposed inputs, targets and ones.
-template <bool kTrain>
+template <bool kTrain, bool kV>
 __global__ __launch_bounds__(kThreads) void layer1_kernel(Args a, const DevState* halt) {
   if (run_halted(halt)) return;
   __shared__ v4f red[16 * 64];
@@ -269,23 +343,33 @@ __global__ __launch_bounds__(kThreads) void layer1_kernel(Args a, const DevState
   }
   __syncthreads();
   const float* src = a.X ? a.X : a.buf;
-  const bool vx = (L & 3) == 0 && aligned16(src);
-  auto fa = [&](int m, int k) {
-    const int slot = s_slot[m];
-    const v4f v = load4(slot >= 0 ? src + (int64_t)slot * L : nullptr, k, L, vx);
-    if (lead && slot >= 0) {
+  auto xt = [&](int m, int k, v4f v) {  // the first unit tile keeps the inputs transposed
+    if (lead && s_slot[m] >= 0) {
 #pragma unroll
       for (int s = 0; s < 4; ++s)
         if (k + s < L) S.XT[(int64_t)(k + s) * S.B4 + r0 + m] = v[s];
     }
     return v;
   };
-  const bool vw = (L & 3) == 0;  // W1 starts the parameter array
-  auto fb = [&](int n, int k) {
-    const int h = c0 + n;
-    return load4(h < a.H1 ? a.P + (int64_t)h * L : nullptr, k, L, vw);
-  };
-  tile_product<4>(L, fa, fb, red);
+  if constexpr (kV) {  // rows of L floats, L a multiple of 4, 16-byte aligned
+    auto la = [&](int m, int k) { return raw4(src + (int64_t)max(s_slot[m], 0) * L, k, L); };
+    auto ma = [&](int m, int k, v4f v) { return xt(m, k, mask4(v, s_slot[m] >= 0, k, L)); };
+    auto lb = [&](int n, int k) { return raw4(a.P + (int64_t)(c0 + n < a.H1 ? c0 + n : 0) * L, k, L); };
+    auto mb = [&](int n, int k, v4f v) { return mask4(v, c0 + n < a.H1, k, L); };
+    tile_product_v<4, 2>(L, la, ma, lb, mb, red);
+  } else {
+    const bool vx = (L & 3) == 0 && aligned16(src);
+    auto fa = [&](int m, int k) {
+      const int slot = s_slot[m];
+      return xt(m, k, load4(slot >= 0 ? src + (int64_t)slot * L : nullptr, k, L, vx));
+    };
+    const bool vw = (L & 3) == 0;  // W1 starts the parameter array
+    auto fb = [&](int n, int k) {
+      const int h = c0 + n;
+      return load4(h < a.H1 ? a.P + (int64_t)h * L : nullptr, k, L, vw);
+    };
+    tile_product<4>(L, fa, fb, red);
+  }
   const TileOut o = tile_sum<4>(red);
   const int h = c0 + o.n, r = r0 + o.m0;
   if (h < a.H1 && r < S.B4) {
@@ -308,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void layer1_kernel(Args a, const DevState
 
 // Layer 2 and the tile's share of the head: ypart[r][unit tile] = sum over
 // the tile's units j (in order) of gelu(A2[r][j]) w3[j].
-template <bool kTrain>
+template <bool kTrain, bool kV>
 __global__ __launch_bounds__(kThreads) void layer2_kernel(Args a, const DevState* halt) {
   if (run_halted(halt)) return;
   __shared__ v4f red[16 * 64];
@@ -316,17 +400,26 @@ __global__ __launch_bounds__(kThreads) void layer2_kernel(Args a, const DevState
   const Scratch& S = a.s;
   const int c0 = blockIdx.x * kT, r0 = blockIdx.y * kT, tid = threadIdx.x, H1 = a.H1;
   const Offs po = offs(a.L, H1, a.H2);
-  auto fa = [&](int m, int k) {
-    const int r = r0 + m;
-    return load4(r < a.B ? S.Hd1 + (int64_t)r * S.ld1 : nullptr, k, H1, true);
-  };
   const float* W2 = a.P + po.W2;
-  const bool vw = ((po.W2 | H1) & 3) == 0;
-  auto fb = [&](int n, int k) {
-    const int j = c0 + n;
-    return load4(j < a.H2 ? W2 + (int64_t)j * H1 : nullptr, k, H1, vw);
-  };
-  tile_product<4>(H1, fa, fb, red);
+  // rows of Hd1: ld1 >= H1 rounded up to 4 floats
+  auto la = [&](int m, int k) { return raw4(S.Hd1 + (int64_t)(r0 + m < a.B ? r0 + m : 0) * S.ld1, k, H1); };
+  auto ma = [&](int m, int k, v4f v) { return mask4(v, r0 + m < a.B, k, H1); };
+  if constexpr (kV) {  // W2 rows of H1 floats, H1 a multiple of 4
+    auto lb = [&](int n, int k) { return raw4(W2 + (int64_t)(c0 + n < a.H2 ? c0 + n : 0) * H1, k, H1); };
+    auto mb = [&](int n, int k, v4f v) { return mask4(v, c0 + n < a.H2, k, H1); };
+    tile_product_v<4, 4>(H1, la, ma, lb, mb, red);
+  } else {
+    auto fa = [&](int m, int k) {
+      const int r = r0 + m;
+      return load4(r < a.B ? S.Hd1 + (int64_t)r * S.ld1 : nullptr, k, H1, true);
+    };
+    const bool vw = ((po.W2 | H1) & 3) == 0;
+    auto fb = [&](int n, int k) {
+      const int j = c0 + n;
+      return load4(j < a.H2 ? W2 + (int64_t)j * H1 : nullptr, k, H1, vw);
+    };
+    tile_product<4>(H1, fa, fb, red);
+  }
   const TileOut o = tile_sum<4>(red);
   const int j = c0 + o.n, r = r0 + o.m0;
   const bool jok = j < a.H2;
@@ -352,9 +445,20 @@ __global__ __launch_bounds__(kThreads) void layer2_kernel(Args a, const DevState
 // y = sum of the head shares in tile order + b3.
 __device__ __forceinline__ float head_sum(const Args& a, int r) {
   const float* yp = a.s.ypart + (int64_t)r * a.s.nT2;
+  const int n = a.s.nT2;
+  const float b3 = a.P[offs(a.L, a.H1, a.H2).b3];
   float y = 0.0f;
-  for (int t = 0; t < a.s.nT2; ++t) y += yp[t];
-  return y + a.P[offs(a.L, a.H1, a.H2).b3];
+  // eight shares loaded before they are added (a load per addition would be
+  // a memory round trip each)
+  for (int t0 = 0; t0 < n; t0 += 8) {
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = yp[min(t0 + q, n - 1)];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (t0 + q < n) y += v[q];
+  }
+  return y + b3;
 }
 
 __global__ __launch_bounds__(kThreads) void head_kernel(Args a, const DevState* halt) {
@@ -367,10 +471,12 @@ __global__ __launch_bounds__(kThreads) void head_kernel(Args a, const DevState* 
 // tile blockIdx.x) of dA1 = (dA2 W2) gelu'(A1), with dA2 formed as the left
 // operand is read; the first unit tile also stores dA2 (transposed), dy and
 // the squared residuals.
+template <bool kV>
 __global__ __launch_bounds__(kThreads) void back_kernel(Args a, const DevState* halt) {
   if (run_halted(halt)) return;
   __shared__ v4f red[16 * 64];
   __shared__ float s_dy[kT];
+  __shared__ float s_w3[kV ? kMaxHidden : 1];
   const Scratch& S = a.s;
   const int c0 = blockIdx.x * kT, r0 = blockIdx.y * kT, tid = threadIdx.x, H2 = a.H2;
   const bool lead = blockIdx.x == 0;
@@ -387,27 +493,50 @@ __global__ __launch_bounds__(kThreads) void back_kernel(Args a, const DevState* 
     }
     s_dy[tid] = dy;
   }
-  __syncthreads();
   const float* w3 = a.P + offs(a.L, a.H1, H2).w3;
-  auto fa = [&](int m, int k) {
-    const int r = r0 + m;
-    v4f d = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (r >= a.B) return d;
-    const v4f g2 = load4(S.G2 + (int64_t)r * S.ld2, k, H2, true);
+  if constexpr (kV) {
+    // w3 in LDS (read per element where a group is used); G2 rows of ld2 >=
+    // H2 rounded up to 4 floats, W2T rows of H2 floats (a multiple of 4)
+    for (int j = tid; j < H2; j += kThreads) s_w3[j] = w3[j];
+    __syncthreads();
+    auto la = [&](int m, int k) { return raw4(S.G2 + (int64_t)(r0 + m < a.B ? r0 + m : 0) * S.ld2, k, H2); };
+    auto ma = [&](int m, int k, v4f g2) {
+      const int r = r0 + m;
+      v4f d;
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-      if (k + s < H2) {
-        d[s] = s_dy[m] * w3[k + s] * g2[s];
-        if (lead) S.D2T[(int64_t)(k + s) * S.B4 + r] = d[s];
+      for (int s = 0; s < 4; ++s) {
+        const bool in = r < a.B && k + s < H2;
+        const float v = s_dy[m] * s_w3[in ? k + s : 0] * g2[s];
+        d[s] = in ? v : 0.0f;
+        if (lead && in) S.D2T[(int64_t)(k + s) * S.B4 + r] = v;
       }
-    return d;
-  };
-  const bool vw = (H2 & 3) == 0;
-  auto fb = [&](int n, int k) {
-    const int i = c0 + n;
-    return load4(i < a.H1 ? a.W2T + (int64_t)i * H2 : nullptr, k, H2, vw);
-  };
-  tile_product<4>(H2, fa, fb, red);
+      return d;
+    };
+    auto lb = [&](int n, int k) { return raw4(a.W2T + (int64_t)(c0 + n < a.H1 ? c0 + n : 0) * H2, k, H2); };
+    auto mb = [&](int n, int k, v4f v) { return mask4(v, c0 + n < a.H1, k, H2); };
+    tile_product_v<4, 4>(H2, la, ma, lb, mb, red);
+  } else {
+    __syncthreads();
+    auto fa = [&](int m, int k) {
+      const int r = r0 + m;
+      v4f d = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (r >= a.B) return d;
+      const v4f g2 = load4(S.G2 + (int64_t)r * S.ld2, k, H2, true);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (k + s < H2) {
+          d[s] = s_dy[m] * w3[k + s] * g2[s];
+          if (lead) S.D2T[(int64_t)(k + s) * S.B4 + r] = d[s];
+        }
+      return d;
+    };
+    const bool vw = (H2 & 3) == 0;
+    auto fb = [&](int n, int k) {
+      const int i = c0 + n;
+      return load4(i < a.H1 ? a.W2T + (int64_t)i * H2 : nullptr, k, H2, vw);
+    };
+    tile_product<4>(H2, fa, fb, red);
+  }
   const TileOut o = tile_sum<4>(red);
   const int i = c0 + o.n, r = r0 + o.m0;
   if (i < a.H1 && r < S.B4) {
@@ -513,13 +642,20 @@ __global__ __launch_bounds__(64 * kGradWaves) void grads_kernel(GradArgs g, cons
   const int kc = ((g.B + kSplit - 1) / kSplit + 15) & ~15;
   const int k0 = min(split * kc, g.B), k1 = min(g.B, k0 + kc);
   const int m0 = tm * kT, n0 = tn * kT;
-  auto fa = [&](int m, int k) {
-    return load4(have && m0 + m < job.M ? job.A + (int64_t)(m0 + m) * B4 + k0 : nullptr, k, k1 - k0, true);
+  // rows of B4 floats (B rounded up to 4) from k0; a missing row reads the
+  // ones row
+  const int K = k1 - k0;
+  auto la = [&](int m, int k) {
+    const bool ok = have && m0 + m < job.M;
+    return raw4((ok ? job.A + (int64_t)(m0 + m) * B4 : g.s.ones) + k0, k, K);
   };
-  auto fb = [&](int n, int k) {
-    return load4(have && n0 + n < job.N ? job.Bt + (int64_t)(n0 + n) * B4 + k0 : nullptr, k, k1 - k0, true);
+  auto ma = [&](int m, int k, v4f v) { return mask4(v, have && m0 + m < job.M, k, K); };
+  auto lb = [&](int n, int k) {
+    const bool ok = have && n0 + n < job.N;
+    return raw4((ok ? job.Bt + (int64_t)(n0 + n) * B4 : g.s.ones) + k0, k, K);
   };
-  tile_product<kGradWaves>(k1 - k0, fa, fb, red);
+  auto mb = [&](int n, int k, v4f v) { return mask4(v, have && n0 + n < job.N, k, K); };
+  tile_product_v<kGradWaves, 4>(K, la, ma, lb, mb, red);
   const TileOut o = tile_sum<kGradWaves>(red);
   const int64_t tsz = kT * kT;
   float* part = g.s.gpart + ((int64_t)tile * kSplit + split) * tsz;
@@ -649,11 +785,27 @@ dim3 grid_of(int units, int rows) {
   return dim3((unsigned)((units + kT - 1) / kT), (unsigned)((rows + kT - 1) / kT));
 }
 
+// Whether every operand row of the layer products can be read as whole
+// 16-byte groups: widths that are multiples of 4 and 16-byte aligned rows
+// (inputs, parameters, transposed W2).
+bool vec_rows(const Args& a) {
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  return (a.L & 3) == 0 && (a.H1 & 3) == 0 && (a.H2 & 3) == 0 && al(a.X ? a.X : a.buf) && al(a.P) &&
+         al(a.W2T);
+}
+
 // The three training launches before the gradient products.
+template <bool kV>
+void launch_train_rows_v(const Args& a, const DevState* halt, hipStream_t s) {
+  hipLaunchKernelGGL((layer1_kernel<true, kV>), grid_of(a.H1, a.B), dim3(kThreads), 0, s, a, halt);
+  hipLaunchKernelGGL((layer2_kernel<true, kV>), grid_of(a.H2, a.B), dim3(kThreads), 0, s, a, halt);
+  hipLaunchKernelGGL(back_kernel<kV>, grid_of(a.H1, a.B), dim3(kThreads), 0, s, a, halt);
+}
 hipError_t launch_train_rows(const Args& a, const DevState* halt, hipStream_t s) {
-  hipLaunchKernelGGL(layer1_kernel<true>, grid_of(a.H1, a.B), dim3(kThreads), 0, s, a, halt);
-  hipLaunchKernelGGL(layer2_kernel<true>, grid_of(a.H2, a.B), dim3(kThreads), 0, s, a, halt);
-  hipLaunchKernelGGL(back_kernel, grid_of(a.H1, a.B), dim3(kThreads), 0, s, a, halt);
+  if (vec_rows(a))
+    launch_train_rows_v<true>(a, halt, s);
+  else
+    launch_train_rows_v<false>(a, halt, s);
   return hipGetLastError();
 }
 
@@ -728,8 +880,13 @@ hipError_t mlp_forward(const MlpDims& d, const float* params, const float* W2T, 
   Args a = base_args(d, params, W2T, B, scratch, false);
   a.X = X;
   a.y = y;
-  hipLaunchKernelGGL(layer1_kernel<false>, grid_of(d.H1, B), dim3(kThreads), 0, s, a, halt);
-  hipLaunchKernelGGL(layer2_kernel<false>, grid_of(d.H2, B), dim3(kThreads), 0, s, a, halt);
+  if (vec_rows(a)) {
+    hipLaunchKernelGGL((layer1_kernel<false, true>), grid_of(d.H1, B), dim3(kThreads), 0, s, a, halt);
+    hipLaunchKernelGGL((layer2_kernel<false, true>), grid_of(d.H2, B), dim3(kThreads), 0, s, a, halt);
+  } else {
+    hipLaunchKernelGGL((layer1_kernel<false, false>), grid_of(d.H1, B), dim3(kThreads), 0, s, a, halt);
+    hipLaunchKernelGGL((layer2_kernel<false, false>), grid_of(d.H2, B), dim3(kThreads), 0, s, a, halt);
+  }
   hipLaunchKernelGGL(head_kernel, dim3((unsigned)((B + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
                      a, halt);
   return hipGetLastError();
