@@ -397,7 +397,7 @@ def main():
                     help="only run a plain 256 MiB device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(row sharding is described in the design notes); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
