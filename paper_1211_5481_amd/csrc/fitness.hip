@@ -571,11 +571,10 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
     const int units = M_pad / Tr::kPerLane;  // Ld units per gene row
     const int total = TP * units;
     const Ld* src = reinterpret_cast<const Ld*>(tile + (int64_t)pt * TP * M_pad);
-    auto ld = [&](int v) {
-      Ld x{};
-      if (v < total) x = ld_unit<kFlow>(src + v);
-      return x;
-    };
+    // unconditional loads (the index clamped into the tile; st skips the
+    // extra ones): a load under a branch makes the compiler wait for it at
+    // the join, and the batch's loads would go one memory latency at a time
+    auto ld = [&](int v) { return ld_unit<kFlow>(src + min(v, total - 1)); };
     auto st = [&](int v, const Ld& x) {
       if (v < total) {
         // global unit c of gene row r: K-block c / 4, lane group c % 4;
