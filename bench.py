@@ -85,8 +85,14 @@ def workload(name: str, dtype: str):
 
 
 def source_hash() -> str:
-    with open(FITNESS_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """sha256[:16] of the fitness kernel's source: fitness.hip and the
+    headers of the library it includes, in that order."""
+    h = hashlib.sha256()
+    csrc = os.path.dirname(FITNESS_SRC)
+    for name in ("fitness.hip", "breed.hpp", "game_internal.hpp", "select.hpp"):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(per_launch_bytes_hint=None):

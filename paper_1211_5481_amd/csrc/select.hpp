@@ -152,10 +152,15 @@ __device__ void block_topk(const double* __restrict__ fit, int P, int n_top, int
   };
   if (P <= kThreads * kCache) {
     double key[kCache];
+    // unconditional loads (index clamped into fit, keys past P replaced): a
+    // load under a bounds branch is waited for where the paths join, which
+    // would make these one memory round trip each
 #pragma unroll
     for (int q = 0; q < kCache; ++q) {
       const int i = tid + q * kThreads;
-      key[q] = i < P ? rank_key(kAgent ? ld_agent(fit + i) : fit[i]) : -INFINITY;
+      const int ic = i < P ? i : P - 1;
+      const double f = kAgent ? ld_agent(fit + ic) : fit[ic];
+      key[q] = i < P ? rank_key(f) : -INFINITY;
     }
     uint32_t taken = 0u;  // bit q: value q of this thread already chosen
     for (int e = 0; e < n_top; ++e) {
@@ -198,31 +203,41 @@ __device__ inline void track_best(DevState* st, const int* __restrict__ top,
                                   const float* __restrict__ pop, int L, float* __restrict__ best) {
   __shared__ int s_improve, s_b;
   __syncthreads();
+  // thread 0 reads everything the decision needs at once (one memory round
+  // trip after the index; nothing else writes these values meanwhile)
+  double m = 0.0, mc = 0.0, best_mse = 0.0, thr = 0.0;
+  int active = 0, gen = 0, end_gen = 0;
   if (threadIdx.x == 0) {
     const int b = ldc<kAgent>(top);
+    m = ld_agent(mse + b);
+    mc = ld_agent(miscls + b);
+    const int have = ldc<kAgent>(&st->have_best);
+    best_mse = ldc<kAgent>(&st->best_mse);
+    active = ldc<kAgent>(&st->run_active);
+    thr = ldc<kAgent>(&st->mse_threshold);
+    gen = ldc<kAgent>(&st->generation);
+    end_gen = ldc<kAgent>(&st->end_generation);
     s_b = b;
-    s_improve = (!ldc<kAgent>(&st->have_best) || ld_agent(mse + b) < ldc<kAgent>(&st->best_mse)) ? 1 : 0;
+    s_improve = (!have || m < best_mse) ? 1 : 0;
   }
   __syncthreads();
   const int b = s_b;
   if (s_improve)
     for (int l = threadIdx.x; l < L; l += blockDim.x) stc<kAgent>(best + l, ldc<kAgent>(pop + (int64_t)b * L + l));
   if (threadIdx.x == 0) {
-    const double m = ld_agent(mse + b);
     stc<kAgent>(&st->best_index, b);
-    double best_mse = ldc<kAgent>(&st->best_mse);
     if (s_improve) {
       best_mse = m;
       stc<kAgent>(&st->have_best, 1);
       stc<kAgent>(&st->best_mse, m);
       stc<kAgent>(&st->best_fitness, 1.0 - m);
-      stc<kAgent>(&st->best_miscls, ld_agent(miscls + b));
+      stc<kAgent>(&st->best_miscls, mc);
     }
-    if (ldc<kAgent>(&st->run_active)) {
-      if (best_mse <= ldc<kAgent>(&st->mse_threshold)) {
+    if (active) {
+      if (best_mse <= thr) {
         stc<kAgent>(&st->stopped, 1);
         stc<kAgent>(&st->stop_reason, (int32_t)GAME_STOP_THRESHOLD);
-      } else if (ldc<kAgent>(&st->generation) + 1 >= ldc<kAgent>(&st->end_generation)) {
+      } else if (gen + 1 >= end_gen) {
         stc<kAgent>(&st->stopped, 1);
         stc<kAgent>(&st->stop_reason, (int32_t)GAME_STOP_MAX_GEN);
       }
