@@ -222,11 +222,15 @@ __device__ __forceinline__ void breed_work(const BreedArgs& a, int blk, uint32_t
         put_gene<O, B, kA>(a, dst, a.E + (int)c1, l,
                        imm1 ? immigrant_gene(c1, ul, g, a) : mutate_gene(x1, c1, ul, g, a));
     };
-    // two strides of parent genes loaded before the first child gene is stored
+    // two strides of parent genes loaded before the first child gene is
+    // stored, without a branch (the second from a clamped index when it is
+    // past the row, unused): a load under a branch is waited for where the
+    // paths join
     for (int l = lane; l < a.L; l += 128) {
       const bool two = l + 64 < a.L;
+      const int l2 = two ? l + 64 : l;
       const float ga = ldc<kA>(ra + l), gb = ldc<kA>(rb + l);
-      const float ga2 = two ? ldc<kA>(ra + l + 64) : 0.0f, gb2 = two ? ldc<kA>(rb + l + 64) : 0.0f;
+      const float ga2 = ldc<kA>(ra + l2), gb2 = ldc<kA>(rb + l2);
       child_genes(l, ga, gb);
       if (two) child_genes(l + 64, ga2, gb2);
     }
