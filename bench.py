@@ -85,11 +85,13 @@ def workload(name: str, dtype: str):
 
 
 def source_hash() -> str:
-    """sha256[:16] of the fitness kernel's source: fitness.hip and the
-    headers of the library it includes, in that order."""
+    """sha256[:16] of the measured kernel's source: fitness.hip and the
+    headers whose code it uses (the ranking and best tracking of its tail,
+    the shared types), in that order.  breed.hpp, which fitness.hip includes
+    for the batched scheduler only, is left out."""
     h = hashlib.sha256()
     csrc = os.path.dirname(FITNESS_SRC)
-    for name in ("fitness.hip", "breed.hpp", "game_internal.hpp", "select.hpp"):
+    for name in ("fitness.hip", "game_internal.hpp", "select.hpp"):
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
