@@ -584,18 +584,14 @@ __device__ __forceinline__ void lds_item(const typename Tr::T* __restrict__ phi,
         *reinterpret_cast<Ld*>(&lds[slot * kLdWords]) = x;
       }
     };
-    if constexpr (sizeof(Ld) == 8) {
-      for (int v = tid; v < total; v += 256 * 8) {
-        const Ld g0 = ld(v), g1 = ld(v + 256), g2 = ld(v + 512), g3 = ld(v + 768);
-        const Ld g4 = ld(v + 1024), g5 = ld(v + 1280), g6 = ld(v + 1536), g7 = ld(v + 1792);
-        st(v, g0), st(v + 256, g1), st(v + 512, g2), st(v + 768, g3);
-        st(v + 1024, g4), st(v + 1280, g5), st(v + 1536, g6), st(v + 1792, g7);
-      }
-    } else {
-      for (int v = tid; v < total; v += 256 * 4) {
-        const Ld g0 = ld(v), g1 = ld(v + 256), g2 = ld(v + 512), g3 = ld(v + 768);
-        st(v, g0), st(v + 256, g1), st(v + 512, g2), st(v + 768, g3);
-      }
+    // 128 bytes of loads in flight per thread, all issued before the stores
+    constexpr int kBatch = 128 / (int)sizeof(Ld);
+    for (int v = tid; v < total; v += 256 * kBatch) {
+      Ld g[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) g[q] = ld(v + 256 * q);
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) st(v + 256 * q, g[q]);
     }
   }
   __syncthreads();
