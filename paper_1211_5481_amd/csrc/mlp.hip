@@ -304,8 +304,9 @@ __host__ __device__ __forceinline__ Offs offs(int L, int H1, int H2) {
   return o;
 }
 
-// Layer 1: tile (row tile blockIdx.y, unit tile blockIdx.x).  The first unit
-// tile also stores the rows' transposed inputs, targets and ones.
+// Layer 1: tile (row tile blockIdx.y, unit tile blockIdx.x).  The row
+// tile's unit tiles also store its rows' inputs transposed (a slice of the
+// genes each); the first one stores the targets and ones.
 template <bool kTrain, bool kV>
 __global__ __launch_bounds__(kThreads) void layer1_kernel(Args a, const DevState* halt) {
   if (run_halted(halt)) return;
@@ -343,11 +344,14 @@ __global__ __launch_bounds__(kThreads) void layer1_kernel(Args a, const DevState
   }
   __syncthreads();
   const float* src = a.X ? a.X : a.buf;
-  auto xt = [&](int m, int k, v4f v) {  // the first unit tile keeps the inputs transposed
-    if (lead && s_slot[m] >= 0) {
+  // the row tile's unit tiles keep the inputs transposed, each its own slice
+  // of k (every element stored once, the work shared)
+  const int xs = (L + gridDim.x - 1) / gridDim.x, xk0 = blockIdx.x * xs, xk1 = min(L, xk0 + xs);
+  auto xt = [&](int m, int k, v4f v) {
+    if (kTrain && s_slot[m] >= 0) {
 #pragma unroll
       for (int s = 0; s < 4; ++s)
-        if (k + s < L) S.XT[(int64_t)(k + s) * S.B4 + r0 + m] = v[s];
+        if (k + s >= xk0 && k + s < xk1) S.XT[(int64_t)(k + s) * S.B4 + r0 + m] = v[s];
     }
     return v;
   };
@@ -469,8 +473,8 @@ __global__ __launch_bounds__(kThreads) void head_kernel(Args a, const DevState* 
 
 // Backward through the head and W2: tile (row tile blockIdx.y, layer-1 unit
 // tile blockIdx.x) of dA1 = (dA2 W2) gelu'(A1), with dA2 formed as the left
-// operand is read; the first unit tile also stores dA2 (transposed), dy and
-// the squared residuals.
+// operand is read; the row tile's unit tiles also store dA2 transposed (a
+// slice of the H2 units each), the first one dy and the squared residuals.
 template <bool kV>
 __global__ __launch_bounds__(kThreads) void back_kernel(Args a, const DevState* halt) {
   if (run_halted(halt)) return;
@@ -480,6 +484,9 @@ __global__ __launch_bounds__(kThreads) void back_kernel(Args a, const DevState* 
   const Scratch& S = a.s;
   const int c0 = blockIdx.x * kT, r0 = blockIdx.y * kT, tid = threadIdx.x, H2 = a.H2;
   const bool lead = blockIdx.x == 0;
+  // dA2 is stored transposed by the row tile's unit tiles, each its own
+  // slice of the H2 units (every element once, the work shared)
+  const int ds = (H2 + gridDim.x - 1) / gridDim.x, dk0 = blockIdx.x * ds, dk1 = min(H2, dk0 + ds);
   if (tid < kT) {
     const int r = r0 + tid;
     float dy = 0.0f;
@@ -508,7 +515,7 @@ __global__ __launch_bounds__(kThreads) void back_kernel(Args a, const DevState* 
         const bool in = r < a.B && k + s < H2;
         const float v = s_dy[m] * s_w3[in ? k + s : 0] * g2[s];
         d[s] = in ? v : 0.0f;
-        if (lead && in) S.D2T[(int64_t)(k + s) * S.B4 + r] = v;
+        if (in && k + s >= dk0 && k + s < dk1) S.D2T[(int64_t)(k + s) * S.B4 + r] = v;
       }
       return d;
     };
@@ -526,7 +533,7 @@ __global__ __launch_bounds__(kThreads) void back_kernel(Args a, const DevState* 
       for (int s = 0; s < 4; ++s)
         if (k + s < H2) {
           d[s] = s_dy[m] * w3[k + s] * g2[s];
-          if (lead) S.D2T[(int64_t)(k + s) * S.B4 + r] = d[s];
+          if (k + s >= dk0 && k + s < dk1) S.D2T[(int64_t)(k + s) * S.B4 + r] = d[s];
         }
       return d;
     };
