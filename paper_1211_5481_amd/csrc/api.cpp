@@ -1590,8 +1590,10 @@ game_status batch_tune(game_batch* b) {
     GAME_TRY(batch_time(b, 3, &best));
   } else {
     const size_t budgets[] = {98304, 49152};
-    const double works[] = {1.0 * (1 << 20), 2.0 * (1 << 20), 4.0 * (1 << 20), 8.0 * (1 << 20),
-                            16.0 * (1 << 20)};
+    // the small sizes are for batches of few runs, whose items must still
+    // outnumber the scheduler's workgroups
+    const double works[] = {0.25 * (1 << 20), 0.5 * (1 << 20), 1.0 * (1 << 20), 2.0 * (1 << 20),
+                            4.0 * (1 << 20), 8.0 * (1 << 20), 16.0 * (1 << 20)};
     std::vector<int> btp, brg;
     std::vector<double> bwk;
     for (size_t budget : budgets)
